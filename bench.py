@@ -1,0 +1,203 @@
+"""Benchmark: relaxed-order mixed-precision GMRES solves of the Laplace
+single-layer BEM system on a 32768-triangle unit sphere, against fixed p.
+
+Workload (synthetic, seeded): octahedron sphere refined to 8*4^6 = 32768 flat
+triangles, centroid collocation, 4-point Gauss rule, boundary data
+phi = Y_l^m(c/|c|) for l = 0..4 with m drawn from default_rng(0); FMM with
+N_CRIT = 64, theta = 0.5; GMRES(50) to a relative residual of 1e-6.
+A step is one relaxed solve (p from 12 down to p_min = 3 by the residual,
+FP32 P2P/expansions once eps_k >= 1e-5, FP64 Arnoldi), cycling over the five
+right-hand sides; inputs are resident in device memory before timing starts.
+The line also reports the fixed-p (p = 12, FP64) solve time, the FP64-only
+relaxed solve time, mat-vec rates, the per-stage split, the roofline of the
+dominant kernel and the oracle's CPU rate on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GMRES solve time & FMM matvec/s, relaxed vs fixed p at 1e-6 resid; p50/p99"
+PEAK_FP32_VALU = 157.3e12  # MI355X published FP32 vector peak
+PEAK_FP64_VALU = 78.6e12
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--level", type=int, default=6, help="sphere refinement: 8*4^level panels")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synthetic as syn
+    from paper_1506_05957_amd import fmmbem as fb
+
+    dev = torch.device("cuda:0")
+    mesh = syn.sphere(args.level)
+    nt = mesh.n_panels
+    orders = syn.ylm_orders(0)
+    rhs = [torch.tensor(syn.ylm_rhs(mesh, l, m), device=dev) for l, m in orders]
+    prm = fb.params(theta=0.5, ncrit=64, p_max=12)
+    t0 = time.time()
+    ctx = fb.fmmbem_build(mesh.xyz, mesh.tri, fb.LAPLACE, prm)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    stats = fb.fmmbem_get_stats(ctx)
+    print(f"bench: built {nt} panels in {t_build:.2f}s: {stats}", file=sys.stderr, flush=True)
+
+    tol = 1e-6
+    relaxed = fb.schedule(fb.LAPLACE, rule=fb.RELAX_SHIFT, p_init=12, p_min=3, mixed=1, restart=50)
+    relaxed64 = fb.schedule(fb.LAPLACE, rule=fb.RELAX_SHIFT, p_init=12, p_min=3, mixed=0, restart=50)
+    fixed = fb.schedule(fb.LAPLACE, rule=fb.FIXED, p_init=12, p_min=12, mixed=0, restart=50)
+    x = torch.empty(nt, dtype=torch.float64, device=dev)
+
+    def solve(sched, i):
+        return fb.fmmbem_solve_ctx(ctx, rhs[i % len(rhs)], tol, sched, x)
+
+    for i in range(args.warmup):
+        solve(relaxed, i)
+        solve(fixed, i)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K relaxed mixed-precision solves
+    fb.fmmbem_set_timing(ctx, True)
+    fb.fmmbem_get_timing(ctx, reset=True)
+    times, iters, matvecs = [], [], 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        rep = solve(relaxed, i)
+        times.append(time.perf_counter() - ts)
+        iters.append(rep["iterations"])
+        matvecs += rep["matvecs"]
+        assert rep["converged"], rep
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    stage = fb.fmmbem_get_timing(ctx, reset=True)
+    fb.fmmbem_set_timing(ctx, False)
+    last_p = [int(v) for v in rep["p_hist"]]
+    last_prec = [int(v) for v in rep["prec_hist"]]
+
+    # ---- comparison solves (outside the timed region)
+    def time_solves(sched, k):
+        ts, its = [], []
+        for i in range(k):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = solve(sched, i)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            its.append(r["iterations"])
+        return ts, its
+
+    k_cmp = max(5, min(args.steps, 10))
+    t_fixed, it_fixed = time_solves(fixed, k_cmp)
+    t_rel64, it_rel64 = time_solves(relaxed64, k_cmp)
+
+    # ---- mat-vec rates
+    def matvec_rate(p, prec, reps=50):
+        y = torch.empty_like(x)
+        fb.fmmbem_matvec(ctx, p, prec, rhs[0], y)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fb.fmmbem_matvec(ctx, p, prec, rhs[0], y)
+        torch.cuda.synchronize()
+        return reps / (time.perf_counter() - t)
+
+    mv = {"p12_fp64": matvec_rate(12, fb.FP64), "p12_fp32": matvec_rate(12, fb.FP32),
+          "p6_fp32": matvec_rate(6, fb.FP32), "p3_fp32": matvec_rate(3, fb.FP32)}
+
+    # ---- roofline of the dominant kernel stage in the timed region
+    dom = max(("p2p", "m2l"), key=lambda s: stage[s][0])
+    t_ms, launches, flops = stage[dom]
+    avg_s = t_ms / 1e3 / max(launches, 1)
+    achieved = flops / max(launches, 1) / avg_s
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                "avg_launch_us": avg_s * 1e6, "launches": launches,
+                "flops_per_launch": flops / max(launches, 1),
+                "note": "mixed FP32/FP64 launches; peak is the FP32 vector peak"}
+
+    stage_split = {k: {"ms": v[0], "launches": v[1]} for k, v in stage.items()}
+
+    # ---- CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        rng = np.random.default_rng(0)
+        nrows = 1024
+        rows = np.sort(rng.choice(nt, nrows, replace=False))
+        xv = rhs[0].cpu().numpy()
+        ts = time.perf_counter()
+        oracle.matvec(oracle.LAPLACE, mesh.xyz, mesh.tri, xv, rows=rows)
+        t_rows = time.perf_counter() - ts
+        t_mv = t_rows * nt / nrows
+        n_mv = int(np.mean(it_fixed)) + 1
+        t_solve_cpu = t_mv * n_mv
+        cpu = {"value": 1.0 / t_solve_cpu, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"dense FP64 oracle mat-vec on {nrows} of {nt} rows ({t_rows:.2f}s), scaled to a full "
+                         f"mat-vec ({t_mv:.1f}s) times {n_mv} mat-vecs (fixed-p iterations + true residual)",
+               "matvec_s": t_mv}
+
+    ms = 1e3 * t_total / args.steps
+    out = {
+        "metric": METRIC,
+        "value": args.steps / t_total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "laplace_sl_sphere32768_ylm_relaxed12to3_tol1e-6", "panels": nt,
+                   "rhs": [f"Y_{l}^{m}" for l, m in orders], "ncrit": 64, "theta": 0.5, "restart": 50},
+        "solve_ms": {"relaxed_mixed_p50": 1e3 * pct(times, 50), "relaxed_mixed_p99": 1e3 * pct(times, 99),
+                     "relaxed_fp64_p50": 1e3 * pct(t_rel64, 50), "relaxed_fp64_p99": 1e3 * pct(t_rel64, 99),
+                     "fixed_p12_fp64_p50": 1e3 * pct(t_fixed, 50), "fixed_p12_fp64_p99": 1e3 * pct(t_fixed, 99)},
+        "speedup_relaxed_vs_fixed": pct(t_fixed, 50) / pct(times, 50),
+        "iterations": {"relaxed_mixed": float(np.mean(iters)), "relaxed_fp64": float(np.mean(it_rel64)),
+                       "fixed": float(np.mean(it_fixed))},
+        "matvec_per_s": {"in_relaxed_solves": matvecs / t_total, **mv},
+        "p2p_interactions_per_matvec": stats["p2p_interactions"],
+        "p2p_interactions_per_s_fp32": stats["p2p_interactions"] * mv["p3_fp32"],
+        "p_history_last": last_p, "prec_history_last": last_prec,
+        "stage_ms": stage_split,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "build_s": t_build,
+        "tree": {k: stats[k] for k in ("n_boxes", "n_leaves", "n_levels", "n_m2l", "n_p2p", "nnz_correction")},
+    }
+    print(json.dumps(out))
+    fb.fmmbem_destroy(ctx)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * fmmbem: FMM-accelerated boundary-element solves with relaxed expansion order
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Sec. 2.1-2.3 of Wang, Layton & Barba, "Inexact Krylov
+ * iterations and relaxation strategies with fast-multipole boundary element
+ * method"): a closed surface made of N flat triangles, one unknown (Laplace)
+ * or three (Stokes) per triangle, collocation at the triangle centroids, and
+ * the first-kind single-layer system A x = b with
+ *   Laplace  A_ij = int_{panel j} 1/(4 pi |x_i - y|) dA            (Eq. 3-4)
+ *   Stokes   A_ij = -1/(8 pi mu) int_{panel j} G(x_i, y) dA,
+ *            G_ab = delta_ab / r + r_a r_b / r^3                    (Eq. 6-7, 9)
+ * integrated with 4 Gauss points on far panels (Eq. 10), a 25-point rule on
+ * near-singular panels (closer than 2 sqrt(2 S_j)) and a semi-analytic rule on
+ * the panel holding the target.  The mat-vec is evaluated as an N-body sum over
+ * Gauss points by a fast multipole method with spherical-harmonic expansions of
+ * order p (Eq. 12, 15-16), and GMRES (Sec. 2.4) lowers p as the residual falls
+ * (Sec. 2.6, Eq. 17-19).
+ *
+ * Conventions for every entry point:
+ *  - Return value: an fmmbem_status; FMMBEM_OK is 0, errors are negative.  No
+ *    exception or abort crosses this interface; fmmbem_last_error() gives the
+ *    message of the calling thread's last failure.
+ *  - Ownership: the caller owns every buffer it passes.  fmmbem_build copies
+ *    the mesh; the context owns all device state it creates and releases it in
+ *    fmmbem_destroy.
+ *  - Vector layout: vectors are in the caller's triangle order.  Laplace has
+ *    n = N unknowns; Stokes has n = 3N, stored [N][3] (x, y, z per triangle).
+ *    Arguments named *_dev are device pointers (HIP global memory); *_host are
+ *    host pointers.
+ *  - Streams: a hip_stream argument is a hipStream_t (NULL: the null stream).
+ *    Work is enqueued on it; calls returning host data synchronise it.
+ *  - Threads: a context is not thread-safe; distinct contexts may be used
+ *    concurrently on distinct streams.
+ */
+#ifndef FMMBEM_H
+#define FMMBEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmmbem_ctx fmmbem_ctx_t;       /* one mesh: tree, lists, corrections, workspaces */
+typedef struct fmmbem_server fmmbem_server_t; /* request loop */
+
+typedef enum {
+    FMMBEM_OK = 0,
+    FMMBEM_EINVAL = -1,    /* invalid argument (null pointer, bad size, index, p, tol ...) */
+    FMMBEM_ENOMEM = -2,    /* device or host allocation failed, or budget exceeded */
+    FMMBEM_EDEVICE = -3,   /* a HIP runtime call failed */
+    FMMBEM_ENOCONV = -4,   /* GMRES reached max_iter; x and the report are still filled */
+    FMMBEM_EBUSY = -5,     /* server: request not finished / queue full */
+    FMMBEM_EINTERNAL = -6  /* internal invariant violated */
+} fmmbem_status;
+
+typedef enum { FMMBEM_LAPLACE_SL = 0, FMMBEM_STOKES_SL = 1 } fmmbem_kernel;
+
+/* Arithmetic of the P2P and expansion (P2M ... L2P) kernels.  Inputs, outputs,
+ * the near-field correction and all Krylov arithmetic are FP64 in both cases. */
+typedef enum { FMMBEM_FP64 = 0, FMMBEM_FP32 = 1 } fmmbem_precision;
+
+/* Expansion-order schedule for GMRES (Sec. 2.6).  With rho the relative
+ * residual after the previous iteration (1 before the first) and eta the
+ * solver tolerance, eps_k = min(eta / min(rho, 1), 1) (Eq. 17):
+ *   FIXED        p_k = p_init
+ *   RELAX_SHIFT  p_k = clamp(p_init + ceil(log2(min(rho, 1))), p_min, p_init)
+ *                (Eq. 17 and 19 with the offset that maps eps = eta to p_init)
+ *   RELAX_BF     p_k = clamp(ceil(-log2(eps_k)), p_min, p_init)   (Eq. 19) */
+typedef enum { FMMBEM_FIXED = 0, FMMBEM_RELAX_SHIFT = 1, FMMBEM_RELAX_BF = 2 } fmmbem_rule;
+
+#define FMMBEM_P_MAX 20        /* largest expansion order supported */
+#define FMMBEM_P_MAX_FP32 14   /* largest order for the FP32 expansion kernels */
+
+typedef struct {
+    int64_t n_vertices;
+    int64_t n_triangles;
+    const double *xyz;   /* host, [n_vertices][3] */
+    const int32_t *tri;  /* host, [n_triangles][3], counter-clockwise seen from outside */
+} fmmbem_mesh;
+
+typedef struct {
+    double theta;     /* multipole acceptance criterion (Sec. 2.5), default 0.5 */
+    int32_t ncrit;    /* most panels in a leaf box (Sec. 2.5), default 64, 1..1024 */
+    int32_t p_max;    /* largest p the context will be asked for, 1..FMMBEM_P_MAX, default 16 */
+    double mu;        /* Stokes viscosity, default 1 */
+} fmmbem_params;
+
+typedef struct {
+    int32_t rule;      /* fmmbem_rule */
+    int32_t p_init;    /* order of the first iterations, <= p_max */
+    int32_t p_min;     /* floor of the relaxed order (Sec. 3.2 recommends >= 3-5 for Stokes) */
+    int32_t mixed;     /* 1: FP32 P2P/expansions when eps_k >= fp32_eps and p_k <= FMMBEM_P_MAX_FP32 */
+    double fp32_eps;   /* default 1e-5 */
+    int32_t restart;   /* GMRES(m) restart length, default 50 */
+    int32_t max_iter;  /* total iteration cap, default 500 */
+} fmmbem_schedule;
+
+typedef struct {
+    int32_t iterations, restarts, converged;
+    double rel_res_implicit;   /* |g_{k+1}| / |b| at exit */
+    double rel_res_true;       /* |b - A x| / |b| with A at p_init in FP64 */
+    double t_solve_s;          /* wall time of the solve (host clock, stream synchronised) */
+    int64_t matvecs;
+    /* caller-owned histories, may be NULL; hist_cap entries each */
+    int32_t hist_cap;
+    int32_t *p_hist;
+    uint8_t *prec_hist;
+    double *res_hist;
+} fmmbem_report;
+
+typedef struct {
+    int64_t n_panels, n_unknowns, n_sources;
+    int32_t n_boxes, n_leaves, n_levels, max_leaf;
+    int64_t n_m2l, n_p2p;        /* box pairs */
+    int64_t p2p_interactions;    /* sum over P2P pairs of |targets| * |sources| */
+    int64_t nnz_correction;      /* near-singular + self entries (blocks for Stokes) */
+    int64_t device_bytes;        /* device memory held by the context */
+} fmmbem_stats;
+
+/* Defaults described above. */
+void fmmbem_params_default(fmmbem_params *prm);
+void fmmbem_schedule_default(fmmbem_schedule *s, int kernel);
+
+/* Build the context of one mesh (Sec. 2.3 and 2.5): panel geometry and Gauss
+ * points, Morton octree with at most ncrit panels per leaf, M2L and P2P lists
+ * from a dual traversal with acceptance theta, and the sparse near-singular and
+ * self corrections.  mesh is copied; EINVAL for a null pointer, no triangle, a
+ * vertex index out of range or a zero-area triangle, or params out of range. */
+int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *params,
+                 void *hip_stream, fmmbem_ctx_t **out);
+
+/* One FMM mat-vec y = A x at expansion order p (1..p_max) in the given
+ * precision (the w <- A z of Sec. 2.4, evaluated as in Eq. 12 and Sec. 2.5).
+ * x_dev and y_dev are device vectors of n doubles and must not overlap.
+ * Enqueued on hip_stream; does not synchronise. */
+int fmmbem_matvec(fmmbem_ctx_t *ctx, int32_t p, int32_t precision, const double *x_dev,
+                  double *y_dev, void *hip_stream);
+
+/* GMRES(m) solve of A x = b on an existing context with the order schedule s
+ * (Sec. 2.4, 2.6).  b_dev, x_dev: device vectors of n doubles.  tol > 0 is the
+ * relative residual target.  Returns OK or ENOCONV (x and report filled). */
+int fmmbem_solve_ctx(fmmbem_ctx_t *ctx, const double *b_dev, double tol, const fmmbem_schedule *s,
+                     double *x_dev, fmmbem_report *report, void *hip_stream);
+
+/* One-shot solve: build with default params (mu from params when given),
+ * copy bc (n doubles, host) to the device, solve, copy x back (host). */
+int fmmbem_solve(const fmmbem_mesh *mesh, const double *bc_host, int kernel, double tol,
+                 const fmmbem_schedule *s, const fmmbem_params *params, double *x_host,
+                 fmmbem_report *report);
+
+int fmmbem_get_stats(const fmmbem_ctx_t *ctx, fmmbem_stats *out);
+void fmmbem_destroy(fmmbem_ctx_t *ctx);
+const char *fmmbem_last_error(void);
+
+/* Per-stage device time, accumulated with HIP events recorded on the stream
+ * each kernel is launched on, while timing is enabled.  Stages: 0 P2P,
+ * 1 M2L, 2 P2M+M2M, 3 L2L+L2P, 4 charges + correction + combine.  t_ms[s] is
+ * the total time, launches[s] the number of timed launches and flops[s] the
+ * algorithmic flops of those launches: P2P counts 12 (Laplace) or 30 (Stokes)
+ * per source-target pair, M2L 4 (p+1)^3 (p+2) per box pair and channel; the
+ * other stages count 0.  Any output pointer may be NULL. */
+#define FMMBEM_N_STAGES 5
+int fmmbem_set_timing(fmmbem_ctx_t *ctx, int enabled);
+int fmmbem_get_timing(fmmbem_ctx_t *ctx, double *t_ms, int64_t *launches, double *flops, int reset);
+
+/* Introspection for tests: sizes, then copies of the tree and lists in the
+ * same layout as the CPU reference (sorted order):
+ *   sizes[4] = n_boxes, n_levels, n_m2l, n_p2p
+ *   perm[N] (sorted position -> caller triangle), keys[N] (63-bit Morton),
+ *   boxes[n_boxes][6] = level, begin, end, parent, first child, child count,
+ *   box_real[n_boxes][5] = centre x, y, z, radius, guard,
+ *   m2l[n_m2l][2], p2p[n_p2p][2] = (target box, source box) sorted,
+ *   cube[4] = lower corner x, y, z, side.
+ * Any output pointer may be NULL. */
+int fmmbem_tree_sizes(const fmmbem_ctx_t *ctx, int64_t *sizes);
+int fmmbem_tree_get(const fmmbem_ctx_t *ctx, int32_t *perm, uint64_t *keys, int32_t *boxes,
+                    double *box_real, int32_t *m2l, int32_t *p2p, double *cube);
+
+/* ---- request loop (continuous batching of solves) ---- */
+typedef struct {
+    int64_t hbm_budget_bytes;  /* admission limit on device memory of admitted requests */
+    int32_t max_active;        /* most requests on the device at once */
+    int32_t n_streams;         /* HIP streams the active requests are spread over */
+} fmmbem_server_params;
+
+typedef struct {
+    double arrival_s, admit_s, finish_s;  /* server clock (seconds since create) */
+    int32_t iterations, converged;
+    double rel_res_true;
+    int64_t device_bytes;
+} fmmbem_request_info;
+
+/* Create a server whose worker thread admits queued requests while their
+ * estimated device footprint fits the budget and a slot is free, and advances
+ * every admitted solve by one GMRES iteration per tick. */
+int fmmbem_server_create(const fmmbem_server_params *p, fmmbem_server_t **out);
+/* Queue a solve; mesh and bc are copied.  ticket identifies it. */
+int fmmbem_submit(fmmbem_server_t *srv, const fmmbem_mesh *mesh, const double *bc_host, int kernel,
+                  double tol, const fmmbem_schedule *s, const fmmbem_params *params, uint64_t *ticket);
+/* done = 1 once the request finished (successfully or not). */
+int fmmbem_poll(fmmbem_server_t *srv, uint64_t ticket, int *done);
+/* Block until finished, copy x (n doubles) and the request info; releases the
+ * request.  Returns the request's own status (OK, ENOCONV, ...). */
+int fmmbem_wait(fmmbem_server_t *srv, uint64_t ticket, double *x_host, fmmbem_request_info *info);
+void fmmbem_server_destroy(fmmbem_server_t *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,365 @@
+// C-ABI entry points of libfmmbem (declared in include/fmmbem.h).
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+namespace fmmbem {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string &m) { g_last_error = m; }
+
+void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev)
+{
+    *ev = nullptr;
+    if (!ctx->timing.enabled)
+        return;
+    Timing &T = ctx->timing;
+    if (T.pool.empty()) {
+        hipEvent_t e;
+        FB_HIP(hipEventCreate(&e));
+        T.pool.push_back(e);
+    }
+    *ev = T.pool.back();
+    T.pool.pop_back();
+    FB_HIP(hipEventRecord(*ev, st));
+    (void)stage;
+}
+
+static void resolve_pending(Timing &T)
+{
+    for (auto &pd : T.pending) {
+        FB_HIP(hipEventSynchronize(pd.b));
+        float ms = 0.f;
+        FB_HIP(hipEventElapsedTime(&ms, pd.a, pd.b));
+        T.t_ms[pd.stage] += ms;
+        T.launches[pd.stage] += 1;
+        T.pool.push_back(pd.a);
+        T.pool.push_back(pd.b);
+    }
+    T.pending.clear();
+}
+
+void stage_end(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t ev, double flops)
+{
+    if (!ctx->timing.enabled || !ev)
+        return;
+    Timing &T = ctx->timing;
+    if (T.pool.empty()) {
+        hipEvent_t e;
+        FB_HIP(hipEventCreate(&e));
+        T.pool.push_back(e);
+    }
+    hipEvent_t e2 = T.pool.back();
+    T.pool.pop_back();
+    FB_HIP(hipEventRecord(e2, st));
+    T.pending.push_back({ev, e2, stage});
+    T.flops[stage] += flops;
+    if (T.pending.size() > 4096)
+        resolve_pending(T);
+}
+
+}  // namespace fmmbem
+
+using namespace fmmbem;
+
+#define API_BEGIN try {
+#define API_END                                                                                                      \
+    }                                                                                                                \
+    catch (const fmmbem::Error &e)                                                                                  \
+    {                                                                                                                \
+        set_last_error(e.what());                                                                                    \
+        return e.code;                                                                                               \
+    }                                                                                                                \
+    catch (const std::bad_alloc &)                                                                                   \
+    {                                                                                                                \
+        set_last_error("host allocation failed");                                                                    \
+        return FMMBEM_ENOMEM;                                                                                        \
+    }                                                                                                                \
+    catch (const std::exception &e)                                                                                  \
+    {                                                                                                                \
+        set_last_error(e.what());                                                                                    \
+        return FMMBEM_EINTERNAL;                                                                                     \
+    }                                                                                                                \
+    catch (...)                                                                                                      \
+    {                                                                                                                \
+        set_last_error("unknown error");                                                                             \
+        return FMMBEM_EINTERNAL;                                                                                     \
+    }
+
+extern "C" {
+
+void fmmbem_params_default(fmmbem_params *prm)
+{
+    if (!prm)
+        return;
+    prm->theta = 0.5;
+    prm->ncrit = 64;
+    prm->p_max = 16;
+    prm->mu = 1.0;
+}
+
+void fmmbem_schedule_default(fmmbem_schedule *s, int kernel)
+{
+    if (!s)
+        return;
+    s->rule = FMMBEM_RELAX_BF;
+    s->p_init = kernel == FMMBEM_STOKES_SL ? 16 : 12;
+    s->p_min = kernel == FMMBEM_STOKES_SL ? 4 : 3;
+    s->mixed = 1;
+    s->fp32_eps = 1e-5;
+    s->restart = 50;
+    s->max_iter = 500;
+}
+
+const char *fmmbem_last_error(void) { return g_last_error.c_str(); }
+
+static void validate_mesh(const fmmbem_mesh *mesh)
+{
+    FB_REQUIRE(mesh != nullptr, FMMBEM_EINVAL, "mesh is NULL");
+    FB_REQUIRE(mesh->xyz != nullptr && mesh->tri != nullptr, FMMBEM_EINVAL, "mesh arrays are NULL");
+    FB_REQUIRE(mesh->n_triangles >= 1, FMMBEM_EINVAL, "mesh has no triangle");
+    FB_REQUIRE(mesh->n_vertices >= 3, FMMBEM_EINVAL, "mesh has fewer than 3 vertices");
+    FB_REQUIRE(mesh->n_triangles < (int64_t)1 << 29, FMMBEM_EINVAL, "too many triangles (limit 2^29)");
+    for (int64_t i = 0; i < 3 * mesh->n_triangles; ++i)
+        FB_REQUIRE(mesh->tri[i] >= 0 && mesh->tri[i] < mesh->n_vertices, FMMBEM_EINVAL,
+                   "triangle " + std::to_string(i / 3) + " has a vertex index out of range");
+    for (int64_t i = 0; i < 3 * mesh->n_vertices; ++i)
+        FB_REQUIRE(std::isfinite(mesh->xyz[i]), FMMBEM_EINVAL, "non-finite vertex coordinate");
+}
+
+static void validate_params(const fmmbem_params *p)
+{
+    FB_REQUIRE(p->theta > 0.0 && p->theta < 1.0, FMMBEM_EINVAL, "theta must be in (0, 1)");
+    FB_REQUIRE(p->ncrit >= 1 && p->ncrit <= 1024, FMMBEM_EINVAL, "ncrit must be in [1, 1024]");
+    FB_REQUIRE(p->p_max >= 1 && p->p_max <= FMMBEM_P_MAX, FMMBEM_EINVAL, "p_max must be in [1, 20]");
+    FB_REQUIRE(p->mu > 0.0 && std::isfinite(p->mu), FMMBEM_EINVAL, "mu must be positive");
+}
+
+int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *params, void *hip_stream,
+                 fmmbem_ctx_t **out)
+{
+    API_BEGIN
+    FB_REQUIRE(out != nullptr, FMMBEM_EINVAL, "out is NULL");
+    *out = nullptr;
+    validate_mesh(mesh);
+    FB_REQUIRE(kernel == FMMBEM_LAPLACE_SL || kernel == FMMBEM_STOKES_SL, FMMBEM_EINVAL, "unknown kernel");
+    fmmbem_params prm;
+    fmmbem_params_default(&prm);
+    if (params)
+        prm = *params;
+    validate_params(&prm);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    fmmbem_ctx *ctx = new fmmbem_ctx();
+    try {
+        ctx->kernel = kernel;
+        ctx->prm = prm;
+        FB_HIP(hipGetDevice(&ctx->device));
+        ctx->nt = mesh->n_triangles;
+        ctx->nsrc = 4 * ctx->nt;
+        ctx->n = kernel == FMMBEM_STOKES_SL ? 3 * ctx->nt : ctx->nt;
+        ctx->nch = kernel == FMMBEM_STOKES_SL ? 4 : 1;
+        build_geometry_and_tree(ctx, mesh, st);
+        build_correction(ctx, st);
+        const int ncs = ncoef(prm.p_max);
+        ctx->charges = ctx->arena.alloc<double>((size_t)ctx->nch * ctx->nsrc);
+        ctx->M = ctx->arena.alloc<double>(2 * (size_t)ctx->tree.nbox * ctx->nch * ncs);
+        ctx->L = ctx->arena.alloc<double>(2 * (size_t)ctx->tree.nbox * ctx->nch * ncs);
+        ctx->y_near = ctx->arena.alloc<double>(ctx->n);
+        ctx->y_far = ctx->arena.alloc<double>(ctx->n);
+        FB_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        ctx->arena.release();
+        delete ctx;
+        throw;
+    }
+    *out = ctx;
+    return FMMBEM_OK;
+    API_END
+}
+
+int fmmbem_matvec(fmmbem_ctx_t *ctx, int32_t p, int32_t precision, const double *x_dev, double *y_dev,
+                  void *hip_stream)
+{
+    API_BEGIN
+    FB_REQUIRE(ctx && x_dev && y_dev, FMMBEM_EINVAL, "null argument");
+    FB_REQUIRE(p >= 1 && p <= ctx->prm.p_max, FMMBEM_EINVAL, "p outside [1, p_max]");
+    FB_REQUIRE(precision == FMMBEM_FP64 || precision == FMMBEM_FP32, FMMBEM_EINVAL, "unknown precision");
+    FB_REQUIRE(precision == FMMBEM_FP64 || p <= FMMBEM_P_MAX_FP32, FMMBEM_EINVAL,
+               "FP32 expansions support p <= 14");
+    FB_REQUIRE(x_dev + ctx->n <= y_dev || y_dev + ctx->n <= x_dev, FMMBEM_EINVAL, "x and y overlap");
+    run_matvec(ctx, p, precision, x_dev, y_dev, static_cast<hipStream_t>(hip_stream));
+    return FMMBEM_OK;
+    API_END
+}
+
+static void validate_schedule(const fmmbem_ctx *ctx, const fmmbem_schedule *s, double tol)
+{
+    FB_REQUIRE(s != nullptr, FMMBEM_EINVAL, "schedule is NULL");
+    FB_REQUIRE(tol > 0.0 && std::isfinite(tol), FMMBEM_EINVAL, "tol must be positive");
+    FB_REQUIRE(s->rule >= FMMBEM_FIXED && s->rule <= FMMBEM_RELAX_BF, FMMBEM_EINVAL, "unknown rule");
+    FB_REQUIRE(s->p_init >= 1 && s->p_init <= ctx->prm.p_max, FMMBEM_EINVAL, "p_init outside [1, p_max]");
+    FB_REQUIRE(s->p_min >= 1 && s->p_min <= s->p_init, FMMBEM_EINVAL, "p_min outside [1, p_init]");
+    FB_REQUIRE(s->restart >= 1 && s->restart <= 1000, FMMBEM_EINVAL, "restart outside [1, 1000]");
+    FB_REQUIRE(s->max_iter >= 1, FMMBEM_EINVAL, "max_iter must be >= 1");
+    FB_REQUIRE(s->fp32_eps > 0.0, FMMBEM_EINVAL, "fp32_eps must be positive");
+}
+
+int fmmbem_solve_ctx(fmmbem_ctx_t *ctx, const double *b_dev, double tol, const fmmbem_schedule *s, double *x_dev,
+                     fmmbem_report *report, void *hip_stream)
+{
+    API_BEGIN
+    FB_REQUIRE(ctx && b_dev && x_dev, FMMBEM_EINVAL, "null argument");
+    validate_schedule(ctx, s, tol);
+    return run_solve(ctx, b_dev, tol, s, x_dev, report, static_cast<hipStream_t>(hip_stream));
+    API_END
+}
+
+int fmmbem_solve(const fmmbem_mesh *mesh, const double *bc_host, int kernel, double tol, const fmmbem_schedule *s,
+                 const fmmbem_params *params, double *x_host, fmmbem_report *report)
+{
+    API_BEGIN
+    FB_REQUIRE(bc_host && x_host, FMMBEM_EINVAL, "null argument");
+    fmmbem_params prm;
+    fmmbem_params_default(&prm);
+    if (params)
+        prm = *params;
+    if (s && s->p_init > prm.p_max)
+        prm.p_max = s->p_init;
+    fmmbem_ctx_t *ctx = nullptr;
+    int rc = fmmbem_build(mesh, kernel, &prm, nullptr, &ctx);
+    if (rc != FMMBEM_OK)
+        return rc;
+    double *b = nullptr, *x = nullptr;
+    try {
+        validate_schedule(ctx, s, tol);
+        FB_HIP(hipMalloc(&b, sizeof(double) * ctx->n));
+        FB_HIP(hipMalloc(&x, sizeof(double) * ctx->n));
+        FB_HIP(hipMemcpy(b, bc_host, sizeof(double) * ctx->n, hipMemcpyHostToDevice));
+        rc = run_solve(ctx, b, tol, s, x, report, nullptr);
+        FB_HIP(hipMemcpy(x_host, x, sizeof(double) * ctx->n, hipMemcpyDeviceToHost));
+    } catch (...) {
+        (void)hipDeviceSynchronize();
+        if (b)
+            (void)hipFree(b);
+        if (x)
+            (void)hipFree(x);
+        fmmbem_destroy(ctx);
+        throw;
+    }
+    (void)hipFree(b);
+    (void)hipFree(x);
+    fmmbem_destroy(ctx);
+    return rc;
+    API_END
+}
+
+int fmmbem_get_stats(const fmmbem_ctx_t *ctx, fmmbem_stats *o)
+{
+    API_BEGIN
+    FB_REQUIRE(ctx && o, FMMBEM_EINVAL, "null argument");
+    std::memset(o, 0, sizeof(*o));
+    o->n_panels = ctx->nt;
+    o->n_unknowns = ctx->n;
+    o->n_sources = ctx->nsrc;
+    o->n_boxes = ctx->tree.nbox;
+    o->n_leaves = ctx->tree.nleaf;
+    o->n_levels = ctx->tree.nlevels;
+    o->max_leaf = ctx->tree.max_leaf;
+    o->n_m2l = ctx->tree.n_m2l;
+    o->n_p2p = ctx->tree.n_p2p;
+    o->p2p_interactions = ctx->tree.p2p_interactions;
+    o->nnz_correction = ctx->corr.nnz;
+    o->device_bytes = ctx->arena.bytes + (ctx->kw ? ctx->kw->arena.bytes : 0);
+    return FMMBEM_OK;
+    API_END
+}
+
+void fmmbem_destroy(fmmbem_ctx_t *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipDeviceSynchronize();
+    for (auto &pd : ctx->timing.pending) {
+        (void)hipEventDestroy(pd.a);
+        (void)hipEventDestroy(pd.b);
+    }
+    for (auto e : ctx->timing.pool)
+        (void)hipEventDestroy(e);
+    free_krylov(ctx);
+    ctx->arena.release();
+    delete ctx;
+}
+
+int fmmbem_set_timing(fmmbem_ctx_t *ctx, int enabled)
+{
+    API_BEGIN
+    FB_REQUIRE(ctx, FMMBEM_EINVAL, "null argument");
+    ctx->timing.enabled = enabled != 0;
+    return FMMBEM_OK;
+    API_END
+}
+
+int fmmbem_get_timing(fmmbem_ctx_t *ctx, double *t_ms, int64_t *launches, double *flops, int reset)
+{
+    API_BEGIN
+    FB_REQUIRE(ctx, FMMBEM_EINVAL, "null argument");
+    resolve_pending(ctx->timing);
+    for (int s = 0; s < FMMBEM_N_STAGES; ++s) {
+        if (t_ms)
+            t_ms[s] = ctx->timing.t_ms[s];
+        if (launches)
+            launches[s] = ctx->timing.launches[s];
+        if (flops)
+            flops[s] = ctx->timing.flops[s];
+        if (reset) {
+            ctx->timing.t_ms[s] = 0.0;
+            ctx->timing.launches[s] = 0;
+            ctx->timing.flops[s] = 0.0;
+        }
+    }
+    return FMMBEM_OK;
+    API_END
+}
+
+int fmmbem_tree_sizes(const fmmbem_ctx_t *ctx, int64_t *sizes)
+{
+    API_BEGIN
+    FB_REQUIRE(ctx && sizes, FMMBEM_EINVAL, "null argument");
+    sizes[0] = ctx->tree.nbox;
+    sizes[1] = ctx->tree.nlevels;
+    sizes[2] = ctx->tree.n_m2l;
+    sizes[3] = ctx->tree.n_p2p;
+    return FMMBEM_OK;
+    API_END
+}
+
+int fmmbem_tree_get(const fmmbem_ctx_t *ctx, int32_t *perm, uint64_t *keys, int32_t *boxes, double *box_real,
+                    int32_t *m2l, int32_t *p2p, double *cube)
+{
+    API_BEGIN
+    FB_REQUIRE(ctx, FMMBEM_EINVAL, "null argument");
+    const Tree &T = ctx->tree;
+    FB_HIP(hipDeviceSynchronize());
+    if (perm)
+        FB_HIP(hipMemcpy(perm, T.perm, sizeof(int32_t) * T.nt, hipMemcpyDeviceToHost));
+    if (keys)
+        FB_HIP(hipMemcpy(keys, T.keys, sizeof(uint64_t) * T.nt, hipMemcpyDeviceToHost));
+    if (boxes)
+        std::memcpy(boxes, T.h_box_i.data(), sizeof(int32_t) * T.h_box_i.size());
+    if (box_real)
+        std::memcpy(box_real, T.h_box_r.data(), sizeof(double) * T.h_box_r.size());
+    if (m2l && T.n_m2l)
+        FB_HIP(hipMemcpy(m2l, T.m2l_pairs, sizeof(int32_t) * 2 * T.n_m2l, hipMemcpyDeviceToHost));
+    if (p2p && T.n_p2p)
+        FB_HIP(hipMemcpy(p2p, T.p2p_pairs, sizeof(int32_t) * 2 * T.n_p2p, hipMemcpyDeviceToHost));
+    if (cube)
+        std::memcpy(cube, T.cube, sizeof(double) * 4);
+    return FMMBEM_OK;
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+// Internal declarations shared by the fmmbem HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fmmbem.h"
+
+namespace fmmbem {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define FB_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            throw ::fmmbem::Error(FMMBEM_EDEVICE, std::string(#call) + ": " +                 \
+                                                      hipGetErrorString(e_));                 \
+    } while (0)
+
+#define FB_REQUIRE(cond, code, msg)                                                           \
+    do {                                                                                      \
+        if (!(cond))                                                                          \
+            throw ::fmmbem::Error((code), (msg));                                             \
+    } while (0)
+
+// Number of m >= 0 coefficients of an expansion of order p.
+__host__ __device__ constexpr inline int ncoef(int p) { return (p + 1) * (p + 2) / 2; }
+__host__ __device__ constexpr inline int cidx(int n, int m) { return n * (n + 1) / 2 + m; }
+
+constexpr int P_MAX = FMMBEM_P_MAX;
+constexpr int P_MAX_FP32 = FMMBEM_P_MAX_FP32;
+constexpr int NC_MAX = ncoef(P_MAX);
+
+// Device buffers owned by a context; freed in reverse order on destruction.
+struct DevArena {
+    std::vector<void *> ptrs;
+    int64_t bytes = 0;
+    template <typename T> T *alloc(size_t n) {
+        void *p = nullptr;
+        size_t b = n * sizeof(T);
+        if (b == 0)
+            b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess)
+            throw Error(FMMBEM_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed: " +
+                                           hipGetErrorString(e));
+        ptrs.push_back(p);
+        bytes += (int64_t)b;
+        return static_cast<T *>(p);
+    }
+    void release() {
+        for (auto it = ptrs.rbegin(); it != ptrs.rend(); ++it)
+            (void)hipFree(*it);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+// The octree and lists in sorted (Morton) order, as built on the device.
+struct Tree {
+    int64_t nt = 0;
+    int32_t nbox = 0, nlevels = 0, nleaf = 0, max_leaf = 0;
+    std::vector<int32_t> level_begin;  // boxes of level l are [level_begin[l], level_begin[l+1])
+    double cube[4] = {0, 0, 0, 1};     // lower corner, side
+    // device
+    int32_t *perm = nullptr;      // [nt] sorted -> caller
+    uint64_t *keys = nullptr;     // [nt]
+    int32_t *box_i = nullptr;     // [nbox][6] level, begin, end, parent, child0, nchild
+    double *box_r = nullptr;      // [nbox][5] cx, cy, cz, R, G
+    int32_t *leaves = nullptr;    // [nleaf] box ids of leaves, box order
+    int32_t *panel_leaf = nullptr;// [nt] leaf of each sorted panel
+    int64_t n_m2l = 0, n_p2p = 0;
+    int32_t *m2l_ptr = nullptr, *m2l_src = nullptr;  // CSR over all boxes
+    int32_t *p2p_ptr = nullptr, *p2p_src = nullptr;  // CSR over all boxes (non-leaves empty)
+    int32_t *m2l_pairs = nullptr, *p2p_pairs = nullptr;  // [n][2] sorted (target, source)
+    // host copies of small metadata
+    std::vector<int32_t> h_box_i;
+    std::vector<double> h_box_r;
+    std::vector<int32_t> h_leaves;
+    int64_t p2p_interactions = 0;
+};
+
+struct Geometry {
+    // sorted order, device
+    double *tc = nullptr;    // [3][nt] centroids (SoA)
+    double *S = nullptr;     // [nt] areas
+    double *vtx = nullptr;   // [nt][9] panel vertices v0, v1, v2
+    double *sp = nullptr;    // [4][nsrc] Gauss points x, y, z and weights q_k S_j
+    float *tc32 = nullptr;   // [3][nt] centroid - leaf centre (FP32)
+    float *sp32 = nullptr;   // [4][nsrc] Gauss point - leaf centre, weight (FP32)
+};
+
+struct Correction {
+    int64_t nnz = 0;
+    int32_t *ptr = nullptr;  // [nt + 1] by sorted target
+    int32_t *col = nullptr;  // [nnz] sorted source panel
+    double *val = nullptr;   // [nnz] (Laplace) or [nnz][9] (Stokes), without the kernel prefactor
+};
+
+struct Timing {
+    bool enabled = false;
+    double t_ms[FMMBEM_N_STAGES] = {0};
+    int64_t launches[FMMBEM_N_STAGES] = {0};
+    double flops[FMMBEM_N_STAGES] = {0};
+    // pending event pairs, resolved at the next get or when the pool fills
+    struct Pending { hipEvent_t a, b; int stage; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+};
+
+// GMRES workspace, one per context (krylov.hip)
+struct KrylovWork {
+    int m = 0;
+    int64_t n = 0;
+    int nb = 0;              // row blocks of the dot-product kernels
+    double *V = nullptr;     // [m+1][n]
+    double *w = nullptr;     // [n]
+    double *r = nullptr;     // [n]
+    double *part = nullptr;  // [m+2][nb]
+    double *h = nullptr;     // [2*(m+2)] device: h1 | h2 (second pass) ; h[.. + m+1] = |w|^2
+    double *y = nullptr;     // [m+1]
+    DevArena arena;
+};
+
+
+}  // namespace fmmbem
+
+#include <chrono>
+
+struct fmmbem_ctx {
+    int kernel = FMMBEM_LAPLACE_SL;
+    fmmbem_params prm{};
+    int device = 0;
+    int64_t nt = 0, n = 0, nsrc = 0;
+    int nch = 1;  // expansion channels: 1 Laplace, 4 Stokes
+    fmmbem::DevArena arena;
+    fmmbem::Tree tree;
+    fmmbem::Geometry geo;
+    fmmbem::Correction corr;
+    // per-mat-vec workspace
+    void *charges = nullptr;   // [nch'][nsrc] Real: Laplace q; Stokes f1, f2, f3 (P2P) and f.(y-c) (P2M)
+    void *M = nullptr;         // [nbox][nch][NC(p_max)] complex Real
+    void *L = nullptr;         // same
+    double *y_near = nullptr;  // [n] sorted order (P2P + far field, in kernel units)
+    double *y_far = nullptr;   // [n]
+    fmmbem::Timing timing;
+    fmmbem::KrylovWork *kw = nullptr;
+};
+
+namespace fmmbem {
+
+struct Sched {
+    int p;
+    int prec;
+};
+
+// GMRES(m) as a state machine so that a request loop can interleave solves:
+// start(); while (!done) { enqueue_step(); complete_step(); }
+// enqueue_step only enqueues device work on the solve's stream (mat-vec,
+// CGS2, asynchronous copy of the Hessenberg column to pinned memory);
+// complete_step waits for it and applies the Givens update on the host.
+struct GmresState {
+    fmmbem_ctx *ctx;
+    const double *b;
+    double *x;
+    fmmbem_schedule s;
+    double tol;
+    hipStream_t st;
+    KrylovWork *kw = nullptr;
+    std::vector<double> H, cs, sn, g, yv;
+    double *hbuf = nullptr;  // pinned host
+    int it = 0, restarts = 0, converged = 0, k = 0;
+    int64_t matvecs = 0;
+    double bnorm = 0, beta = 0, rel = 1, true_rel = 1, rho_prev = 1;
+    bool done = false;
+    Sched cur{0, 0};
+    std::vector<int32_t> p_hist;
+    std::vector<uint8_t> prec_hist;
+    std::vector<double> res_hist;
+    std::chrono::steady_clock::time_point t0, t1;
+
+    GmresState(fmmbem_ctx *c, const double *b, double tol, const fmmbem_schedule *s, double *x, hipStream_t st);
+    ~GmresState();
+    GmresState(const GmresState &) = delete;
+    GmresState &operator=(const GmresState &) = delete;
+    void start();
+    void enqueue_step();
+    void complete_step();
+    void fill_report(fmmbem_report *rep) const;
+
+  private:
+    void begin_cycle();
+    void end_cycle();
+    void record(int p, int prec, double r);
+};
+
+void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream_t st);
+void build_correction(fmmbem_ctx *ctx, hipStream_t st);
+void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hipStream_t st);
+int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
+              fmmbem_report *rep, hipStream_t st);
+void free_krylov(fmmbem_ctx *ctx);
+// timing helpers (api.hip)
+void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev);
+void stage_end(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t ev, double flops = 0.0);
+// rules (rules.cpp): Gauss-Legendre by Golub-Welsch, near rule tables
+void gauss_legendre_gw(int n, double *x, double *w);
+void near_rule_table(int n1d, double *bary, double *w);
+void set_last_error(const std::string &m);
+inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+}  // namespace fmmbem
