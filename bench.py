@@ -68,8 +68,8 @@ def main():
     print(f"bench: built {nt} panels in {t_build:.2f}s: {stats}", file=sys.stderr, flush=True)
 
     tol = 1e-6
-    relaxed = fb.schedule(fb.LAPLACE, rule=fb.RELAX_SHIFT, p_init=12, p_min=3, mixed=1, restart=50)
-    relaxed64 = fb.schedule(fb.LAPLACE, rule=fb.RELAX_SHIFT, p_init=12, p_min=3, mixed=0, restart=50)
+    relaxed = fb.schedule(fb.LAPLACE, rule=fb.RELAX_BF, p_init=12, p_min=3, mixed=1, restart=50)
+    relaxed64 = fb.schedule(fb.LAPLACE, rule=fb.RELAX_BF, p_init=12, p_min=3, mixed=0, restart=50)
     fixed = fb.schedule(fb.LAPLACE, rule=fb.FIXED, p_init=12, p_min=12, mixed=0, restart=50)
     x = torch.empty(nt, dtype=torch.float64, device=dev)
 

@@ -23,6 +23,7 @@ SOURCES = [
     ("rules.cpp", []),
     ("tree.hip", ["-ffp-contract=off"]),
     ("near.hip", ["-ffp-contract=off"]),
+    ("translations.hip", []),
     ("fmm.hip", []),
     ("krylov.hip", []),
     ("api.hip", []),

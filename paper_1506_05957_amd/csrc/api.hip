@@ -1,4 +1,5 @@
 // C-ABI entry points of libfmmbem (declared in include/fmmbem.h).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -163,8 +164,10 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         ctx->nch = kernel == FMMBEM_STOKES_SL ? 4 : 1;
         build_geometry_and_tree(ctx, mesh, st);
         build_correction(ctx, st);
+        build_translations(ctx, st);
         const int ncs = ncoef(prm.p_max);
-        ctx->charges = ctx->arena.alloc<double>((size_t)ctx->nch * ctx->nsrc);
+        ctx->charges = ctx->arena.alloc<double>((size_t)(kernel == FMMBEM_STOKES_SL ? 8 : 4) * ctx->nsrc);
+        ctx->Y = ctx->arena.alloc<double>(2 * (size_t)std::max<int64_t>(ctx->tree.n_m2l, 1) * ctx->nch * ncs);
         ctx->M = ctx->arena.alloc<double>(2 * (size_t)ctx->tree.nbox * ctx->nch * ncs);
         ctx->L = ctx->arena.alloc<double>(2 * (size_t)ctx->tree.nbox * ctx->nch * ncs);
         ctx->y_near = ctx->arena.alloc<double>(ctx->n);

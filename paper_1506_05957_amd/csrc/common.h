@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/fmmbem.h"
+#include "harmonics.h"
 
 namespace fmmbem {
 
@@ -116,6 +117,19 @@ struct Timing {
     std::vector<hipEvent_t> pool;
 };
 
+// M2L pairs grouped by translation (translations.hip)
+constexpr int M2L_CHUNK = 64;
+struct M2LPlan {
+    int q = 0;                          // tables hold I_n^m for n <= q = 2 p_max
+    int n_trans = 0, n_chunks = 0;
+    int32_t *pair_sorted = nullptr;     // [n_m2l] pair index (target order), sorted by translation key
+    int32_t *chunk_begin = nullptr;     // [n_chunks + 1] ranges of pair_sorted, one key per chunk
+    int32_t *chunk_trans = nullptr;     // [n_chunks] translation of each chunk
+    uint64_t *trans_key = nullptr;      // [n_trans]
+    cplx<double> *table64 = nullptr;    // [n_trans][(q+1)^2] full irregular tables
+    cplx<float> *table32 = nullptr;
+};
+
 // GMRES workspace, one per context (krylov.hip)
 struct KrylovWork {
     int m = 0;
@@ -146,7 +160,9 @@ struct fmmbem_ctx {
     fmmbem::Geometry geo;
     fmmbem::Correction corr;
     // per-mat-vec workspace
-    void *charges = nullptr;   // [nch'][nsrc] Real: Laplace q; Stokes f1, f2, f3 (P2P) and f.(y-c) (P2M)
+    void *charges = nullptr;   // [nsrc] packed sources (position + charges) of the current mat-vec
+    void *Y = nullptr;         // [n_m2l][nch][NC(p)] per-pair M2L results
+    fmmbem::M2LPlan m2l;
     void *M = nullptr;         // [nbox][nch][NC(p_max)] complex Real
     void *L = nullptr;         // same
     double *y_near = nullptr;  // [n] sorted order (P2P + far field, in kernel units)
@@ -204,6 +220,7 @@ struct GmresState {
 
 void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream_t st);
 void build_correction(fmmbem_ctx *ctx, hipStream_t st);
+void build_translations(fmmbem_ctx *ctx, hipStream_t st);
 void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hipStream_t st);
 int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
               fmmbem_report *rep, hipStream_t st);

@@ -13,6 +13,7 @@
 //
 // Expansions are stored scaled by the box half-size s: M~ = M / s^n and
 // L~ = L s^(n+1), so that FP32 stays in range; all owner-computes, no atomics.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -116,30 +117,45 @@ template <typename R> __device__ inline cplx<R> load_full(const cplx<R> *__restr
 }
 
 // ---------------------------------------------------------------------------
-// charges (a4)
+// charges (a4): packed sources of this mat-vec, position and charge together so
+// that P2P can stream them with one wave-uniform (scalar) load per source.
+// FP64: absolute position; FP32: position relative to the leaf centre.
+template <typename R, bool STOKES> struct Src;
+template <> struct Src<double, false> { double x, y, z, q; };
+template <> struct Src<float, false> { float x, y, z, q; };
+template <> struct Src<double, true> { double x, y, z, f0, f1, f2, pad0, pad1; };
+template <> struct Src<float, true> { float x, y, z, f0, f1, f2, pad0, pad1; };
+
 template <typename R, bool STOKES>
-__global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const int32_t *__restrict__ panel_leaf,
-                          const double *__restrict__ box_r, const double *__restrict__ sp,
-                          const double *__restrict__ x, R *__restrict__ q)
+__global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const double *__restrict__ sp,
+                          const float *__restrict__ sp32, const double *__restrict__ x,
+                          Src<R, STOKES> *__restrict__ src)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ns = 4 * nt;
     if (s >= ns)
         return;
-    int64_t j = s >> 2;
-    int64_t o = perm[j];
-    double w = sp[3 * ns + s];
-    if (!STOKES) {
-        q[s] = (R)(w * x[o]);
+    const int64_t o = perm[s >> 2];
+    const double w = sp[3 * ns + s];
+    Src<R, STOKES> v;
+    if constexpr (sizeof(R) == 8) {
+        v.x = sp[s];
+        v.y = sp[ns + s];
+        v.z = sp[2 * ns + s];
     } else {
-        double t0 = x[3 * o], t1 = x[3 * o + 1], t2 = x[3 * o + 2];
-        const double *c = box_r + 5 * (int64_t)panel_leaf[j];
-        double dy0 = sp[s] - c[0], dy1 = sp[ns + s] - c[1], dy2 = sp[2 * ns + s] - c[2];
-        q[s] = (R)(w * t0);
-        q[ns + s] = (R)(w * t1);
-        q[2 * ns + s] = (R)(w * t2);
-        q[3 * ns + s] = (R)(w * ((t0 * dy0 + t1 * dy1) + t2 * dy2));
+        v.x = sp32[s];
+        v.y = sp32[ns + s];
+        v.z = sp32[2 * ns + s];
     }
+    if constexpr (!STOKES) {
+        v.q = (R)(w * x[o]);
+    } else {
+        v.f0 = (R)(w * x[3 * o]);
+        v.f1 = (R)(w * x[3 * o + 1]);
+        v.f2 = (R)(w * x[3 * o + 2]);
+        v.pad0 = v.pad1 = 0;
+    }
+    src[s] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -147,8 +163,7 @@ __global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const in
 template <typename R, int NCH>
 __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__restrict__ leaves,
                                              const int32_t *__restrict__ box_i, const double *__restrict__ box_r,
-                                             double side, int64_t nt, const double *__restrict__ sp,
-                                             const float *__restrict__ sp32, const R *__restrict__ q,
+                                             double side, const Src<R, NCH == 4> *__restrict__ src,
                                              cplx<R> *__restrict__ M)
 {
     constexpr int SL = 8;
@@ -158,7 +173,6 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
     const double s = ldexp(side, -(lv + 1));
     const double *c = box_r + 5 * (int64_t)b;
     const int m = threadIdx.x & 31, sl = threadIdx.x >> 5;
-    const int64_t ns = 4 * nt;
     const int nc = ncoef(p);
     for (int ch = 0; ch < NCH; ++ch) {
         R are[P_MAX + 1], aim[P_MAX + 1];
@@ -166,20 +180,28 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
         for (int n = 0; n <= P_MAX; ++n)
             are[n] = aim[n] = 0;
         if (m <= p) {
-            for (int64_t src = 4 * (int64_t)pb + sl; src < 4 * (int64_t)pe; src += SL) {
-                R x, y, z;
+            for (int64_t si = 4 * (int64_t)pb + sl; si < 4 * (int64_t)pe; si += SL) {
+                const Src<R, NCH == 4> sv = src[si];
+                R x, y, z;  // relative to the leaf centre
                 if constexpr (sizeof(R) == 8) {
-                    double is = 1.0 / s;
-                    x = (R)((sp[src] - c[0]) * is);
-                    y = (R)((sp[ns + src] - c[1]) * is);
-                    z = (R)((sp[2 * ns + src] - c[2]) * is);
+                    x = sv.x - c[0];
+                    y = sv.y - c[1];
+                    z = sv.z - c[2];
                 } else {
-                    float is = (float)(1.0 / s);
-                    x = sp32[src] * is;
-                    y = sp32[ns + src] * is;
-                    z = sp32[2 * ns + src] * is;
+                    x = sv.x;
+                    y = sv.y;
+                    z = sv.z;
                 }
-                const R qq = q[ch * ns + src];
+                R qq;
+                if constexpr (NCH == 1) {
+                    qq = sv.q;
+                } else {
+                    qq = ch == 0 ? sv.f0 : ch == 1 ? sv.f1 : ch == 2 ? sv.f2 : (sv.f0 * x + sv.f1 * y) + sv.f2 * z;
+                }
+                const R is = (R)(1.0 / s);
+                x *= is;
+                y *= is;
+                z *= is;
                 const R r2 = x * x + y * y + z * z;
                 R dre = 1, dim = 0;
                 for (int k = 1; k <= m; ++k) {
@@ -320,100 +342,133 @@ __global__ __launch_bounds__(64) void k_m2m(int p, int ncs, int box0, const int3
 }
 
 // ---------------------------------------------------------------------------
-// M2L (a7): one block per target box, owner-computes over its M2L list.
-// L_k^l = (-1)^k sum_{n,m} M_n^m I_{n+k}^{m+l}(c_T - c_S), in scaled form with
-// sigma = the larger half-size of the pair.
-template <typename R, int NCH>
-__global__ __launch_bounds__(64) void k_m2l(int p, int ncs, const int32_t *__restrict__ ptr,
-                                            const int32_t *__restrict__ srcs, const int32_t *__restrict__ box_i,
-                                            const double *__restrict__ box_r, double side,
-                                            const cplx<R> *__restrict__ M, cplx<R> *__restrict__ L)
+// M2L (a7), in two passes.
+// Pass 1, one block per chunk of pairs sharing a translation (D, eT, eS): the
+// tabulated I_n^m(D 2^-e) sits in LDS; thread (slot, k, l) computes, for PB
+// pairs at once,
+//   L_k^l = (-1)^k 2^(-eT (k+1)) sum_{n,m} 2^(-eS n) M_n^m I_{n+k}^{m+l}
+// (the scaled form of L = sum M I with sigma the larger half-size), and writes
+// it to Y[pair].  Pass 2 sums Y over each target's pairs in list order.
+template <typename R, int NCH, int PB>
+__global__ __launch_bounds__(256) void k_m2l_group(int p, int ncs, int q_tab, const int32_t *__restrict__ chunk_begin,
+                                                   const int32_t *__restrict__ chunk_trans,
+                                                   const uint64_t *__restrict__ trans_key,
+                                                   const int32_t *__restrict__ pair_sorted,
+                                                   const int32_t *__restrict__ pairs, const double *__restrict__ box_r,
+                                                   const cplx<R> *__restrict__ table, const cplx<R> *__restrict__ M,
+                                                   cplx<R> *__restrict__ Y)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *It = reinterpret_cast<cplx<R> *>(smem_raw);  // (2p+1)^2
     const int q = 2 * p;
-    cplx<R> *Ms = It + (q + 1) * (q + 1);                  // NCH * (p+1)^2
-    const int fp = (p + 1) * (p + 1);
-    const int T = blockIdx.x;
-    const int lvT = box_i[6 * T];
-    const double *cT = box_r + 5 * (int64_t)T;
-    const int nc = ncoef(p);
-    constexpr int NO = (NC_MAX + 63) / 64;
-    R acc_re[NO][NCH], acc_im[NO][NCH];
-#pragma unroll
-    for (int o = 0; o < NO; ++o)
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-            acc_re[o][ch] = acc_im[o][ch] = 0;
-    for (int e = ptr[T]; e < ptr[T + 1]; ++e) {
-        const int S = srcs[e];
-        const int lvS = box_i[6 * S];
-        const int lmin = min(lvS, lvT);
-        const int eS = lvS - lmin, eT = lvT - lmin;
-        const double sigma = ldexp(side, -(lmin + 1));
-        const double *cS = box_r + 5 * (int64_t)S;
-        const double d[3] = {cT[0] - cS[0], cT[1] - cS[1], cT[2] - cS[2]};
+    const int fq = (q + 1) * (q + 1), fp = (p + 1) * (p + 1), nc = ncoef(p);
+    const int nslots = max(1, (int)blockDim.x / nc);
+    cplx<R> *It = reinterpret_cast<cplx<R> *>(smem_raw);
+    cplx<R> *Ms = It + fq;  // [nslots][PB][NCH][fp]
+    const int c = blockIdx.x;
+    const int u = chunk_trans[c], pb = chunk_begin[c], pe = chunk_begin[c + 1];
+    const uint64_t key = trans_key[u];
+    const int eT = (int)((key >> 48) & 63), eS = (int)((key >> 54) & 63);
+    const cplx<R> *tab = table + (int64_t)u * (q_tab + 1) * (q_tab + 1);
+    for (int t = threadIdx.x; t < fq; t += blockDim.x)
+        It[t] = tab[t];
+    const int slot = threadIdx.x / nc, idx = threadIdx.x - slot * nc;
+    const bool active = slot < nslots;
+    int k = 0, l = 0;
+    idx_to_nm(active ? idx : 0, k, l);
+    const R f = (R)ldexp((k & 1) ? -1.0 : 1.0, -eT * (k + 1));
+    const int per_round = nslots * PB;
+    for (int base = pb; base < pe; base += per_round) {
         __syncthreads();
-        if ((int)threadIdx.x <= q)
-            irregular_column_full<R>((R)(d[0] / sigma), (R)(d[1] / sigma), (R)(d[2] / sigma), threadIdx.x, q, It);
-        for (int t = threadIdx.x; t < fp; t += blockDim.x) {
-            int n = 0;
-            while ((n + 1) * (n + 1) <= t)
-                ++n;
-            int m = t - n * n - n;
-            R sc = (R)ldexp(1.0, -eS * n);
-            for (int ch = 0; ch < NCH; ++ch) {
-                cplx<R> v = load_full(M + ((int64_t)S * NCH + ch) * ncs, n, m);
-                Ms[ch * fp + t] = cplx<R>{v.re * sc, v.im * sc};
+        const int nload = per_round * NCH * fp;
+        for (int t = threadIdx.x; t < nload; t += blockDim.x) {
+            const int fi = t % fp;
+            const int ch = (t / fp) % NCH;
+            const int sj = t / (fp * NCH);  // slot * PB + j
+            const int pos = base + sj;
+            cplx<R> v{0, 0};
+            if (pos < pe) {
+                const int S = pairs[2 * pair_sorted[pos] + 1];
+                int n = (int)sqrtf((float)fi);
+                while ((n + 1) * (n + 1) <= fi)
+                    ++n;
+                while (n * n > fi)
+                    --n;
+                const int m = fi - n * n - n;
+                v = load_full(M + ((int64_t)S * NCH + ch) * ncs, n, m);
+                const R sc = (R)ldexp(1.0, -eS * n);
+                v.re *= sc;
+                v.im *= sc;
             }
+            Ms[t] = v;
         }
         __syncthreads();
+        if (!active)
+            continue;
+        R are[PB][NCH], aim[PB][NCH];
 #pragma unroll
-        for (int o = 0; o < NO; ++o) {
-            int idx = threadIdx.x + 64 * o;
-            if (idx >= nc)
-                continue;
-            int k, l;
-            idx_to_nm(idx, k, l);
-            R sre[NCH], sim[NCH];
+        for (int j = 0; j < PB; ++j)
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch)
-                sre[ch] = sim[ch] = 0;
-            for (int n = 0; n <= p; ++n) {
-                const cplx<R> *Irow = It + full_idx(n + k, l);  // + m below
-                const int mb = n * n + n;
-                for (int m = -n; m <= n; ++m) {
-                    cplx<R> iv = Irow[m];
+                are[j][ch] = aim[j][ch] = 0;
+        const cplx<R> *Mslot = Ms + (int64_t)slot * PB * NCH * fp;
+        for (int n = 0; n <= p; ++n) {
+            const cplx<R> *Irow = It + (n + k) * (n + k) + (n + k) + l;  // + m
+            const int mb = n * n + n;
+            for (int m = -n; m <= n; ++m) {
+                const cplx<R> iv = Irow[m];
+#pragma unroll
+                for (int j = 0; j < PB; ++j)
 #pragma unroll
                     for (int ch = 0; ch < NCH; ++ch) {
-                        cplx<R> mv = Ms[ch * fp + mb + m];
-                        sre[ch] += mv.re * iv.re - mv.im * iv.im;
-                        sim[ch] += mv.re * iv.im + mv.im * iv.re;
+                        const cplx<R> mv = Mslot[(j * NCH + ch) * fp + mb + m];
+                        are[j][ch] += mv.re * iv.re - mv.im * iv.im;
+                        aim[j][ch] += mv.re * iv.im + mv.im * iv.re;
                     }
-                }
             }
-            R f = (R)ldexp((k & 1) ? -1.0 : 1.0, -eT * (k + 1));
+        }
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            const int pos = base + slot * PB + j;
+            if (pos >= pe)
+                continue;
+            const int orig = pair_sorted[pos];
+            R o_re[NCH], o_im[NCH];
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                acc_re[o][ch] += f * sre[ch];
-                acc_im[o][ch] += f * sim[ch];
+                o_re[ch] = f * are[j][ch];
+                o_im[ch] = f * aim[j][ch];
             }
             if constexpr (NCH == 4) {
                 // change of centre of Phi_4 from c_S to c_T
+                const double *cT = box_r + 5 * (int64_t)pairs[2 * orig], *cS = box_r + 5 * (int64_t)pairs[2 * orig + 1];
                 const R g0 = (R)(cS[0] - cT[0]), g1 = (R)(cS[1] - cT[1]), g2 = (R)(cS[2] - cT[2]);
-                acc_re[o][3] += f * (g0 * sre[0] + g1 * sre[1] + g2 * sre[2]);
-                acc_im[o][3] += f * (g0 * sim[0] + g1 * sim[1] + g2 * sim[2]);
+                o_re[3] += g0 * o_re[0] + g1 * o_re[1] + g2 * o_re[2];
+                o_im[3] += g0 * o_im[0] + g1 * o_im[1] + g2 * o_im[2];
             }
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                Y[((int64_t)orig * NCH + ch) * nc + idx] = cplx<R>{o_re[ch], o_im[ch]};
         }
     }
-#pragma unroll
-    for (int o = 0; o < NO; ++o) {
-        int idx = threadIdx.x + 64 * o;
-        if (idx >= nc)
-            continue;
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-            L[((int64_t)T * NCH + ch) * ncs + idx] = cplx<R>{acc_re[o][ch], acc_im[o][ch]};
+}
+
+// Pass 2: L(T) = sum of Y over T's pairs (CSR order), all boxes.
+template <typename R, int NCH>
+__global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_t *__restrict__ ptr,
+                                                    const cplx<R> *__restrict__ Y, cplx<R> *__restrict__ L)
+{
+    const int T = blockIdx.x;
+    const int nc = ncoef(p);
+    const int e0 = ptr[T], e1 = ptr[T + 1];
+    for (int t = threadIdx.x; t < NCH * nc; t += blockDim.x) {
+        R sr = 0, si = 0;
+        for (int e = e0; e < e1; ++e) {
+            const cplx<R> v = Y[(int64_t)e * NCH * nc + t];
+            sr += v.re;
+            si += v.im;
+        }
+        const int ch = t / nc, idx = t - ch * nc;
+        L[((int64_t)T * NCH + ch) * ncs + idx] = cplx<R>{sr, si};
     }
 }
 
@@ -594,24 +649,25 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
 }
 
 // ---------------------------------------------------------------------------
-// P2P (a10): one block per target leaf, 4 waves splitting the source leaves,
-// sources staged in LDS, fixed-order reduction of the 4 partial sums.
+// P2P (a10): one block per target leaf, one target per lane, the 4 waves of the
+// block splitting the leaf's source leaves.  Source indices are wave-uniform,
+// so each packed source is fetched once per wave through the scalar cache and
+// feeds 64 targets; the 4 partial sums are reduced in a fixed order.
+// FP32 works in leaf-relative coordinates: r = (t - c_T) + (c_T - c_S) - (y - c_S).
 template <typename R, bool STOKES>
 __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaves, const int32_t *__restrict__ box_i,
                                              const int32_t *__restrict__ ptr, const int32_t *__restrict__ srcs,
                                              const double *__restrict__ box_r, int64_t nt,
                                              const double *__restrict__ tc, const float *__restrict__ tc32,
-                                             const double *__restrict__ sp, const float *__restrict__ sp32,
-                                             const R *__restrict__ q, double *__restrict__ ynear)
+                                             const Src<R, STOKES> *__restrict__ src, double *__restrict__ ynear)
 {
     constexpr int NQ = STOKES ? 3 : 1;
-    constexpr int TILE = 256;
-    __shared__ R sx[4][TILE], sy[4][TILE], sz[4][TILE], sq[4][NQ][TILE];
     __shared__ R red[4][NQ][64];
     const int b = leaves[blockIdx.x];
     const int tb = box_i[6 * b + 1], te = box_i[6 * b + 2];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t ns = 4 * nt;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int e0 = ptr[b], e1 = ptr[b + 1];
     const double *cT = box_r + 5 * (int64_t)b;
     for (int t0 = tb; t0 < te; t0 += 64) {
         const int i = t0 + lane;
@@ -632,62 +688,37 @@ __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaves,
 #pragma unroll
         for (int a = 0; a < NQ; ++a)
             acc[a] = 0;
-        for (int e = ptr[b] + w; e < ptr[b + 1]; e += 4) {
+        for (int e = e0 + w; e < e1; e += 4) {
             const int sb = srcs[e];
-            const int s0 = 4 * box_i[6 * sb + 1], s1 = 4 * box_i[6 * sb + 2];
-            R ox = 0, oy = 0, oz = 0;  // target offset into the source frame (FP32)
+            const int k0 = 4 * box_i[6 * sb + 1], k1 = 4 * box_i[6 * sb + 2];
+            R px = tx, py = ty, pz = tz;
             if constexpr (sizeof(R) == 4) {
                 const double *cS = box_r + 5 * (int64_t)sb;
-                ox = (float)(cT[0] - cS[0]);
-                oy = (float)(cT[1] - cS[1]);
-                oz = (float)(cT[2] - cS[2]);
+                px += (float)(cT[0] - cS[0]);
+                py += (float)(cT[1] - cS[1]);
+                pz += (float)(cT[2] - cS[2]);
             }
-            const R px = tx + ox, py = ty + oy, pz = tz + oz;
-            for (int c0 = s0; c0 < s1; c0 += TILE) {
-                const int cn = min(TILE, s1 - c0);
-                __builtin_amdgcn_wave_barrier();
-                for (int k = lane; k < cn; k += 64) {
-                    const int64_t sidx = c0 + k;
-                    if constexpr (sizeof(R) == 8) {
-                        sx[w][k] = sp[sidx];
-                        sy[w][k] = sp[ns + sidx];
-                        sz[w][k] = sp[2 * ns + sidx];
-                    } else {
-                        sx[w][k] = sp32[sidx];
-                        sy[w][k] = sp32[ns + sidx];
-                        sz[w][k] = sp32[2 * ns + sidx];
-                    }
-#pragma unroll
-                    for (int a = 0; a < NQ; ++a)
-                        sq[w][a][k] = q[a * ns + sidx];
+            const bool self = sb == b;
+#pragma unroll 4
+            for (int k = k0; k < k1; ++k) {
+                const Src<R, STOKES> sv = src[k];
+                const R dx = px - sv.x, dy = py - sv.y, dz = pz - sv.z;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                R rinv;
+                if constexpr (sizeof(R) == 8)
+                    rinv = rsqrt(r2);
+                else
+                    rinv = __builtin_amdgcn_rsqf(r2);
+                if (self && (k >> 2) == i)
+                    rinv = 0;  // the target's own panel: integrated by the correction
+                if constexpr (!STOKES) {
+                    acc[0] += sv.q * rinv;
+                } else {
+                    const R dot = (dx * sv.f0 + dy * sv.f1 + dz * sv.f2) * (rinv * rinv * rinv);
+                    acc[0] += sv.f0 * rinv + dx * dot;
+                    acc[1] += sv.f1 * rinv + dy * dot;
+                    acc[2] += sv.f2 * rinv + dz * dot;
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (active) {
-                    const bool self = sb == b;
-                    for (int k = 0; k < cn; ++k) {
-                        if (self && ((c0 + k) >> 2) == i)
-                            continue;
-                        const R dx = px - sx[w][k], dy = py - sy[w][k], dz = pz - sz[w][k];
-                        const R r2 = dx * dx + dy * dy + dz * dz;
-                        R rinv;
-                        if constexpr (sizeof(R) == 8)
-                            rinv = rsqrt(r2);
-                        else
-                            rinv = __builtin_amdgcn_rsqf(r2);
-                        if constexpr (!STOKES) {
-                            acc[0] += sq[w][0][k] * rinv;
-                        } else {
-                            const R f0 = sq[w][0][k], f1 = sq[w][1][k], f2 = sq[w][2][k];
-                            const R dot = (dx * f0 + dy * f1 + dz * f2) * (rinv * rinv * rinv);
-                            acc[0] += f0 * rinv + dx * dot;
-                            acc[1] += f1 * rinv + dy * dot;
-                            acc[2] += f2 * rinv + dz * dot;
-                        }
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
             }
         }
 #pragma unroll
@@ -749,19 +780,19 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
     const int64_t nt = ctx->nt, ns = ctx->nsrc;
     const int ncs = ncoef(ctx->prm.p_max);
     const double side = T.cube[3];
-    R *q = static_cast<R *>(ctx->charges);
+    Src<R, STOKES> *src = static_cast<Src<R, STOKES> *>(ctx->charges);
     cplx<R> *M = static_cast<cplx<R> *>(ctx->M);
     cplx<R> *L = static_cast<cplx<R> *>(ctx->L);
     hipEvent_t ev;
 
     stage_begin(ctx, 4, st, &ev);
-    k_charges<R, STOKES><<<grid_for(ns, 256), 256, 0, st>>>(nt, T.perm, T.panel_leaf, T.box_r, G.sp, x, q);
+    k_charges<R, STOKES><<<grid_for(ns, 256), 256, 0, st>>>(nt, T.perm, G.sp, G.sp32, x, src);
     FB_HIP(hipGetLastError());
     stage_end(ctx, 4, st, ev);
 
     if (T.n_m2l > 0) {
         stage_begin(ctx, 2, st, &ev);
-        k_p2m<R, NCH><<<T.nleaf, 256, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.sp, G.sp32, q, M);
+        k_p2m<R, NCH><<<T.nleaf, 256, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
         FB_HIP(hipGetLastError());
         for (int l = T.nlevels - 2; l >= 0; --l) {
             int b0 = T.level_begin[l], nb = T.level_begin[l + 1] - b0;
@@ -771,9 +802,27 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
         stage_end(ctx, 2, st, ev);
 
         stage_begin(ctx, 1, st, &ev);
-        size_t shm = sizeof(cplx<R>) * ((size_t)(2 * p + 1) * (2 * p + 1) + (size_t)NCH * (p + 1) * (p + 1));
-        k_m2l<R, NCH><<<T.nbox, 64, shm, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_i, T.box_r, side, M, L);
-        FB_HIP(hipGetLastError());
+        {
+            constexpr int PB = NCH == 1 ? 4 : 1;
+            const M2LPlan &P = ctx->m2l;
+            const int nc = ncoef(p);
+            const int threads = nc > 128 ? 64 * ((nc + 63) / 64) : 256;
+            const int nslots = std::max(1, threads / nc);
+            const size_t shm = sizeof(cplx<R>) * ((size_t)(2 * p + 1) * (2 * p + 1) +
+                                                  (size_t)nslots * PB * NCH * (p + 1) * (p + 1));
+            const cplx<R> *table;
+            if constexpr (sizeof(R) == 8)
+                table = P.table64;
+            else
+                table = P.table32;
+            cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
+            k_m2l_group<R, NCH, PB><<<P.n_chunks, threads, shm, st>>>(p, ncs, P.q, P.chunk_begin, P.chunk_trans,
+                                                                      P.trans_key, P.pair_sorted, T.m2l_pairs,
+                                                                      T.box_r, table, M, Y);
+            FB_HIP(hipGetLastError());
+            k_m2l_reduce<R, NCH><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, Y, L);
+            FB_HIP(hipGetLastError());
+        }
         stage_end(ctx, 1, st, ev, 4.0 * (p + 1) * (p + 1) * (p + 1) * (p + 2) * NCH * (double)T.n_m2l);
 
         stage_begin(ctx, 3, st, &ev);
@@ -792,7 +841,7 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
 
     stage_begin(ctx, 0, st, &ev);
     k_p2p<R, STOKES><<<T.nleaf, 256, 0, st>>>(T.leaves, T.box_i, T.p2p_ptr, T.p2p_src, T.box_r, nt, G.tc, G.tc32,
-                                              G.sp, G.sp32, q, ctx->y_near);
+                                              src, ctx->y_near);
     FB_HIP(hipGetLastError());
     // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
     stage_end(ctx, 0, st, ev, (STOKES ? 30.0 : 12.0) * (double)(T.p2p_interactions - 4 * nt));

@@ -1,0 +1,183 @@
+// Translation tables for M2L (Sec. 2.5), built once per mesh.
+//
+// Box centres lie on a grid: a box of level l with integer cell i has centre
+// lo + (i + 1/2) side 2^-l.  For an M2L pair (T, S), let l0 be the coarser of
+// the two levels, sigma = side 2^-(l0+1) its half-size, eT = lT - l0 and
+// eS = lS - l0.  Then (c_T - c_S) / sigma = D 2^-e, e = max(eT, eS), with the
+// integer vector D = (2 iT + 1) 2^(e - eT) - (2 iS + 1) 2^(e - eS).  Pairs with
+// equal (D, eT, eS) share one scaled M2L operator, so the irregular harmonics
+// I_n^m(D 2^-e), n <= 2 p_max, are tabulated once per distinct key (FP64 and
+// FP32), and the M2L kernel processes the pairs of one key together.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "harmonics.h"
+
+namespace fmmbem {
+
+namespace {
+
+__device__ __host__ inline uint32_t gather3(uint64_t x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+
+constexpr int KEY_BIAS = 1 << 15;
+
+// key = (Dx + 2^15) | (Dy + 2^15) << 16 | (Dz + 2^15) << 32 | eT << 48 | eS << 54
+__global__ void k_translation_keys(int64_t n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ box_i,
+                                   const uint64_t *__restrict__ keys, uint64_t *__restrict__ tkey,
+                                   int32_t *__restrict__ idx, int *__restrict__ overflow)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int T = pairs[2 * i], S = pairs[2 * i + 1];
+    const int lT = box_i[6 * T], lS = box_i[6 * S];
+    const uint64_t pT = keys[box_i[6 * T + 1]] >> (3 * (21 - lT));
+    const uint64_t pS = keys[box_i[6 * S + 1]] >> (3 * (21 - lS));
+    const int l0 = min(lT, lS), eT = lT - l0, eS = lS - l0, e = max(eT, eS);
+    const int64_t cT[3] = {gather3(pT >> 2), gather3(pT >> 1), gather3(pT)};
+    const int64_t cS[3] = {gather3(pS >> 2), gather3(pS >> 1), gather3(pS)};
+    uint64_t key = ((uint64_t)eT << 48) | ((uint64_t)eS << 54);
+    bool bad = eT > 63 || eS > 63;
+    for (int d = 0; d < 3; ++d) {
+        int64_t D = (2 * cT[d] + 1) * ((int64_t)1 << (e - eT)) - (2 * cS[d] + 1) * ((int64_t)1 << (e - eS));
+        if (D <= -KEY_BIAS || D >= KEY_BIAS)
+            bad = true;
+        key |= (uint64_t)((D + KEY_BIAS) & 0xffff) << (16 * d);
+    }
+    if (bad)
+        atomicAdd(overflow, 1);
+    tkey[i] = key;
+    idx[i] = (int32_t)i;
+}
+
+__device__ inline int full_index(int n, int m) { return n * n + n + m; }
+
+// One block per distinct translation: thread m computes column m of the
+// irregular table (n = m..q) in FP64 and stores FP64 and FP32 copies.
+__global__ void k_translation_tables(int nu, const uint64_t *__restrict__ ukey, int q, cplx<double> *__restrict__ t64,
+                                     cplx<float> *__restrict__ t32)
+{
+    const int u = blockIdx.x;
+    if (u >= nu)
+        return;
+    const uint64_t key = ukey[u];
+    const int eT = (int)((key >> 48) & 63), eS = (int)((key >> 54) & 63), e = max(eT, eS);
+    double v[3];
+    for (int d = 0; d < 3; ++d)
+        v[d] = ldexp((double)((int64_t)((key >> (16 * d)) & 0xffff) - KEY_BIAS), -e);
+    const int fq = (q + 1) * (q + 1);
+    cplx<double> *T64 = t64 + (int64_t)u * fq;
+    cplx<float> *T32 = t32 + (int64_t)u * fq;
+    for (int m = threadIdx.x; m <= q; m += blockDim.x) {
+        const double x = v[0], y = v[1], z = v[2];
+        const double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
+        double dre = 1.0 / sqrt(r2), dim = 0.0;
+        for (int k = 1; k <= m; ++k) {
+            double f = -(2.0 * k - 1.0) * ir2;
+            double a = f * (x * dre - y * dim), b = f * (x * dim + y * dre);
+            dre = a;
+            dim = b;
+        }
+        double cr = dre, ci = dim, pr = 0.0, pi = 0.0;
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        for (int n = m; n <= q; ++n) {
+            if (n > m) {
+                double a = (2.0 * n - 1.0) * z, b = (double)((n - 1) * (n - 1) - m * m);
+                double nr = (a * cr - b * pr) * ir2, ni = (a * ci - b * pi) * ir2;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+            }
+            T64[full_index(n, m)] = cplx<double>{cr, ci};
+            T32[full_index(n, m)] = cplx<float>{(float)cr, (float)ci};
+            if (m > 0) {
+                T64[full_index(n, -m)] = cplx<double>{sg * cr, -sg * ci};
+                T32[full_index(n, -m)] = cplx<float>{(float)(sg * cr), (float)(-sg * ci)};
+            }
+        }
+    }
+}
+
+}  // namespace
+
+void build_translations(fmmbem_ctx *ctx, hipStream_t st)
+{
+    Tree &T = ctx->tree;
+    M2LPlan &P = ctx->m2l;
+    const int64_t n = T.n_m2l;
+    P.q = 2 * ctx->prm.p_max;
+    if (n == 0)
+        return;
+    DevArena tmp;
+    try {
+        uint64_t *key = tmp.alloc<uint64_t>(n), *key_sorted = tmp.alloc<uint64_t>(n);
+        int32_t *idx = tmp.alloc<int32_t>(n);
+        int *ovf = tmp.alloc<int>(1);
+        FB_HIP(hipMemsetAsync(ovf, 0, sizeof(int), st));
+        P.pair_sorted = ctx->arena.alloc<int32_t>(n);
+        k_translation_keys<<<grid_for(n, 256), 256, 0, st>>>(n, T.m2l_pairs, T.box_i, T.keys, key, idx, ovf);
+        FB_HIP(hipGetLastError());
+        size_t bytes = 0;
+        FB_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, key, key_sorted, idx, P.pair_sorted, (int)n, 0, 60,
+                                                  st));
+        void *t = tmp.alloc<char>(bytes);
+        FB_HIP(hipcub::DeviceRadixSort::SortPairs(t, bytes, key, key_sorted, idx, P.pair_sorted, (int)n, 0, 60, st));
+        std::vector<uint64_t> hk(n);
+        int hovf = 0;
+        FB_HIP(hipMemcpyAsync(hk.data(), key_sorted, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, st));
+        FB_HIP(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
+        FB_HIP(hipStreamSynchronize(st));
+        FB_REQUIRE(hovf == 0, FMMBEM_EINTERNAL, "M2L translation key out of range");
+        // distinct keys and chunks of at most M2L_CHUNK pairs with one key
+        std::vector<uint64_t> ukeys;
+        std::vector<int32_t> cbeg, cu;
+        for (int64_t i = 0; i < n;) {
+            int64_t j = i;
+            while (j < n && hk[j] == hk[i])
+                ++j;
+            int u = (int)ukeys.size();
+            ukeys.push_back(hk[i]);
+            for (int64_t a = i; a < j; a += M2L_CHUNK) {
+                cbeg.push_back((int32_t)a);
+                cu.push_back(u);
+            }
+            i = j;
+        }
+        cbeg.push_back((int32_t)n);
+        P.n_trans = (int)ukeys.size();
+        P.n_chunks = (int)cu.size();
+        P.chunk_begin = ctx->arena.alloc<int32_t>(cbeg.size());
+        P.chunk_trans = ctx->arena.alloc<int32_t>(cu.size());
+        P.trans_key = ctx->arena.alloc<uint64_t>(ukeys.size());
+        FB_HIP(hipMemcpyAsync(P.chunk_begin, cbeg.data(), sizeof(int32_t) * cbeg.size(), hipMemcpyHostToDevice, st));
+        FB_HIP(hipMemcpyAsync(P.chunk_trans, cu.data(), sizeof(int32_t) * cu.size(), hipMemcpyHostToDevice, st));
+        FB_HIP(hipMemcpyAsync(P.trans_key, ukeys.data(), sizeof(uint64_t) * ukeys.size(), hipMemcpyHostToDevice, st));
+        const int64_t fq = (int64_t)(P.q + 1) * (P.q + 1);
+        P.table64 = ctx->arena.alloc<cplx<double>>(fq * P.n_trans);
+        P.table32 = ctx->arena.alloc<cplx<float>>(fq * P.n_trans);
+        k_translation_tables<<<P.n_trans, 64, 0, st>>>(P.n_trans, P.trans_key, P.q, P.table64, P.table32);
+        FB_HIP(hipGetLastError());
+        FB_HIP(hipStreamSynchronize(st));
+        tmp.release();
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        tmp.release();
+        throw;
+    }
+}
+
+}  // namespace fmmbem

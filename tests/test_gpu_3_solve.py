@@ -7,6 +7,13 @@ tol = 1e-8 against the oracle converged to 1e-11, where the stopping error is
 below the bar.  At the bench tolerance 1e-6 the tests check the true residual
 and that relaxation does not move the solution further from the oracle than
 the stopping error itself.
+
+Stokes: the first-kind single layer maps the normal field of each closed
+body to (nearly) zero, so a traction is fixed only up to one multiple of the
+normal per body, which GMRES picks along its own Krylov path.  Stokes
+solutions are therefore compared after removing, body by body, their
+area-weighted normal component, and through the force on each body (which the
+normal field does not change).
 """
 import numpy as np
 import pytest
@@ -33,6 +40,42 @@ def describe(rep, x, xo):
             f"prec={[int(v) for v in rep['prec_hist']]} true={rep['rel_res_true']:.1e} err={rel_l2(x, xo):.1e}")
 
 
+def bodies_of(name, n_panels):
+    if name.startswith("cells"):
+        k = int(name[5:].split("x")[0])
+        return [range(i * (n_panels // k), (i + 1) * (n_panels // k)) for i in range(k)]
+    return [range(n_panels)]
+
+
+def strip_normal(orc, m, t, bodies):
+    """t minus, per body, its area-weighted normal component."""
+    _, S, nrm = orc.panels(m.xyz, m.tri)
+    t = t.reshape(-1, 3).copy()
+    for b in bodies:
+        idx = np.fromiter(b, dtype=np.int64)
+        a = np.sum(np.einsum("ij,ij->i", t[idx], nrm[idx]) * S[idx]) / np.sum(S[idx])
+        t[idx] -= a * nrm[idx]
+    return t.reshape(-1)
+
+
+def body_forces(orc, m, t, bodies):
+    _, S, _ = orc.panels(m.xyz, m.tri)
+    t = t.reshape(-1, 3)
+    return np.array([np.sum(t[np.fromiter(b, dtype=np.int64)] * S[np.fromiter(b, dtype=np.int64), None], axis=0)
+                     for b in bodies])
+
+
+def compare(orc, kernel, mesh_name, m, x, xo):
+    """relative error of x against the oracle solution, null-space free for Stokes"""
+    if kernel == 0:
+        return rel_l2(x, xo)
+    bodies = bodies_of(mesh_name, m.n_panels)
+    e = rel_l2(strip_normal(orc, m, x, bodies), strip_normal(orc, m, xo, bodies))
+    Fo = body_forces(orc, m, xo, bodies)
+    eF = float(np.max(np.abs(body_forces(orc, m, x, bodies) - Fo)) / np.max(np.abs(Fo)))
+    return max(e, eF)
+
+
 CASES = {
     "laplace_sphere_one": (0, "sphere2048", lambda m: np.ones(m.n_panels), 12, 3),
     "laplace_sphere_ylm": (0, "sphere2048", lambda m: syn.ylm_rhs(m, 3, 0), 12, 3),
@@ -53,10 +96,11 @@ def test_solve_parity_tight(orc, case, rule, mixed):
     xo = orc.solve(kernel, m.xyz, m.tri, b, tol=1e-11)[0]
     ctx = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(ncrit=64, p_max=p_init))
     x, rep = solve(fb, ctx, b, 1e-8, fb.schedule(kernel, rule=rule, mixed=mixed, p_init=p_init, p_min=p_min))
-    announce(describe(rep, x, xo))
+    err = compare(orc, kernel, mesh_name, m, x, xo)
+    announce(describe(rep, x, xo) + f" cmp={err:.1e}")
     assert rep["converged"]
     assert rep["rel_res_true"] <= 1e-7
-    assert rel_l2(x, xo) <= 1e-5
+    assert err <= 1e-5
     if rule == 0:
         assert set(int(v) for v in rep["p_hist"]) == {p_init}
         assert set(int(v) for v in rep["prec_hist"]) == {0}
@@ -80,7 +124,9 @@ def test_solve_bench_tolerance(orc, case):
     announce(describe(rr, xr, xo))
     assert rf["converged"] and rr["converged"]
     assert rr["rel_res_true"] <= 1.5e-6
-    assert rel_l2(xr, xo) <= 2 * rel_l2(xf, xo) + 1e-5
+    ef, er = compare(orc, kernel, mesh_name, m, xf, xo), compare(orc, kernel, mesh_name, m, xr, xo)
+    announce(f"  fixed {ef:.1e} relaxed {er:.1e}")
+    assert er <= 2 * ef + 1e-5
     if kernel == 1:
         F, _ = orc.force_torque(m.xyz, m.tri, xr)
         assert abs(F[0] + 6 * np.pi) / (6 * np.pi) < 5e-3

@@ -211,3 +211,13 @@ def test_gmres_implicit_residual_is_true_residual(orc):
     assert it == 10
     assert abs(hist[-1] - np.linalg.norm(b - A @ x) / np.linalg.norm(b)) < 1e-12
     assert abs(tr - hist[-1]) < 1e-12
+
+
+def test_stokes_normal_field_is_near_null(orc):
+    # incompressibility: a traction along the normal of a closed body induces no
+    # velocity (int_S G n dS = 0), so the discrete operator nearly annihilates n
+    m = syn.sphere(3)
+    c, S, n = orc.panels(m.xyz, m.tri)
+    un = orc.matvec(orc.STOKES, m.xyz, m.tri, n.reshape(-1))
+    ue = orc.matvec(orc.STOKES, m.xyz, m.tri, np.tile([1.0, 0.0, 0.0], m.n_panels))
+    assert np.linalg.norm(un) < 1e-4 * np.linalg.norm(ue)
