@@ -103,6 +103,7 @@ struct Correction {
     int64_t nnz = 0;
     int32_t *ptr = nullptr;  // [nt + 1] by sorted target
     int32_t *col = nullptr;  // [nnz] sorted source panel
+    int32_t *col_orig = nullptr;  // [nnz] the same panel in the caller's order
     double *val = nullptr;   // [nnz] (Laplace) or [nnz][9] (Stokes), without the kernel prefactor
 };
 
@@ -128,6 +129,11 @@ struct M2LPlan {
     uint64_t *trans_key = nullptr;      // [n_trans]
     cplx<double> *table64 = nullptr;    // [n_trans][(q+1)^2] full irregular tables
     cplx<float> *table32 = nullptr;
+    // parent <-> child: the child centre sits at (+-1/2, +-1/2, +-1/2) parent
+    // half-sizes from the parent centre; regular tables of the 8 offsets
+    int8_t *box_oct = nullptr;          // [nbox] octant of each box in its parent (x<<2 | y<<1 | z)
+    cplx<double> *oct64 = nullptr;      // [8][(p_max+1)^2]
+    cplx<float> *oct32 = nullptr;
 };
 
 // GMRES workspace, one per context (krylov.hip)
@@ -141,6 +147,7 @@ struct KrylovWork {
     double *part = nullptr;  // [m+2][nb]
     double *h = nullptr;     // [2*(m+2)] device: h1 | h2 (second pass) ; h[.. + m+1] = |w|^2
     double *y = nullptr;     // [m+1]
+    unsigned int *ticket = nullptr;  // [m+2] arrival counters of the fused reductions
     DevArena arena;
 };
 

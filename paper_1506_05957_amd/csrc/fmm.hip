@@ -30,8 +30,6 @@ template <> __device__ inline float inv_int<float>(int k) { return c_inv_f.v[k];
 
 namespace {
 
-constexpr int FULL_MAX = (P_MAX + 1) * (P_MAX + 1);
-
 __device__ inline int full_idx(int n, int m) { return n * n + n + m; }
 
 // Column m (n = m..p) of the regular harmonics at (x, y, z), written to the
@@ -159,28 +157,34 @@ __global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const do
 }
 
 // ---------------------------------------------------------------------------
-// P2M (a5): one block per leaf; thread = (order m, source slice).
-template <typename R, int NCH>
+// P2M (a5): one block per leaf.  Thread = (order m, source slice): it runs the
+// recurrence of column m (n = m..p) for every source of its slice and
+// accumulates q conj(R_n^m((y - c) / s)); slices are summed in a fixed order.
+// PM is a compile-time bound on p so that the accumulators stay in registers.
+template <typename R, int NCH, int PM>
 __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__restrict__ leaves,
                                              const int32_t *__restrict__ box_i, const double *__restrict__ box_r,
                                              double side, const Src<R, NCH == 4> *__restrict__ src,
                                              cplx<R> *__restrict__ M)
 {
-    constexpr int SL = 8;
-    __shared__ cplx<R> red[SL][NC_MAX];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *red = reinterpret_cast<cplx<R> *>(smem_raw);  // [nsl][nc]
     const int b = leaves[blockIdx.x];
     const int lv = box_i[6 * b], pb = box_i[6 * b + 1], pe = box_i[6 * b + 2];
     const double s = ldexp(side, -(lv + 1));
     const double *c = box_r + 5 * (int64_t)b;
-    const int m = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const int nm = p + 1, nsl = (int)blockDim.x / nm;
+    const int m = threadIdx.x % nm, sl = threadIdx.x / nm;
+    const bool active = sl < nsl;
     const int nc = ncoef(p);
+    const R is = (R)(1.0 / s);
     for (int ch = 0; ch < NCH; ++ch) {
-        R are[P_MAX + 1], aim[P_MAX + 1];
+        R are[PM + 1], aim[PM + 1];
 #pragma unroll
-        for (int n = 0; n <= P_MAX; ++n)
+        for (int n = 0; n <= PM; ++n)
             are[n] = aim[n] = 0;
-        if (m <= p) {
-            for (int64_t si = 4 * (int64_t)pb + sl; si < 4 * (int64_t)pe; si += SL) {
+        if (active) {
+            for (int64_t si = 4 * (int64_t)pb + sl; si < 4 * (int64_t)pe; si += nsl) {
                 const Src<R, NCH == 4> sv = src[si];
                 R x, y, z;  // relative to the leaf centre
                 if constexpr (sizeof(R) == 8) {
@@ -198,7 +202,6 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
                 } else {
                     qq = ch == 0 ? sv.f0 : ch == 1 ? sv.f1 : ch == 2 ? sv.f2 : (sv.f0 * x + sv.f1 * y) + sv.f2 * z;
                 }
-                const R is = (R)(1.0 / s);
                 x *= is;
                 y *= is;
                 z *= is;
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
                 }
                 R cr = 0, ci = 0, pr = 0, pi = 0;
 #pragma unroll
-                for (int n = 0; n <= P_MAX; ++n) {
+                for (int n = 0; n <= PM; ++n) {
                     if (n <= p) {
                         if (n == m) {
                             cr = dre;
@@ -233,111 +236,98 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
                     }
                 }
             }
-        }
-        if (m <= p) {
 #pragma unroll
-            for (int n = 0; n <= P_MAX; ++n)
+            for (int n = 0; n <= PM; ++n)
                 if (n <= p && n >= m)
-                    red[sl][cidx(n, m)] = cplx<R>{are[n], aim[n]};
+                    red[sl * nc + cidx(n, m)] = cplx<R>{are[n], aim[n]};
         }
         __syncthreads();
         for (int t = threadIdx.x; t < nc; t += blockDim.x) {
-            R sr = 0, si = 0;
-            for (int k = 0; k < SL; ++k) {
-                sr += red[k][t].re;
-                si += red[k][t].im;
+            R sr = 0, si2 = 0;
+            for (int k = 0; k < nsl; ++k) {
+                sr += red[k * nc + t].re;
+                si2 += red[k * nc + t].im;
             }
-            M[((int64_t)b * NCH + ch) * ncs + t] = cplx<R>{sr, si};
+            M[((int64_t)b * NCH + ch) * ncs + t] = cplx<R>{sr, si2};
         }
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// M2M (a6): one block per box of a level; sums its children (written before).
+// M2M (a6): one block per box of a level; sums its children (written before):
+// M_n^m(P) = sum_C sum_{k,l} conj(R_k^l(delta_C)) 2^-(n-k) M_{n-k}^{m-l}(C), with
+// delta_C = (c_C - c_P) / s_P one of the 8 tabulated octant offsets.
 template <typename R, int NCH>
-__global__ __launch_bounds__(64) void k_m2m(int p, int ncs, int box0, const int32_t *__restrict__ box_i,
-                                            const double *__restrict__ box_r, double side, cplx<R> *__restrict__ M)
+__global__ __launch_bounds__(256) void k_m2m(int p, int ncs, int fpm, int box0, const int32_t *__restrict__ box_i,
+                                             const double *__restrict__ box_r, const int8_t *__restrict__ box_oct,
+                                             const cplx<R> *__restrict__ oct_tab, cplx<R> *__restrict__ M)
 {
-    __shared__ cplx<R> Rt[FULL_MAX];
-    __shared__ cplx<R> Mc[NCH][FULL_MAX];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int P = box0 + blockIdx.x;
     const int nchild = box_i[6 * P + 5];
     if (nchild == 0)
         return;
-    const int c0 = box_i[6 * P + 4], lvP = box_i[6 * P];
-    const double sP = ldexp(side, -(lvP + 1));
-    const double *cP = box_r + 5 * (int64_t)P;
     const int nc = ncoef(p);
-    constexpr int NO = (NC_MAX + 63) / 64;
-    R acc_re[NO][NCH], acc_im[NO][NCH];
-#pragma unroll
-    for (int o = 0; o < NO; ++o)
+    const int nslot = max(1, min(8, (int)blockDim.x / nc));
+    const int slot = threadIdx.x / nc, idx = threadIdx.x - slot * nc;
+    cplx<R> *red = reinterpret_cast<cplx<R> *>(smem_raw);  // [nslot][NCH][nc]
+    const int c0 = box_i[6 * P + 4];
+    const double *cP = box_r + 5 * (int64_t)P;
+    if (slot < nslot) {
+        int n, m;
+        idx_to_nm(idx, n, m);
+        R acc_re[NCH], acc_im[NCH];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
-            acc_re[o][ch] = acc_im[o][ch] = 0;
-    for (int C = c0; C < c0 + nchild; ++C) {
-        const double *cC = box_r + 5 * (int64_t)C;
-        const double dphys[3] = {cC[0] - cP[0], cC[1] - cP[1], cC[2] - cP[2]};
-        __syncthreads();
-        if ((int)threadIdx.x <= p)
-            regular_column_full<R>((R)(dphys[0] / sP), (R)(dphys[1] / sP), (R)(dphys[2] / sP), threadIdx.x, p, Rt);
-        for (int t = threadIdx.x; t < (p + 1) * (p + 1); t += blockDim.x) {
-            int n = 0;
-            while ((n + 1) * (n + 1) <= t)
-                ++n;
-            int m = t - n * n - n;
-            R sc = (R)ldexp(1.0, -n);
-            for (int ch = 0; ch < NCH; ++ch) {
-                cplx<R> v = load_full(M + ((int64_t)C * NCH + ch) * ncs, n, m);
-                Mc[ch][t] = cplx<R>{v.re * sc, v.im * sc};
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int o = 0; o < NO; ++o) {
-            int idx = threadIdx.x + 64 * o;
-            if (idx >= nc)
-                continue;
-            int n, m;
-            idx_to_nm(idx, n, m);
+            acc_re[ch] = acc_im[ch] = 0;
+        for (int cc = slot; cc < nchild; cc += nslot) {
+            const int C = c0 + cc;
+            const cplx<R> *Rc = oct_tab + (int64_t)box_oct[C] * fpm;
+            const cplx<R> *MC = M + (int64_t)C * NCH * ncs;
             R sre[NCH], sim[NCH];
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch)
                 sre[ch] = sim[ch] = 0;
             for (int k = 0; k <= n; ++k) {
-                int j = n - k;
-                int l0 = max(-k, m - j), l1 = min(k, m + j);
+                const int j = n - k;
+                const R sc = (R)ldexp(1.0, -j);
+                const int l0 = max(-k, m - j), l1 = min(k, m + j);
                 for (int l = l0; l <= l1; ++l) {
-                    cplx<R> rv = Rt[full_idx(k, l)];  // conj applied below
-                    int mi = full_idx(j, m - l);
+                    const cplx<R> rv = Rc[full_idx(k, l)];  // conj applied below
 #pragma unroll
                     for (int ch = 0; ch < NCH; ++ch) {
-                        cplx<R> mv = Mc[ch][mi];
-                        sre[ch] += rv.re * mv.re + rv.im * mv.im;
-                        sim[ch] += rv.re * mv.im - rv.im * mv.re;
+                        const cplx<R> mv = load_full(MC + ch * ncs, j, m - l);
+                        sre[ch] += sc * (rv.re * mv.re + rv.im * mv.im);
+                        sim[ch] += sc * (rv.re * mv.im - rv.im * mv.re);
                     }
                 }
             }
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                acc_re[o][ch] += sre[ch];
-                acc_im[o][ch] += sim[ch];
+                acc_re[ch] += sre[ch];
+                acc_im[ch] += sim[ch];
             }
             if constexpr (NCH == 4) {
-                acc_re[o][3] += (R)dphys[0] * sre[0] + (R)dphys[1] * sre[1] + (R)dphys[2] * sre[2];
-                acc_im[o][3] += (R)dphys[0] * sim[0] + (R)dphys[1] * sim[1] + (R)dphys[2] * sim[2];
+                const double *cC = box_r + 5 * (int64_t)C;
+                const R d0 = (R)(cC[0] - cP[0]), d1 = (R)(cC[1] - cP[1]), d2 = (R)(cC[2] - cP[2]);
+                acc_re[3] += d0 * sre[0] + d1 * sre[1] + d2 * sre[2];
+                acc_im[3] += d0 * sim[0] + d1 * sim[1] + d2 * sim[2];
             }
         }
-    }
-#pragma unroll
-    for (int o = 0; o < NO; ++o) {
-        int idx = threadIdx.x + 64 * o;
-        if (idx >= nc)
-            continue;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
-            M[((int64_t)P * NCH + ch) * ncs + idx] = cplx<R>{acc_re[o][ch], acc_im[o][ch]};
+            red[(slot * NCH + ch) * nc + idx] = cplx<R>{acc_re[ch], acc_im[ch]};
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < NCH * nc; t += blockDim.x) {
+        R sr = 0, si = 0;
+        for (int sl = 0; sl < nslot; ++sl) {
+            sr += red[sl * NCH * nc + t].re;
+            si += red[sl * NCH * nc + t].im;
+        }
+        const int ch = t / nc, id = t - ch * nc;
+        M[((int64_t)P * NCH + ch) * ncs + id] = cplx<R>{sr, si};
     }
 }
 
@@ -360,10 +350,8 @@ __global__ __launch_bounds__(256) void k_m2l_group(int p, int ncs, int q_tab, co
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int q = 2 * p;
-    const int fq = (q + 1) * (q + 1), fp = (p + 1) * (p + 1), nc = ncoef(p);
-    const int nslots = max(1, (int)blockDim.x / nc);
+    const int fq = (q + 1) * (q + 1), nc = ncoef(p);
     cplx<R> *It = reinterpret_cast<cplx<R> *>(smem_raw);
-    cplx<R> *Ms = It + fq;  // [nslots][PB][NCH][fp]
     const int c = blockIdx.x;
     const int u = chunk_trans[c], pb = chunk_begin[c], pe = chunk_begin[c + 1];
     const uint64_t key = trans_key[u];
@@ -371,133 +359,153 @@ __global__ __launch_bounds__(256) void k_m2l_group(int p, int ncs, int q_tab, co
     const cplx<R> *tab = table + (int64_t)u * (q_tab + 1) * (q_tab + 1);
     for (int t = threadIdx.x; t < fq; t += blockDim.x)
         It[t] = tab[t];
-    const int slot = threadIdx.x / nc, idx = threadIdx.x - slot * nc;
-    const bool active = slot < nslots;
-    int k = 0, l = 0;
-    idx_to_nm(active ? idx : 0, k, l);
-    const R f = (R)ldexp((k & 1) ? -1.0 : 1.0, -eT * (k + 1));
-    const int per_round = nslots * PB;
-    for (int base = pb; base < pe; base += per_round) {
-        __syncthreads();
-        const int nload = per_round * NCH * fp;
-        for (int t = threadIdx.x; t < nload; t += blockDim.x) {
-            const int fi = t % fp;
-            const int ch = (t / fp) % NCH;
-            const int sj = t / (fp * NCH);  // slot * PB + j
-            const int pos = base + sj;
-            cplx<R> v{0, 0};
-            if (pos < pe) {
-                const int S = pairs[2 * pair_sorted[pos] + 1];
-                int n = (int)sqrtf((float)fi);
-                while ((n + 1) * (n + 1) <= fi)
-                    ++n;
-                while (n * n > fi)
-                    --n;
-                const int m = fi - n * n - n;
-                v = load_full(M + ((int64_t)S * NCH + ch) * ncs, n, m);
-                const R sc = (R)ldexp(1.0, -eS * n);
-                v.re *= sc;
-                v.im *= sc;
-            }
-            Ms[t] = v;
-        }
-        __syncthreads();
-        if (!active)
-            continue;
-        R are[PB][NCH], aim[PB][NCH];
+    __syncthreads();
+    // waves take PB-pair batches in turn; lanes are output coefficients (k, l)
+    const int nwave = blockDim.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const R rS = (R)ldexp(1.0, -eS);
+    for (int o0 = 0; o0 < nc; o0 += 64) {
+        const int idx = o0 + lane;
+        const bool active = idx < nc;
+        int k = 0, l = 0;
+        idx_to_nm(active ? idx : 0, k, l);
+        const R f = (R)ldexp((k & 1) ? -1.0 : 1.0, -eT * (k + 1));
+        for (int base = pb + wv * PB; base < pe; base += nwave * PB) {
+            int Sb[PB];
 #pragma unroll
-        for (int j = 0; j < PB; ++j)
+            for (int j = 0; j < PB; ++j)
+                Sb[j] = base + j < pe ? pairs[2 * pair_sorted[base + j] + 1] : pairs[2 * pair_sorted[base] + 1];
+            R are[PB][NCH], aim[PB][NCH];
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-                are[j][ch] = aim[j][ch] = 0;
-        const cplx<R> *Mslot = Ms + (int64_t)slot * PB * NCH * fp;
-        for (int n = 0; n <= p; ++n) {
-            const cplx<R> *Irow = It + (n + k) * (n + k) + (n + k) + l;  // + m
-            const int mb = n * n + n;
-            for (int m = -n; m <= n; ++m) {
-                const cplx<R> iv = Irow[m];
+            for (int j = 0; j < PB; ++j)
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch)
+                    are[j][ch] = aim[j][ch] = 0;
+            // Horner in n: acc = acc * 2^-eS + sum_m M_n^m I_{n+k}^{m+l}, n = p..0
+            for (int n = p; n >= 0; --n) {
 #pragma unroll
                 for (int j = 0; j < PB; ++j)
 #pragma unroll
                     for (int ch = 0; ch < NCH; ++ch) {
-                        const cplx<R> mv = Mslot[(j * NCH + ch) * fp + mb + m];
-                        are[j][ch] += mv.re * iv.re - mv.im * iv.im;
-                        aim[j][ch] += mv.re * iv.im + mv.im * iv.re;
+                        are[j][ch] *= rS;
+                        aim[j][ch] *= rS;
                     }
-            }
-        }
+                const cplx<R> *Irow = It + (n + k) * (n + k) + (n + k) + l;
+                // m = 0 and the pairs (m, -m), m > 0, with M_n^-m = (-1)^m conj(M_n^m):
+                // M_n^m I^{l+m} + (-1)^m conj(M_n^m) I^{l-m}
+                {
+                    const cplx<R> iv = Irow[0];
 #pragma unroll
-        for (int j = 0; j < PB; ++j) {
-            const int pos = base + slot * PB + j;
-            if (pos >= pe)
+                    for (int j = 0; j < PB; ++j)
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch) {
+                            const cplx<R> mv = M[((int64_t)Sb[j] * NCH + ch) * ncs + cidx(n, 0)];
+                            are[j][ch] += mv.re * iv.re;
+                            are[j][ch] -= mv.im * iv.im;
+                            aim[j][ch] += mv.re * iv.im;
+                            aim[j][ch] += mv.im * iv.re;
+                        }
+                }
+#pragma unroll 2
+                for (int m = 1; m <= n; ++m) {
+                    const cplx<R> ip = Irow[m], in0 = Irow[-m];
+                    const R sg = (m & 1) ? R(-1) : R(1);
+                    const cplx<R> iq{sg * in0.re, sg * in0.im};
+#pragma unroll
+                    for (int j = 0; j < PB; ++j)
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch) {
+                            const cplx<R> mv = M[((int64_t)Sb[j] * NCH + ch) * ncs + cidx(n, m)];
+                            are[j][ch] += mv.re * ip.re;
+                            are[j][ch] -= mv.im * ip.im;
+                            aim[j][ch] += mv.re * ip.im;
+                            aim[j][ch] += mv.im * ip.re;
+                            are[j][ch] += mv.re * iq.re;
+                            are[j][ch] += mv.im * iq.im;
+                            aim[j][ch] += mv.re * iq.im;
+                            aim[j][ch] -= mv.im * iq.re;
+                        }
+                }
+            }
+            if (!active)
                 continue;
-            const int orig = pair_sorted[pos];
-            R o_re[NCH], o_im[NCH];
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                o_re[ch] = f * are[j][ch];
-                o_im[ch] = f * aim[j][ch];
-            }
-            if constexpr (NCH == 4) {
-                // change of centre of Phi_4 from c_S to c_T
-                const double *cT = box_r + 5 * (int64_t)pairs[2 * orig], *cS = box_r + 5 * (int64_t)pairs[2 * orig + 1];
-                const R g0 = (R)(cS[0] - cT[0]), g1 = (R)(cS[1] - cT[1]), g2 = (R)(cS[2] - cT[2]);
-                o_re[3] += g0 * o_re[0] + g1 * o_re[1] + g2 * o_re[2];
-                o_im[3] += g0 * o_im[0] + g1 * o_im[1] + g2 * o_im[2];
-            }
+            for (int j = 0; j < PB; ++j) {
+                if (base + j >= pe)
+                    continue;
+                const int orig = pair_sorted[base + j];
+                R o_re[NCH], o_im[NCH];
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-                Y[((int64_t)orig * NCH + ch) * nc + idx] = cplx<R>{o_re[ch], o_im[ch]};
+                for (int ch = 0; ch < NCH; ++ch) {
+                    o_re[ch] = f * are[j][ch];
+                    o_im[ch] = f * aim[j][ch];
+                }
+                if constexpr (NCH == 4) {
+                    // change of centre of Phi_4 from c_S to c_T
+                    const double *cT = box_r + 5 * (int64_t)pairs[2 * orig], *cS = box_r + 5 * (int64_t)pairs[2 * orig + 1];
+                    const R g0 = (R)(cS[0] - cT[0]), g1 = (R)(cS[1] - cT[1]), g2 = (R)(cS[2] - cT[2]);
+                    o_re[3] += g0 * o_re[0] + g1 * o_re[1] + g2 * o_re[2];
+                    o_im[3] += g0 * o_im[0] + g1 * o_im[1] + g2 * o_im[2];
+                }
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch)
+                    Y[((int64_t)orig * NCH + ch) * nc + idx] = cplx<R>{o_re[ch], o_im[ch]};
+            }
         }
     }
 }
 
-// Pass 2: L(T) = sum of Y over T's pairs (CSR order), all boxes.
+// Pass 2: L(T) = sum of Y over T's pairs (CSR order), all boxes; thread =
+// (pair slice, output), slices summed in a fixed order.
 template <typename R, int NCH>
 __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_t *__restrict__ ptr,
                                                     const cplx<R> *__restrict__ Y, cplx<R> *__restrict__ L)
 {
+    __shared__ cplx<R> red[256];
     const int T = blockIdx.x;
-    const int nc = ncoef(p);
+    const int no = NCH * ncoef(p);
     const int e0 = ptr[T], e1 = ptr[T + 1];
-    for (int t = threadIdx.x; t < NCH * nc; t += blockDim.x) {
+    for (int o0 = 0; o0 < no; o0 += blockDim.x) {
+        const int span = min((int)blockDim.x, no - o0);
+        const int sl = threadIdx.x / span, t = o0 + threadIdx.x % span;
+        const int nsl_here = max(1, (int)blockDim.x / span);
         R sr = 0, si = 0;
-        for (int e = e0; e < e1; ++e) {
-            const cplx<R> v = Y[(int64_t)e * NCH * nc + t];
-            sr += v.re;
-            si += v.im;
+        if (sl < nsl_here) {
+            for (int e = e0 + sl; e < e1; e += nsl_here) {
+                const cplx<R> v = Y[(int64_t)e * no + t];
+                sr += v.re;
+                si += v.im;
+            }
         }
-        const int ch = t / nc, idx = t - ch * nc;
-        L[((int64_t)T * NCH + ch) * ncs + idx] = cplx<R>{sr, si};
+        __syncthreads();
+        red[threadIdx.x] = cplx<R>{sr, si};
+        __syncthreads();
+        if ((int)threadIdx.x < span) {
+            R ar = 0, ai = 0;
+            for (int k = 0; k < nsl_here; ++k) {
+                ar += red[k * span + threadIdx.x].re;
+                ai += red[k * span + threadIdx.x].im;
+            }
+            const int ch = t / ncoef(p), idx = t - ch * ncoef(p);
+            L[((int64_t)T * NCH + ch) * ncs + idx] = cplx<R>{ar, ai};
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// L2L (a8): one block per box of a level >= 1, adds its parent's local expansion.
+// L2L (a8): one block per box of a level >= 1, adds its parent's local expansion:
+// L_j^k(C) += 2^-(j+1) sum_{n >= j, m} L_n^m(P) conj(R_{n-j}^{m-k}(delta_C)).
 template <typename R, int NCH>
-__global__ __launch_bounds__(64) void k_l2l(int p, int ncs, int box0, const int32_t *__restrict__ box_i,
-                                            const double *__restrict__ box_r, double side, cplx<R> *__restrict__ L)
+__global__ __launch_bounds__(256) void k_l2l(int p, int ncs, int fpm, int box0, const int32_t *__restrict__ box_i,
+                                             const double *__restrict__ box_r, const int8_t *__restrict__ box_oct,
+                                             const cplx<R> *__restrict__ oct_tab, cplx<R> *__restrict__ L)
 {
-    __shared__ cplx<R> Rt[FULL_MAX];
-    __shared__ cplx<R> Lp[NCH][FULL_MAX];
+    const int nc = ncoef(p);
     const int C = box0 + blockIdx.x;
     const int P = box_i[6 * C + 3];
-    const int lvP = box_i[6 * P];
-    const double sP = ldexp(side, -(lvP + 1));
+    const cplx<R> *Rt = oct_tab + (int64_t)box_oct[C] * fpm;
+    const cplx<R> *LP = L + (int64_t)P * NCH * ncs;
     const double *cP = box_r + 5 * (int64_t)P, *cC = box_r + 5 * (int64_t)C;
-    const double dphys[3] = {cC[0] - cP[0], cC[1] - cP[1], cC[2] - cP[2]};
-    if ((int)threadIdx.x <= p)
-        regular_column_full<R>((R)(dphys[0] / sP), (R)(dphys[1] / sP), (R)(dphys[2] / sP), threadIdx.x, p, Rt);
-    for (int t = threadIdx.x; t < (p + 1) * (p + 1); t += blockDim.x) {
-        int n = 0;
-        while ((n + 1) * (n + 1) <= t)
-            ++n;
-        int m = t - n * n - n;
-        for (int ch = 0; ch < NCH; ++ch)
-            Lp[ch][t] = load_full(L + ((int64_t)P * NCH + ch) * ncs, n, m);
-    }
-    __syncthreads();
-    const int nc = ncoef(p);
     for (int idx = threadIdx.x; idx < nc; idx += blockDim.x) {
         int j, kk;
         idx_to_nm(idx, j, kk);
@@ -506,23 +514,23 @@ __global__ __launch_bounds__(64) void k_l2l(int p, int ncs, int box0, const int3
         for (int ch = 0; ch < NCH; ++ch)
             sre[ch] = sim[ch] = 0;
         for (int n = j; n <= p; ++n) {
-            int a = n - j;
-            int m0 = max(-n, kk - a), m1 = min(n, kk + a);
+            const int a = n - j;
+            const int m0 = max(-n, kk - a), m1 = min(n, kk + a);
             for (int m = m0; m <= m1; ++m) {
-                cplx<R> rv = Rt[full_idx(a, m - kk)];  // conj below
-                int li = full_idx(n, m);
+                const cplx<R> rv = Rt[full_idx(a, m - kk)];  // conj below
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
-                    cplx<R> lv = Lp[ch][li];
+                    const cplx<R> lv = load_full(LP + ch * ncs, n, m);
                     sre[ch] += lv.re * rv.re + lv.im * rv.im;
                     sim[ch] += lv.im * rv.re - lv.re * rv.im;
                 }
             }
         }
-        R f = (R)ldexp(1.0, -(j + 1));
+        const R f = (R)ldexp(1.0, -(j + 1));
         if constexpr (NCH == 4) {
-            sre[3] -= (R)dphys[0] * sre[0] + (R)dphys[1] * sre[1] + (R)dphys[2] * sre[2];
-            sim[3] -= (R)dphys[0] * sim[0] + (R)dphys[1] * sim[1] + (R)dphys[2] * sim[2];
+            const R d0 = (R)(cC[0] - cP[0]), d1 = (R)(cC[1] - cP[1]), d2 = (R)(cC[2] - cP[2]);
+            sre[3] -= d0 * sre[0] + d1 * sre[1] + d2 * sre[2];
+            sim[3] -= d0 * sim[0] + d1 * sim[1] + d2 * sim[2];
         }
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
@@ -649,20 +657,60 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
 }
 
 // ---------------------------------------------------------------------------
-// P2P (a10): one block per target leaf, one target per lane, the 4 waves of the
-// block splitting the leaf's source leaves.  Source indices are wave-uniform,
-// so each packed source is fetched once per wave through the scalar cache and
-// feeds 64 targets; the 4 partial sums are reduced in a fixed order.
-// FP32 works in leaf-relative coordinates: r = (t - c_T) + (c_T - c_S) - (y - c_S).
+// P2P (a10): one block per target leaf, one target per lane, the NW waves of
+// the block splitting the leaf's source leaves.  Source indices are
+// wave-uniform, so each packed source is fetched once per wave through the
+// scalar cache and feeds 64 targets; the NW partial sums are reduced in a fixed
+// order.  FP32 works in leaf-relative coordinates:
+// r = (t - c_T) + (c_T - c_S) - (y - c_S).
+constexpr int P2P_WAVES = 16;
+
+template <typename R, bool STOKES, bool SELF>
+__device__ __forceinline__ void p2p_leaf(int k0, int k1, int i, R px, R py, R pz,
+                                         const Src<R, STOKES> *__restrict__ src, R *acc)
+{
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) {
+        const Src<R, STOKES> sv = src[k];
+        const R dx = px - sv.x, dy = py - sv.y, dz = pz - sv.z;
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        R rinv;
+        if constexpr (sizeof(R) == 8) {
+            // hardware estimate refined by two Newton steps (r2 is finite and > 0
+            // for every pair the result keeps; the self pair is masked below)
+            double y = __builtin_amdgcn_rsq(r2);
+            const double h = 0.5 * r2;
+            y = y * (1.5 - h * y * y);
+            y = y * (1.5 - h * y * y);
+            rinv = y;
+        } else {
+            rinv = __builtin_amdgcn_rsqf(r2);
+        }
+        if constexpr (SELF)
+            rinv = (k >> 2) == i ? R(0) : rinv;  // the target's own panel: integrated by the correction
+        if constexpr (!STOKES) {
+            acc[0] += sv.q * rinv;
+        } else {
+            const R dot = (dx * sv.f0 + dy * sv.f1 + dz * sv.f2) * (rinv * rinv * rinv);
+            acc[0] += sv.f0 * rinv + dx * dot;
+            acc[1] += sv.f1 * rinv + dy * dot;
+            acc[2] += sv.f2 * rinv + dz * dot;
+        }
+    }
+}
+
 template <typename R, bool STOKES>
-__global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaves, const int32_t *__restrict__ box_i,
-                                             const int32_t *__restrict__ ptr, const int32_t *__restrict__ srcs,
-                                             const double *__restrict__ box_r, int64_t nt,
-                                             const double *__restrict__ tc, const float *__restrict__ tc32,
-                                             const Src<R, STOKES> *__restrict__ src, double *__restrict__ ynear)
+__global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(const int32_t *__restrict__ leaves,
+                                                        const int32_t *__restrict__ box_i,
+                                                        const int32_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ srcs,
+                                                        const double *__restrict__ box_r, int64_t nt,
+                                                        const double *__restrict__ tc, const float *__restrict__ tc32,
+                                                        const Src<R, STOKES> *__restrict__ src,
+                                                        double *__restrict__ ynear)
 {
     constexpr int NQ = STOKES ? 3 : 1;
-    __shared__ R red[4][NQ][64];
+    __shared__ R red[P2P_WAVES][NQ][64];
     const int b = leaves[blockIdx.x];
     const int tb = box_i[6 * b + 1], te = box_i[6 * b + 2];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -688,7 +736,7 @@ __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaves,
 #pragma unroll
         for (int a = 0; a < NQ; ++a)
             acc[a] = 0;
-        for (int e = e0 + w; e < e1; e += 4) {
+        for (int e = e0 + w; e < e1; e += P2P_WAVES) {
             const int sb = srcs[e];
             const int k0 = 4 * box_i[6 * sb + 1], k1 = 4 * box_i[6 * sb + 2];
             R px = tx, py = ty, pz = tz;
@@ -698,28 +746,10 @@ __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaves,
                 py += (float)(cT[1] - cS[1]);
                 pz += (float)(cT[2] - cS[2]);
             }
-            const bool self = sb == b;
-#pragma unroll 4
-            for (int k = k0; k < k1; ++k) {
-                const Src<R, STOKES> sv = src[k];
-                const R dx = px - sv.x, dy = py - sv.y, dz = pz - sv.z;
-                const R r2 = dx * dx + dy * dy + dz * dz;
-                R rinv;
-                if constexpr (sizeof(R) == 8)
-                    rinv = rsqrt(r2);
-                else
-                    rinv = __builtin_amdgcn_rsqf(r2);
-                if (self && (k >> 2) == i)
-                    rinv = 0;  // the target's own panel: integrated by the correction
-                if constexpr (!STOKES) {
-                    acc[0] += sv.q * rinv;
-                } else {
-                    const R dot = (dx * sv.f0 + dy * sv.f1 + dz * sv.f2) * (rinv * rinv * rinv);
-                    acc[0] += sv.f0 * rinv + dx * dot;
-                    acc[1] += sv.f1 * rinv + dy * dot;
-                    acc[2] += sv.f2 * rinv + dz * dot;
-                }
-            }
+            if (sb == b)
+                p2p_leaf<R, STOKES, true>(k0, k1, i, px, py, pz, src, acc);
+            else
+                p2p_leaf<R, STOKES, false>(k0, k1, i, px, py, pz, src, acc);
         }
 #pragma unroll
         for (int a = 0; a < NQ; ++a)
@@ -728,8 +758,9 @@ __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaves,
         if (w == 0 && active) {
 #pragma unroll
             for (int a = 0; a < NQ; ++a) {
-                double sum = ((double)red[0][a][lane] + (double)red[1][a][lane]) +
-                             ((double)red[2][a][lane] + (double)red[3][a][lane]);
+                double sum = 0.0;
+                for (int v = 0; v < P2P_WAVES; ++v)
+                    sum += (double)red[v][a][lane];
                 ynear[(int64_t)NQ * i + a] = sum;
             }
         }
@@ -752,13 +783,13 @@ __global__ void k_combine(int64_t nt, const int32_t *__restrict__ perm, const in
     if (!STOKES) {
         double acc = ynear[i] + yfar[i];
         for (int e = cptr[i]; e < cptr[i + 1]; ++e)
-            acc += cval[e] * x[perm[ccol[e]]];
+            acc += cval[e] * x[ccol[e]];
         y[o] = pref * acc;
     } else {
         double a0 = ynear[3 * i] + yfar[3 * i], a1 = ynear[3 * i + 1] + yfar[3 * i + 1],
                a2 = ynear[3 * i + 2] + yfar[3 * i + 2];
         for (int e = cptr[i]; e < cptr[i + 1]; ++e) {
-            const int64_t jo = perm[ccol[e]];
+            const int64_t jo = ccol[e];
             const double *v = cval + 9 * (int64_t)e;
             const double t0 = x[3 * jo], t1 = x[3 * jo + 1], t2 = x[3 * jo + 2];
             a0 += (v[0] * t0 + v[1] * t1) + v[2] * t2;
@@ -792,11 +823,33 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
 
     if (T.n_m2l > 0) {
         stage_begin(ctx, 2, st, &ev);
-        k_p2m<R, NCH><<<T.nleaf, 256, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-        FB_HIP(hipGetLastError());
+        {
+            const int nsl = 256 / (p + 1);
+            const size_t shm = sizeof(cplx<R>) * (size_t)nsl * ncoef(p);
+            if (p <= 4)
+                k_p2m<R, NCH, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (p <= 8)
+                k_p2m<R, NCH, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (p <= 12)
+                k_p2m<R, NCH, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (p <= 16)
+                k_p2m<R, NCH, 16><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else
+                k_p2m<R, NCH, 20><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            FB_HIP(hipGetLastError());
+        }
+        const M2LPlan &P = ctx->m2l;
+        const int fpm = (ctx->prm.p_max + 1) * (ctx->prm.p_max + 1);
+        const cplx<R> *oct;
+        if constexpr (sizeof(R) == 8)
+            oct = P.oct64;
+        else
+            oct = P.oct32;
         for (int l = T.nlevels - 2; l >= 0; --l) {
             int b0 = T.level_begin[l], nb = T.level_begin[l + 1] - b0;
-            k_m2m<R, NCH><<<nb, 64, 0, st>>>(p, ncs, b0, T.box_i, T.box_r, side, M);
+            const int nslot = std::max(1, std::min(8, 256 / ncoef(p)));
+            const size_t shm = sizeof(cplx<R>) * (size_t)nslot * NCH * ncoef(p);
+            k_m2m<R, NCH><<<nb, 256, shm, st>>>(p, ncs, fpm, b0, T.box_i, T.box_r, P.box_oct, oct, M);
             FB_HIP(hipGetLastError());
         }
         stage_end(ctx, 2, st, ev);
@@ -804,12 +857,8 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
         stage_begin(ctx, 1, st, &ev);
         {
             constexpr int PB = NCH == 1 ? 4 : 1;
-            const M2LPlan &P = ctx->m2l;
-            const int nc = ncoef(p);
-            const int threads = nc > 128 ? 64 * ((nc + 63) / 64) : 256;
-            const int nslots = std::max(1, threads / nc);
-            const size_t shm = sizeof(cplx<R>) * ((size_t)(2 * p + 1) * (2 * p + 1) +
-                                                  (size_t)nslots * PB * NCH * (p + 1) * (p + 1));
+            const int threads = 256;
+            const size_t shm = sizeof(cplx<R>) * ((size_t)(2 * p + 1) * (2 * p + 1));
             const cplx<R> *table;
             if constexpr (sizeof(R) == 8)
                 table = P.table64;
@@ -828,7 +877,7 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
         stage_begin(ctx, 3, st, &ev);
         for (int l = 1; l < T.nlevels; ++l) {
             int b0 = T.level_begin[l], nb = T.level_begin[l + 1] - b0;
-            k_l2l<R, NCH><<<nb, 64, 0, st>>>(p, ncs, b0, T.box_i, T.box_r, side, L);
+            k_l2l<R, NCH><<<nb, std::min(256, 64 * ((ncoef(p) + 63) / 64)), 0, st>>>(p, ncs, fpm, b0, T.box_i, T.box_r, P.box_oct, oct, L);
             FB_HIP(hipGetLastError());
         }
         k_l2p<R, STOKES><<<T.nleaf, 64, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L,
@@ -840,7 +889,7 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
     }
 
     stage_begin(ctx, 0, st, &ev);
-    k_p2p<R, STOKES><<<T.nleaf, 256, 0, st>>>(T.leaves, T.box_i, T.p2p_ptr, T.p2p_src, T.box_r, nt, G.tc, G.tc32,
+    k_p2p<R, STOKES><<<T.nleaf, 64 * P2P_WAVES, 0, st>>>(T.leaves, T.box_i, T.p2p_ptr, T.p2p_src, T.box_r, nt, G.tc, G.tc32,
                                               src, ctx->y_near);
     FB_HIP(hipGetLastError());
     // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
@@ -867,10 +916,10 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
     stage_begin(ctx, 4, st, &ev);
     const double pref = stokes ? -1.0 / (8.0 * M_PI * ctx->prm.mu) : 1.0 / (4.0 * M_PI);
     if (stokes)
-        k_combine<true><<<grid_for(ctx->nt, 256), 256, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col,
+        k_combine<true><<<grid_for(ctx->nt, 64), 64, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col_orig,
                                                                 ctx->corr.val, x, ctx->y_near, ctx->y_far, pref, y);
     else
-        k_combine<false><<<grid_for(ctx->nt, 256), 256, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col,
+        k_combine<false><<<grid_for(ctx->nt, 64), 64, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col_orig,
                                                                  ctx->corr.val, x, ctx->y_near, ctx->y_far, pref, y);
     FB_HIP(hipGetLastError());
     stage_end(ctx, 4, st, ev);

@@ -50,6 +50,113 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_multidot(int64_t n, const double 
     }
 }
 
+// part[j][b] as above; the last block to finish column j (atomic ticket)
+// sums part[j][0..nb) in block order into out[j] and re-arms the ticket.
+__global__ __launch_bounds__(DOT_BLOCK) void k_multidot_fused(int64_t n, const double *__restrict__ V, int64_t ldv,
+                                                               const double *__restrict__ w, double *__restrict__ part,
+                                                               int nb, double *__restrict__ out,
+                                                               unsigned int *__restrict__ ticket)
+{
+    __shared__ double sh[DOT_BLOCK / 64];
+    __shared__ bool last;
+    const int b = blockIdx.x, j = blockIdx.y;
+    const double *v = V + (int64_t)j * ldv;
+    double s = 0.0;
+    const int64_t base = (int64_t)b * DOT_BLOCK * DOT_PER_THREAD;
+    for (int k = 0; k < DOT_PER_THREAD; ++k) {
+        int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
+        if (i < n)
+            s += v[i] * w[i];
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < DOT_BLOCK / 64; ++k)
+            t += sh[k];
+        part[(int64_t)j * nb + b] = t;
+        __threadfence();
+        last = atomicAdd(&ticket[j], 1u) == (unsigned)(nb - 1);
+    }
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nb; k += DOT_BLOCK)
+        t += __builtin_nontemporal_load(&part[(int64_t)j * nb + k]);
+    for (int off = 32; off > 0; off >>= 1)
+        t += __shfl_down(t, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int k = 0; k < DOT_BLOCK / 64; ++k)
+            r += sh[k];
+        out[j] = r;
+        ticket[j] = 0u;
+    }
+}
+
+// w -= sum_{j<nv} h[j] V_j, and |w|^2 into *nrm2 (same last-block scheme)
+__global__ __launch_bounds__(DOT_BLOCK) void k_update_norm(int64_t n, const double *__restrict__ V, int64_t ldv,
+                                                            int nv, const double *__restrict__ h,
+                                                            double *__restrict__ w, double *__restrict__ part, int nb,
+                                                            double *__restrict__ nrm2, unsigned int *__restrict__ ticket)
+{
+    __shared__ double sh[DOT_BLOCK / 64];
+    __shared__ bool last;
+    const int b = blockIdx.x;
+    double s = 0.0;
+    const int64_t base = (int64_t)b * DOT_BLOCK * DOT_PER_THREAD;
+    for (int k = 0; k < DOT_PER_THREAD; ++k) {
+        int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
+        if (i < n) {
+            double x = w[i];
+            for (int j = 0; j < nv; ++j)
+                x -= h[j] * V[(int64_t)j * ldv + i];
+            w[i] = x;
+            s += x * x;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < DOT_BLOCK / 64; ++k)
+            t += sh[k];
+        part[b] = t;
+        __threadfence();
+        last = atomicAdd(ticket, 1u) == (unsigned)(nb - 1);
+    }
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nb; k += DOT_BLOCK)
+        t += __builtin_nontemporal_load(&part[k]);
+    for (int off = 32; off > 0; off >>= 1)
+        t += __shfl_down(t, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int k = 0; k < DOT_BLOCK / 64; ++k)
+            r += sh[k];
+        *nrm2 = r;
+        *ticket = 0u;
+    }
+}
+
 // out[j] = sum_b part[j][b] in block order (one block per j)
 __global__ void k_reduce_parts(const double *__restrict__ part, int nb, double *__restrict__ out)
 {
@@ -133,6 +240,8 @@ KrylovWork *get_work(fmmbem_ctx *ctx, int m)
         kw->part = kw->arena.alloc<double>((size_t)(m + 2) * kw->nb);
         kw->h = kw->arena.alloc<double>(2 * (size_t)(m + 2));
         kw->y = kw->arena.alloc<double>(m + 1);
+        kw->ticket = kw->arena.alloc<unsigned int>(m + 2);
+        FB_HIP(hipMemset(kw->ticket, 0, sizeof(unsigned int) * (m + 2)));
     } catch (...) {
         kw->arena.release();
         delete kw;
@@ -146,9 +255,7 @@ KrylovWork *get_work(fmmbem_ctx *ctx, int m)
 void multidot(KrylovWork *kw, const double *V, int nv, const double *w, double *out, hipStream_t st)
 {
     dim3 grid(kw->nb, nv);
-    k_multidot<<<grid, DOT_BLOCK, 0, st>>>(kw->n, V, kw->n, w, kw->part, kw->nb);
-    FB_HIP(hipGetLastError());
-    k_reduce_parts<<<nv, 256, 0, st>>>(kw->part, kw->nb, out);
+    k_multidot_fused<<<grid, DOT_BLOCK, 0, st>>>(kw->n, V, kw->n, w, kw->part, kw->nb, out, kw->ticket);
     FB_HIP(hipGetLastError());
 }
 
@@ -255,12 +362,12 @@ void GmresState::enqueue_step()
     run_matvec(ctx, cur.p, cur.prec, vk, kw->w, st);
     ++matvecs;
     multidot(kw, kw->V, k + 1, kw->w, kw->h, st);
-    k_update<<<grid_for(n, 256), 256, 0, st>>>(n, kw->V, n, k + 1, kw->h, kw->w);
+    k_update<<<grid_for(n, DOT_BLOCK), DOT_BLOCK, 0, st>>>(n, kw->V, n, k + 1, kw->h, kw->w);
     FB_HIP(hipGetLastError());
     multidot(kw, kw->V, k + 1, kw->w, kw->h + (m + 2), st);
-    k_update<<<grid_for(n, 256), 256, 0, st>>>(n, kw->V, n, k + 1, kw->h + (m + 2), kw->w);
+    k_update_norm<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->V, n, k + 1, kw->h + (m + 2), kw->w, kw->part, kw->nb,
+                                                kw->h + (k + 1), kw->ticket + (m + 1));
     FB_HIP(hipGetLastError());
-    multidot(kw, kw->w, 1, kw->w, kw->h + (k + 1), st);
     k_normalize<<<grid_for(n, 256), 256, 0, st>>>(n, kw->w, kw->h + (k + 1), vn);
     FB_HIP(hipGetLastError());
     FB_HIP(hipMemcpyAsync(hbuf, kw->h, sizeof(double) * (k + 2), hipMemcpyDeviceToHost, st));

@@ -105,7 +105,8 @@ __global__ void k_corr_fill(int64_t nt, const int32_t *__restrict__ panel_leaf, 
                             const double *__restrict__ tc, const double *__restrict__ S,
                             const double *__restrict__ vtx, const double *__restrict__ sp,
                             const int32_t *__restrict__ rowptr, int32_t *__restrict__ col, double *__restrict__ val,
-                            const RuleTables *__restrict__ Rg)
+                            const RuleTables *__restrict__ Rg, const int32_t *__restrict__ perm,
+                            int32_t *__restrict__ col_orig)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nt)
@@ -122,6 +123,7 @@ __global__ void k_corr_fill(int64_t nt, const int32_t *__restrict__ panel_leaf, 
             if (!self && !is_near(tc, S, nt, (int)i, j))
                 continue;
             col[o] = j;
+            col_orig[o] = perm[j];
             const double *v = vtx + 9 * (int64_t)j;
             if (!STOKES) {
                 double acc;
@@ -218,13 +220,14 @@ void build_correction(fmmbem_ctx *ctx, hipStream_t st)
         C.nnz = nnz;
         const bool stokes = ctx->kernel == FMMBEM_STOKES_SL;
         C.col = ctx->arena.alloc<int32_t>(std::max<int64_t>(nnz, 1));
+        C.col_orig = ctx->arena.alloc<int32_t>(std::max<int64_t>(nnz, 1));
         C.val = ctx->arena.alloc<double>(std::max<int64_t>(nnz, 1) * (stokes ? 9 : 1));
         if (stokes)
             k_corr_fill<true><<<grid_for(nt, 64), 64, 0, st>>>(nt, T.panel_leaf, T.p2p_ptr, T.p2p_src, T.box_i, G.tc,
-                                                               G.S, G.vtx, G.sp, C.ptr, C.col, C.val, dR);
+                                                               G.S, G.vtx, G.sp, C.ptr, C.col, C.val, dR, T.perm, C.col_orig);
         else
             k_corr_fill<false><<<grid_for(nt, 64), 64, 0, st>>>(nt, T.panel_leaf, T.p2p_ptr, T.p2p_src, T.box_i, G.tc,
-                                                                G.S, G.vtx, G.sp, C.ptr, C.col, C.val, dR);
+                                                                G.S, G.vtx, G.sp, C.ptr, C.col, C.val, dR, T.perm, C.col_orig);
         FB_HIP(hipGetLastError());
         FB_HIP(hipStreamSynchronize(st));
         tmp.release();

@@ -112,6 +112,55 @@ __global__ void k_translation_tables(int nu, const uint64_t *__restrict__ ukey, 
     }
 }
 
+// octant digit of every box (root: 0)
+__global__ void k_box_octant(int nbox, const int32_t *__restrict__ box_i, const uint64_t *__restrict__ keys,
+                             int8_t *__restrict__ oct)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox)
+        return;
+    const int lv = box_i[6 * b];
+    oct[b] = lv == 0 ? 0 : (int8_t)((keys[box_i[6 * b + 1]] >> (3 * (21 - lv))) & 7u);
+}
+
+// regular tables R_n^m at (+-1/2, +-1/2, +-1/2), one block per octant
+__global__ void k_octant_tables(int p, cplx<double> *__restrict__ t64, cplx<float> *__restrict__ t32)
+{
+    const int o = blockIdx.x;
+    const double x = (o & 4) ? 0.5 : -0.5, y = (o & 2) ? 0.5 : -0.5, z = (o & 1) ? 0.5 : -0.5;
+    const int fp = (p + 1) * (p + 1);
+    for (int m = threadIdx.x; m <= p; m += blockDim.x) {
+        const double r2 = x * x + y * y + z * z;
+        double dre = 1.0, dim = 0.0;
+        for (int k = 1; k <= m; ++k) {
+            double f = -1.0 / (2.0 * k);
+            double a = f * (x * dre - y * dim), b = f * (x * dim + y * dre);
+            dre = a;
+            dim = b;
+        }
+        double cr = dre, ci = dim, pr = 0.0, pi = 0.0;
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        for (int n = m; n <= p; ++n) {
+            if (n > m) {
+                double f = 1.0 / (double)((n - m) * (n + m));
+                double a = (2.0 * n - 1.0) * z;
+                double nr = (a * cr - r2 * pr) * f, ni = (a * ci - r2 * pi) * f;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+            }
+            const int i1 = o * fp + full_index(n, m), i2 = o * fp + full_index(n, -m);
+            t64[i1] = cplx<double>{cr, ci};
+            t32[i1] = cplx<float>{(float)cr, (float)ci};
+            if (m > 0) {
+                t64[i2] = cplx<double>{sg * cr, -sg * ci};
+                t32[i2] = cplx<float>{(float)(sg * cr), (float)(-sg * ci)};
+            }
+        }
+    }
+}
+
 }  // namespace
 
 void build_translations(fmmbem_ctx *ctx, hipStream_t st)
@@ -120,6 +169,16 @@ void build_translations(fmmbem_ctx *ctx, hipStream_t st)
     M2LPlan &P = ctx->m2l;
     const int64_t n = T.n_m2l;
     P.q = 2 * ctx->prm.p_max;
+    {
+        const int pm = ctx->prm.p_max, fp = (pm + 1) * (pm + 1);
+        P.box_oct = ctx->arena.alloc<int8_t>(T.nbox);
+        P.oct64 = ctx->arena.alloc<cplx<double>>(8 * fp);
+        P.oct32 = ctx->arena.alloc<cplx<float>>(8 * fp);
+        k_box_octant<<<grid_for(T.nbox, 256), 256, 0, st>>>(T.nbox, T.box_i, T.keys, P.box_oct);
+        FB_HIP(hipGetLastError());
+        k_octant_tables<<<8, 64, 0, st>>>(pm, P.oct64, P.oct32);
+        FB_HIP(hipGetLastError());
+    }
     if (n == 0)
         return;
     DevArena tmp;
