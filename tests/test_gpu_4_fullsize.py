@@ -1,0 +1,177 @@
+"""Full-size workloads on the GPU, checked row by row against the oracle.
+
+At these sizes the oracle cannot solve, but it can evaluate single rows of the
+dense operator.  Each test solves on the GPU and then recomputes, with the
+oracle, the residual b_i - (A x)_i on a seeded sample of rows: its size
+relative to b must match the solver's relative-residual target.  The FMM
+product itself is compared on the same rows.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as syn
+from gpu_util import announce, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def sampled_rows(n_panels, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n_panels, k, replace=False))
+
+
+def rows_of(vec, rows, kernel):
+    if kernel == 0:
+        return vec[rows]
+    return vec.reshape(-1, 3)[rows].reshape(-1)
+
+
+def check_solution(orc, kernel, m, b, x, rows, mu=1.0):
+    Ax = orc.matvec(kernel, m.xyz, m.tri, x, mu=mu, rows=rows)
+    r = rows_of(b, rows, kernel) - Ax
+    rel = np.linalg.norm(r) / np.linalg.norm(rows_of(b, rows, kernel))
+    return rel
+
+
+def matvec(fb, ctx, p, prec, x):
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    fb.fmmbem_matvec(ctx, p, prec, xd, yd)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+def test_laplace_sphere_32768(orc):
+    from paper_1506_05957_amd import fmmbem as fb
+    announce("full size: Laplace sphere 32768, Y_l^m, relaxed 12 -> 3 mixed")
+    m = syn.sphere(6)
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE, fb.params(ncrit=64, p_max=12))
+    rows = sampled_rows(m.n_panels, 256, 0)
+    x = syn.random_vector(m.n_panels, 3)
+    yr = orc.matvec(orc.LAPLACE, m.xyz, m.tri, x, rows=rows)
+    for p, prec, bar in ((12, fb.FP64, 1e-6), (12, fb.FP32, 1e-5), (6, fb.FP32, 1e-3)):
+        e = np.linalg.norm(matvec(fb, ctx, p, prec, x)[rows] - yr) / np.linalg.norm(yr)
+        announce(f"  mat-vec p={p} prec={prec}: sampled rel err {e:.1e}")
+        assert e <= bar
+    for l, mm in syn.ylm_orders(0):
+        b = syn.ylm_rhs(m, l, mm)
+        bd = to_dev(b)
+        xd = torch.empty_like(bd)
+        rep = fb.fmmbem_solve_ctx(ctx, bd, 1e-6, fb.schedule(fb.LAPLACE), xd)
+        xs = xd.cpu().numpy()
+        rel = check_solution(orc, orc.LAPLACE, m, b, xs, rows)
+        exact = (2 * l + 1) * b
+        eclosed = np.linalg.norm(xs - exact) / np.linalg.norm(exact)
+        announce(f"  Y_{l}^{mm}: it={rep['iterations']} true={rep['rel_res_true']:.1e} sampled={rel:.1e} "
+                 f"closed-form err={eclosed:.1e}")
+        assert rep["converged"] and rep["rel_res_true"] <= 1.5e-6
+        assert rel <= 5e-6
+        assert eclosed <= 1e-2
+    fb.fmmbem_destroy(ctx)
+
+
+def test_stokes_sphere_8192_drag(orc):
+    from paper_1506_05957_amd import fmmbem as fb
+    announce("full size: Stokes sphere 8192, relaxed 16 -> 4 mixed vs fixed 16")
+    m = syn.sphere(5)
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=64, p_max=16))
+    u = np.tile([1.0, 0.0, 0.0], m.n_panels)
+    ud = to_dev(u)
+    rows = sampled_rows(m.n_panels, 128, 1)
+    res = {}
+    for name, sched in (("fixed", fb.schedule(fb.STOKES, rule=fb.FIXED, p_min=16, mixed=0)),
+                        ("relaxed", fb.schedule(fb.STOKES))):
+        xd = torch.empty_like(ud)
+        rep = fb.fmmbem_solve_ctx(ctx, ud, 1e-6, sched, xd)
+        t = xd.cpu().numpy()
+        F, _ = orc.force_torque(m.xyz, m.tri, t)
+        rel = check_solution(orc, orc.STOKES, m, u, t, rows)
+        announce(f"  {name}: it={rep['iterations']} true={rep['rel_res_true']:.1e} sampled={rel:.1e} "
+                 f"F_x={F[0]:.6f} (exact {-6 * np.pi:.6f})")
+        assert rep["converged"] and rel <= 5e-6
+        res[name] = F[0]
+    for v in res.values():
+        assert abs(v + 6 * np.pi) / (6 * np.pi) < 2e-3
+    assert abs(res["fixed"] - res["relaxed"]) / (6 * np.pi) < 1e-5
+    fb.fmmbem_destroy(ctx)
+
+
+def test_stokes_64_cells(orc):
+    from paper_1506_05957_amd import fmmbem as fb
+    announce("full size: 64 red blood cells x 2048 panels (131072 panels, 393216 unknowns)")
+    m = syn.rbc_scene(64, 4, 0)
+    assert m.n_panels == 131072
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=64, p_max=16))
+    st = fb.fmmbem_get_stats(ctx)
+    announce(f"  stats: {st}")
+    u = np.tile([1.0, 0.0, 0.0], m.n_panels)
+    ud = to_dev(u)
+    xd = torch.empty_like(ud)
+    rep = fb.fmmbem_solve_ctx(ctx, ud, 1e-6, fb.schedule(fb.STOKES), xd)
+    t = xd.cpu().numpy()
+    rows = sampled_rows(m.n_panels, 64, 2)
+    rel = check_solution(orc, orc.STOKES, m, u, t, rows)
+    announce(f"  relaxed: it={rep['iterations']} restarts={rep['restarts']} true={rep['rel_res_true']:.1e} "
+             f"sampled={rel:.1e} t={rep['t_solve_s']:.2f}s p={[int(v) for v in rep['p_hist']]}")
+    assert rep["converged"] and rep["rel_res_true"] <= 1.5e-6
+    assert rel <= 1e-5
+    # every cell drags along the flow with a force of the single-cell size
+    _, S, _ = orc.panels(m.xyz, m.tri)
+    tt = t.reshape(64, -1, 3)
+    F = np.einsum("cpa,cp->ca", tt, S.reshape(64, -1))
+    assert np.all(F[:, 0] < 0)
+    fb.fmmbem_destroy(ctx)
+
+
+def test_serving_alone_equals_in_the_mix(orc):
+    from paper_1506_05957_amd import fmmbem as fb
+    announce("serving: 12 mixed requests, alone vs in the mix")
+    reqs = syn.request_stream(12, 1000.0, 0, levels=(3, 4))
+    inputs = []
+    for r in reqs:
+        m = r.mesh()
+        kernel = fb.LAPLACE if r.kernel == "laplace" else fb.STOKES
+        b = np.ones(m.n_panels) if kernel == fb.LAPLACE else np.tile([1.0, 0.0, 0.0], m.n_panels)
+        inputs.append((m, kernel, b))
+    alone = []
+    for m, kernel, b in inputs:
+        ctx = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(p_max=16))
+        bd = to_dev(b)
+        xd = torch.empty_like(bd)
+        fb.fmmbem_solve_ctx(ctx, bd, 1e-6, fb.schedule(kernel), xd)
+        alone.append(xd.cpu().numpy())
+        fb.fmmbem_destroy(ctx)
+    for budget, max_active in ((8 << 30, 16), (96 << 20, 16), (8 << 30, 1)):
+        srv = fb.fmmbem_server_create(hbm_budget_bytes=budget, max_active=max_active, n_streams=4)
+        tickets = [fb.fmmbem_submit(srv, m.xyz, m.tri, b, kernel, 1e-6, fb.schedule(kernel))
+                   for m, kernel, b in inputs]
+        infos = []
+        for tk, (m, kernel, b), xa in zip(tickets, inputs, alone):
+            x, info = fb.fmmbem_wait(srv, tk, b.shape[0])
+            infos.append(info)
+            assert info["status"] == fb.OK and info["converged"]
+            assert np.array_equal(x, xa), np.max(np.abs(x - xa))
+        fb.fmmbem_server_destroy(srv)
+        lat = np.array([i["finish_s"] - i["arrival_s"] for i in infos])
+        announce(f"  budget={budget >> 20} MiB max_active={max_active}: latency p50={np.median(lat) * 1e3:.1f} ms "
+                 f"max={lat.max() * 1e3:.1f} ms")
+
+
+def test_serving_errors():
+    from paper_1506_05957_amd import fmmbem as fb
+    srv = fb.fmmbem_server_create(hbm_budget_bytes=1 << 30, max_active=2, n_streams=2)
+    m = syn.sphere(2)
+    # a zero-area triangle makes the request fail with EINVAL; others are unaffected
+    bad = m.xyz.copy()
+    tri = m.tri.copy()
+    tri[0] = [tri[0][0], tri[0][0], tri[0][1]]
+    t_bad = fb.fmmbem_submit(srv, bad, tri, np.ones(m.n_panels), fb.LAPLACE, 1e-6, fb.schedule(fb.LAPLACE))
+    t_ok = fb.fmmbem_submit(srv, m.xyz, m.tri, np.ones(m.n_panels), fb.LAPLACE, 1e-6, fb.schedule(fb.LAPLACE))
+    with pytest.raises(fb.FmmbemError) as e:
+        fb.fmmbem_wait(srv, t_bad, m.n_panels)
+    assert e.value.code == fb.EINVAL
+    x, info = fb.fmmbem_wait(srv, t_ok, m.n_panels)
+    assert info["converged"]
+    with pytest.raises(fb.FmmbemError):
+        fb.fmmbem_poll(srv, 12345)
+    fb.fmmbem_server_destroy(srv)
