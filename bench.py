@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--level", type=int, default=6, help="sphere refinement: 8*4^level panels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (3 times), to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
@@ -50,6 +52,15 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": a.numel() * 8, "launches": 3}))
+        return
 
     import synthetic as syn
     from paper_1506_05957_amd import fmmbem as fb
@@ -132,17 +143,20 @@ def main():
           "p6_fp32": matvec_rate(6, fb.FP32), "p3_fp32": matvec_rate(3, fb.FP32)}
 
     # ---- roofline of the dominant kernel stage in the timed region
-    dom = max(("p2p", "m2l"), key=lambda s: stage[s][0])
+    dom = max(("p2p_fp32", "p2p_fp64", "m2l_fp32", "m2l_fp64"), key=lambda s: stage[s][0])
     t_ms, launches, flops = stage[dom]
     avg_s = t_ms / 1e3 / max(launches, 1)
     achieved = flops / max(launches, 1) / avg_s
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+    peak = PEAK_FP32_VALU if dom.endswith("fp32") else PEAK_FP64_VALU
+    kname = {"p2p_fp32": "k_p2p<float, false>", "p2p_fp64": "k_p2p<double, false>",
+             "m2l_fp32": "k_m2l_group<float, 1, 4> + k_m2l_reduce<float, 1>",
+             "m2l_fp64": "k_m2l_group<double, 1, 4> + k_m2l_reduce<double, 1>"}[dom]
+    roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                 "avg_launch_us": avg_s * 1e6, "launches": launches,
-                "flops_per_launch": flops / max(launches, 1),
-                "note": "mixed FP32/FP64 launches; peak is the FP32 vector peak"}
+                "flops_per_launch": flops / max(launches, 1)}
 
-    stage_split = {k: {"ms": v[0], "launches": v[1]} for k, v in stage.items()}
+    stage_split = {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in stage.items() if v[1]}
 
     # ---- CPU oracle on a bounded sample
     cpu = None

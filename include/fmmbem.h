@@ -156,13 +156,15 @@ void fmmbem_destroy(fmmbem_ctx_t *ctx);
 const char *fmmbem_last_error(void);
 
 /* Per-stage device time, accumulated with HIP events recorded on the stream
- * each kernel is launched on, while timing is enabled.  Stages: 0 P2P,
- * 1 M2L, 2 P2M+M2M, 3 L2L+L2P, 4 charges + correction + combine.  t_ms[s] is
- * the total time, launches[s] the number of timed launches and flops[s] the
- * algorithmic flops of those launches: P2P counts 12 (Laplace) or 30 (Stokes)
- * per source-target pair, M2L 4 (p+1)^3 (p+2) per box pair and channel; the
- * other stages count 0.  Any output pointer may be NULL. */
-#define FMMBEM_N_STAGES 5
+ * each kernel is launched on, while timing is enabled.  Stages: 0 P2P (one
+ * kernel), 1 M2L (two kernels), 2 P2M+M2M, 3 L2L+L2P, 4 charges + correction
+ * + combine; entry [prec * 5 + stage] holds the launches made in precision
+ * prec (FMMBEM_FP64 = 0, FMMBEM_FP32 = 1), FMMBEM_N_STAGES entries in all.
+ * t_ms[i] is the total time, launches[i] the number of timed launches and
+ * flops[i] the algorithmic flops of those launches: P2P counts 12 (Laplace) or
+ * 30 (Stokes) per source-target pair, M2L 4 (p+1)^3 (p+2) per box pair and
+ * channel; the other stages count 0.  Any output pointer may be NULL. */
+#define FMMBEM_N_STAGES 10
 int fmmbem_set_timing(fmmbem_ctx_t *ctx, int enabled);
 int fmmbem_get_timing(fmmbem_ctx_t *ctx, double *t_ms, int64_t *launches, double *flops, int reset);
 

@@ -82,6 +82,15 @@ struct Tree {
     int32_t *m2l_ptr = nullptr, *m2l_src = nullptr;  // CSR over all boxes
     int32_t *p2p_ptr = nullptr, *p2p_src = nullptr;  // CSR over all boxes (non-leaves empty)
     int32_t *m2l_pairs = nullptr, *p2p_pairs = nullptr;  // [n][2] sorted (target, source)
+    // P2P target groups: consecutive leaves (Morton order) packed into one
+    // 64-lane wave, with the union of their source leaves and, per source
+    // leaf, a bit mask of the members whose list holds it
+    int32_t n_grp = 0;
+    int32_t *grp_info = nullptr;    // [n_grp][8]: tb, te, nmem, mem_end[4] (panel index), ref leaf
+    int32_t *grp_src_ptr = nullptr; // [n_grp + 1]
+    int32_t *grp_src = nullptr;     // [nnz] source leaf
+    int32_t *grp_src_mask = nullptr;// [nnz] member bits
+    float *tcg32 = nullptr;         // [3][nt] target - group reference leaf centre (FP32)
     // host copies of small metadata
     std::vector<int32_t> h_box_i;
     std::vector<double> h_box_r;

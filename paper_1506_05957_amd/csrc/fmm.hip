@@ -700,26 +700,34 @@ __device__ __forceinline__ void p2p_leaf(int k0, int k1, int i, R px, R py, R pz
 }
 
 template <typename R, bool STOKES>
-__global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(const int32_t *__restrict__ leaves,
+__global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int ngrp, int per_xcd, const int32_t *__restrict__ ginfo,
+                                                        const int32_t *__restrict__ gptr,
+                                                        const int32_t *__restrict__ gsrc,
+                                                        const int32_t *__restrict__ gmask,
                                                         const int32_t *__restrict__ box_i,
-                                                        const int32_t *__restrict__ ptr,
-                                                        const int32_t *__restrict__ srcs,
                                                         const double *__restrict__ box_r, int64_t nt,
-                                                        const double *__restrict__ tc, const float *__restrict__ tc32,
+                                                        const double *__restrict__ tc, const float *__restrict__ tcg32,
                                                         const Src<R, STOKES> *__restrict__ src,
                                                         double *__restrict__ ynear)
 {
     constexpr int NQ = STOKES ? 3 : 1;
     __shared__ R red[P2P_WAVES][NQ][64];
-    const int b = leaves[blockIdx.x];
-    const int tb = box_i[6 * b + 1], te = box_i[6 * b + 2];
+    // blocks are dealt to the 8 XCDs round robin; give each XCD a contiguous
+    // run of groups so that neighbouring groups share its L2
+    const int g = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (g >= ngrp)
+        return;
+    const int32_t *gi = ginfo + 8 * (int64_t)g;
+    const int tb = gi[0], te = gi[1];
+    const int me0 = gi[3], me1 = gi[4], me2 = gi[5];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int e0 = ptr[b], e1 = ptr[b + 1];
-    const double *cT = box_r + 5 * (int64_t)b;
+    const int e0 = gptr[g], e1 = gptr[g + 1];
+    const double *cG = box_r + 5 * (int64_t)gi[7];
     for (int t0 = tb; t0 < te; t0 += 64) {
         const int i = t0 + lane;
         const bool active = i < te;
+        const int gm = (i >= me0) + (i >= me1) + (i >= me2);  // member holding target i
         R tx = 0, ty = 0, tz = 0;
         if (active) {
             if constexpr (sizeof(R) == 8) {
@@ -727,9 +735,9 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(const int32_t *__restric
                 ty = tc[nt + i];
                 tz = tc[2 * nt + i];
             } else {
-                tx = tc32[i];
-                ty = tc32[nt + i];
-                tz = tc32[2 * nt + i];
+                tx = tcg32[i];
+                ty = tcg32[nt + i];
+                tz = tcg32[2 * nt + i];
             }
         }
         R acc[NQ];
@@ -737,19 +745,22 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(const int32_t *__restric
         for (int a = 0; a < NQ; ++a)
             acc[a] = 0;
         for (int e = e0 + w; e < e1; e += P2P_WAVES) {
-            const int sb = srcs[e];
-            const int k0 = 4 * box_i[6 * sb + 1], k1 = 4 * box_i[6 * sb + 2];
+            const int sb = gsrc[e];
+            const int mask = gmask[e];
+            const int s0 = box_i[6 * sb + 1], s1 = box_i[6 * sb + 2];
             R px = tx, py = ty, pz = tz;
             if constexpr (sizeof(R) == 4) {
                 const double *cS = box_r + 5 * (int64_t)sb;
-                px += (float)(cT[0] - cS[0]);
-                py += (float)(cT[1] - cS[1]);
-                pz += (float)(cT[2] - cS[2]);
+                px += (float)(cG[0] - cS[0]);
+                py += (float)(cG[1] - cS[1]);
+                pz += (float)(cG[2] - cS[2]);
             }
-            if (sb == b)
-                p2p_leaf<R, STOKES, true>(k0, k1, i, px, py, pz, src, acc);
-            else
-                p2p_leaf<R, STOKES, false>(k0, k1, i, px, py, pz, src, acc);
+            if (active && ((mask >> gm) & 1)) {
+                if (s0 >= tb && s0 < te)  // a member leaf: skip each target's own panel
+                    p2p_leaf<R, STOKES, true>(4 * s0, 4 * s1, i, px, py, pz, src, acc);
+                else
+                    p2p_leaf<R, STOKES, false>(4 * s0, 4 * s1, i, px, py, pz, src, acc);
+            }
         }
 #pragma unroll
         for (int a = 0; a < NQ; ++a)
@@ -806,6 +817,7 @@ template <typename R, int NCH>
 void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
 {
     constexpr bool STOKES = NCH == 4;
+    constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
     Tree &T = ctx->tree;
     Geometry &G = ctx->geo;
     const int64_t nt = ctx->nt, ns = ctx->nsrc;
@@ -816,13 +828,13 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
     cplx<R> *L = static_cast<cplx<R> *>(ctx->L);
     hipEvent_t ev;
 
-    stage_begin(ctx, 4, st, &ev);
+    stage_begin(ctx, SO + 4, st, &ev);
     k_charges<R, STOKES><<<grid_for(ns, 256), 256, 0, st>>>(nt, T.perm, G.sp, G.sp32, x, src);
     FB_HIP(hipGetLastError());
-    stage_end(ctx, 4, st, ev);
+    stage_end(ctx, SO + 4, st, ev);
 
     if (T.n_m2l > 0) {
-        stage_begin(ctx, 2, st, &ev);
+        stage_begin(ctx, SO + 2, st, &ev);
         {
             const int nsl = 256 / (p + 1);
             const size_t shm = sizeof(cplx<R>) * (size_t)nsl * ncoef(p);
@@ -852,9 +864,9 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
             k_m2m<R, NCH><<<nb, 256, shm, st>>>(p, ncs, fpm, b0, T.box_i, T.box_r, P.box_oct, oct, M);
             FB_HIP(hipGetLastError());
         }
-        stage_end(ctx, 2, st, ev);
+        stage_end(ctx, SO + 2, st, ev);
 
-        stage_begin(ctx, 1, st, &ev);
+        stage_begin(ctx, SO + 1, st, &ev);
         {
             constexpr int PB = NCH == 1 ? 4 : 1;
             const int threads = 256;
@@ -872,9 +884,9 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
             k_m2l_reduce<R, NCH><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, Y, L);
             FB_HIP(hipGetLastError());
         }
-        stage_end(ctx, 1, st, ev, 4.0 * (p + 1) * (p + 1) * (p + 1) * (p + 2) * NCH * (double)T.n_m2l);
+        stage_end(ctx, SO + 1, st, ev, 4.0 * (p + 1) * (p + 1) * (p + 1) * (p + 2) * NCH * (double)T.n_m2l);
 
-        stage_begin(ctx, 3, st, &ev);
+        stage_begin(ctx, SO + 3, st, &ev);
         for (int l = 1; l < T.nlevels; ++l) {
             int b0 = T.level_begin[l], nb = T.level_begin[l + 1] - b0;
             k_l2l<R, NCH><<<nb, std::min(256, 64 * ((ncoef(p) + 63) / 64)), 0, st>>>(p, ncs, fpm, b0, T.box_i, T.box_r, P.box_oct, oct, L);
@@ -883,17 +895,21 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
         k_l2p<R, STOKES><<<T.nleaf, 64, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L,
                                                  ctx->y_far);
         FB_HIP(hipGetLastError());
-        stage_end(ctx, 3, st, ev);
+        stage_end(ctx, SO + 3, st, ev);
     } else {
         FB_HIP(hipMemsetAsync(ctx->y_far, 0, sizeof(double) * ctx->n, st));
     }
 
-    stage_begin(ctx, 0, st, &ev);
-    k_p2p<R, STOKES><<<T.nleaf, 64 * P2P_WAVES, 0, st>>>(T.leaves, T.box_i, T.p2p_ptr, T.p2p_src, T.box_r, nt, G.tc, G.tc32,
-                                              src, ctx->y_near);
+    stage_begin(ctx, SO + 0, st, &ev);
+    {
+        const int per_xcd = (T.n_grp + 7) / 8;
+        k_p2p<R, STOKES><<<8 * per_xcd, 64 * P2P_WAVES, 0, st>>>(T.n_grp, per_xcd, T.grp_info, T.grp_src_ptr,
+                                                                T.grp_src, T.grp_src_mask, T.box_i, T.box_r, nt,
+                                                                G.tc, T.tcg32, src, ctx->y_near);
+    }
     FB_HIP(hipGetLastError());
     // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
-    stage_end(ctx, 0, st, ev, (STOKES ? 30.0 : 12.0) * (double)(T.p2p_interactions - 4 * nt));
+    stage_end(ctx, SO + 0, st, ev, (STOKES ? 30.0 : 12.0) * (double)(T.p2p_interactions - 4 * nt));
 }
 
 }  // namespace
@@ -913,7 +929,8 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
             launch_fmm<float, 1>(ctx, p, x, st);
     }
     hipEvent_t ev;
-    stage_begin(ctx, 4, st, &ev);
+    const int SO = prec == FMMBEM_FP64 ? 0 : 5;
+    stage_begin(ctx, SO + 4, st, &ev);
     const double pref = stokes ? -1.0 / (8.0 * M_PI * ctx->prm.mu) : 1.0 / (4.0 * M_PI);
     if (stokes)
         k_combine<true><<<grid_for(ctx->nt, 64), 64, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col_orig,
@@ -922,7 +939,7 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
         k_combine<false><<<grid_for(ctx->nt, 64), 64, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col_orig,
                                                                  ctx->corr.val, x, ctx->y_near, ctx->y_far, pref, y);
     FB_HIP(hipGetLastError());
-    stage_end(ctx, 4, st, ev);
+    stage_end(ctx, SO + 4, st, ev);
 }
 
 }  // namespace fmmbem

@@ -383,6 +383,89 @@ template <typename T> void exclusive_scan(const T *in, T *out, int64_t n, hipStr
     FB_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, st));
 }
 
+// target coordinates relative to the reference leaf centre of their P2P group
+__global__ void k_group_relative(int ngrp, const int32_t *__restrict__ ginfo, const double *__restrict__ box_r,
+                                 const double *__restrict__ tc, int64_t nt, float *__restrict__ tcg32)
+{
+    const int g = blockIdx.x;
+    if (g >= ngrp)
+        return;
+    const int32_t *gi = ginfo + 8 * (int64_t)g;
+    const double *c = box_r + 5 * (int64_t)gi[7];
+    for (int i = gi[0] + threadIdx.x; i < gi[1]; i += blockDim.x)
+        for (int d = 0; d < 3; ++d)
+            tcg32[d * nt + i] = (float)(tc[d * nt + i] - c[d]);
+}
+
+// Consecutive leaves in Morton (panel) order are packed while they fit one
+// wave (<= 64 targets, <= 4 leaves); a leaf with more than 64 targets is a
+// group of its own.  For every group: the sorted union of its members' P2P
+// source leaves, each with the bit mask of the members that list it.
+void build_p2p_groups(fmmbem_ctx *ctx, const std::vector<int32_t> &hp, int64_t n_p2p, hipStream_t st)
+{
+    Tree &T = ctx->tree;
+    const std::vector<int32_t> &hb = T.h_box_i;
+    std::vector<int32_t> leaves = T.h_leaves;
+    std::sort(leaves.begin(), leaves.end(), [&](int a, int b) { return hb[6 * a + 1] < hb[6 * b + 1]; });
+    // per-leaf source lists (hp is sorted by target)
+    std::vector<int64_t> first(T.nbox + 1, 0);
+    for (int64_t i = 0; i < n_p2p; ++i)
+        first[hp[2 * i] + 1]++;
+    for (int b = 0; b < T.nbox; ++b)
+        first[b + 1] += first[b];
+    std::vector<int32_t> info, sptr(1, 0), src, mask;
+    size_t i = 0;
+    while (i < leaves.size()) {
+        std::vector<int> mem{leaves[i]};
+        int nt_g = hb[6 * leaves[i] + 2] - hb[6 * leaves[i] + 1];
+        size_t j = i + 1;
+        while (nt_g <= 64 && j < leaves.size() && mem.size() < 4) {
+            int c = hb[6 * leaves[j] + 2] - hb[6 * leaves[j] + 1];
+            if (nt_g + c > 64 || hb[6 * leaves[j] + 1] != hb[6 * mem.back() + 2])
+                break;
+            mem.push_back(leaves[j]);
+            nt_g += c;
+            ++j;
+        }
+        int32_t gi[8] = {hb[6 * mem[0] + 1], hb[6 * mem.back() + 2], (int32_t)mem.size(), 0, 0, 0, 0, mem[0]};
+        for (size_t k = 0; k < 4; ++k)
+            gi[3 + k] = k < mem.size() ? hb[6 * mem[k] + 2] : gi[1];
+        info.insert(info.end(), gi, gi + 8);
+        std::vector<std::pair<int32_t, int32_t>> u;
+        for (size_t k = 0; k < mem.size(); ++k)
+            for (int64_t e = first[mem[k]]; e < first[mem[k] + 1]; ++e)
+                u.push_back({hp[2 * e + 1], 1 << k});
+        std::sort(u.begin(), u.end());
+        for (size_t a = 0; a < u.size();) {
+            int32_t m = 0;
+            size_t b = a;
+            while (b < u.size() && u[b].first == u[a].first)
+                m |= u[b++].second;
+            src.push_back(u[a].first);
+            mask.push_back(m);
+            a = b;
+        }
+        sptr.push_back((int32_t)src.size());
+        i = j;
+    }
+    T.n_grp = (int32_t)(info.size() / 8);
+    DevArena &A = ctx->arena;
+    T.grp_info = A.alloc<int32_t>(info.size());
+    T.grp_src_ptr = A.alloc<int32_t>(sptr.size());
+    T.grp_src = A.alloc<int32_t>(std::max<size_t>(src.size(), 1));
+    T.grp_src_mask = A.alloc<int32_t>(std::max<size_t>(mask.size(), 1));
+    FB_HIP(hipMemcpyAsync(T.grp_info, info.data(), sizeof(int32_t) * info.size(), hipMemcpyHostToDevice, st));
+    FB_HIP(hipMemcpyAsync(T.grp_src_ptr, sptr.data(), sizeof(int32_t) * sptr.size(), hipMemcpyHostToDevice, st));
+    if (!src.empty()) {
+        FB_HIP(hipMemcpyAsync(T.grp_src, src.data(), sizeof(int32_t) * src.size(), hipMemcpyHostToDevice, st));
+        FB_HIP(hipMemcpyAsync(T.grp_src_mask, mask.data(), sizeof(int32_t) * mask.size(), hipMemcpyHostToDevice, st));
+    }
+    T.tcg32 = A.alloc<float>(3 * T.nt);
+    k_group_relative<<<T.n_grp, 64, 0, st>>>(T.n_grp, T.grp_info, T.box_r, ctx->geo.tc, T.nt, T.tcg32);
+    FB_HIP(hipGetLastError());
+    FB_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
+}
+
 }  // namespace
 
 void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream_t st)
@@ -617,6 +700,7 @@ void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream
             int a = hp[2 * i], b = hp[2 * i + 1];
             T.p2p_interactions += (int64_t)(hb[6 * a + 2] - hb[6 * a + 1]) * 4 * (hb[6 * b + 2] - hb[6 * b + 1]);
         }
+        build_p2p_groups(ctx, hp, n_p2p, st);
         tmp.release();
     } catch (...) {
         (void)hipStreamSynchronize(st);

@@ -24,8 +24,9 @@ LAPLACE, STOKES = 0, 1
 FP64, FP32 = 0, 1
 FIXED, RELAX_SHIFT, RELAX_BF = 0, 1, 2
 P_MAX, P_MAX_FP32 = 20, 14
-N_STAGES = 5
-STAGES = ("p2p", "m2l", "p2m_m2m", "l2l_l2p", "charges_correction")
+N_STAGES = 10
+STAGES = tuple(f"{s}_{pr}" for pr in ("fp64", "fp32")
+               for s in ("p2p", "m2l", "p2m_m2m", "l2l_l2p", "charges_correction"))
 
 c_i32, c_i64, c_d, c_u8, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint8, ctypes.c_void_p
 P = ctypes.POINTER
