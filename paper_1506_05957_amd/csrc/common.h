@@ -39,6 +39,8 @@ __host__ __device__ constexpr inline int cidx(int n, int m) { return n * (n + 1)
 constexpr int P_MAX = FMMBEM_P_MAX;
 constexpr int P_MAX_FP32 = FMMBEM_P_MAX_FP32;
 constexpr int NC_MAX = ncoef(P_MAX);
+// sources per P2P chunk (one LDS tile of a wave)
+constexpr int P2P_TILE = 128;
 
 // Device buffers owned by a context; freed in reverse order on destruction.
 struct DevArena {
@@ -82,15 +84,14 @@ struct Tree {
     int32_t *m2l_ptr = nullptr, *m2l_src = nullptr;  // CSR over all boxes
     int32_t *p2p_ptr = nullptr, *p2p_src = nullptr;  // CSR over all boxes (non-leaves empty)
     int32_t *m2l_pairs = nullptr, *p2p_pairs = nullptr;  // [n][2] sorted (target, source)
-    // P2P target groups: consecutive leaves (Morton order) packed into one
-    // 64-lane wave, with the union of their source leaves and, per source
-    // leaf, a bit mask of the members whose list holds it
-    int32_t n_grp = 0;
-    int32_t *grp_info = nullptr;    // [n_grp][8]: tb, te, nmem, mem_end[4] (panel index), ref leaf
-    int32_t *grp_src_ptr = nullptr; // [n_grp + 1]
-    int32_t *grp_src = nullptr;     // [nnz] source leaf
-    int32_t *grp_src_mask = nullptr;// [nnz] member bits
-    float *tcg32 = nullptr;         // [3][nt] target - group reference leaf centre (FP32)
+    // P2P work units: up to 64 targets of one leaf, with the leaf's P2P
+    // sources as chunks of at most P2P_TILE consecutive sources of one source
+    // leaf, in decreasing size order
+    int32_t n_unit = 0;
+    int64_t n_chunk = 0;
+    int4 *p2p_unit = nullptr;     // [n_unit] first target, end target, first chunk, end chunk
+    int2 *p2p_chunk = nullptr;    // [n_chunk] first source, count | 1 << 16 if it is the target's own leaf
+    float4 *p2p_choff = nullptr;  // [n_chunk] target leaf centre - source leaf centre (FP32), 0
     // host copies of small metadata
     std::vector<int32_t> h_box_i;
     std::vector<double> h_box_r;
@@ -143,6 +144,25 @@ struct M2LPlan {
     int8_t *box_oct = nullptr;          // [nbox] octant of each box in its parent (x<<2 | y<<1 | z)
     cplx<double> *oct64 = nullptr;      // [8][(p_max+1)^2]
     cplx<float> *oct32 = nullptr;
+    // M2M and L2L as real linear maps of the stored coefficients (m >= 0, real
+    // and imaginary parts interleaved): one D x D matrix per octant at p_max,
+    // D = 2 ncoef(p_max), stored input-major ([o][k][r]); order p uses the
+    // leading 2 ncoef(p) block
+    int op_dim = 0;
+    double *m2m64 = nullptr, *l2l64 = nullptr;
+    float *m2m32 = nullptr, *l2l32 = nullptr;
+    // the boxes of each level >= 1 grouped by octant, in tiles of at most
+    // 16 / nch boxes: level l owns tiles [tile_begin[l], tile_begin[l + 1])
+    std::vector<int> tile_begin;
+    int4 *tiles = nullptr;              // octant, first entry of level_list, count, 0
+    int32_t *level_list = nullptr;
+    // boxes with children, by level: level l owns [par_begin[l], par_begin[l + 1])
+    std::vector<int> par_begin;
+    int32_t *parents = nullptr;
+    // coarsest levels holding an M2L source / target: M2M into levels above
+    // the first and L2L out of levels above the second carry nothing
+    int lmin_src = 0, lmin_tgt = 0;
+    void *Z = nullptr;                  // [nbox][nch][ncoef(p_max)] complex FP64: per-child M2M terms
 };
 
 // GMRES workspace, one per context (krylov.hip)

@@ -255,80 +255,114 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// M2M (a6): one block per box of a level; sums its children (written before):
-// M_n^m(P) = sum_C sum_{k,l} conj(R_k^l(delta_C)) 2^-(n-k) M_{n-k}^{m-l}(C), with
-// delta_C = (c_C - c_P) / s_P one of the 8 tabulated octant offsets.
-template <typename R, int NCH>
-__global__ __launch_bounds__(256) void k_m2m(int p, int ncs, int fpm, int box0, const int32_t *__restrict__ box_i,
-                                             const double *__restrict__ box_r, const int8_t *__restrict__ box_oct,
-                                             const cplx<R> *__restrict__ oct_tab, cplx<R> *__restrict__ M)
+// M2M (a6) and L2L (a8) as products with the octant operators: the child C
+// sits at delta = (c_C - c_P) / s_P, one of the 8 offsets (+-1/2, +-1/2, +-1/2),
+// and in the scaled expansions
+//   M2M: M_n^m(P) += sum_{j <= n} 2^-j sum_mm conj(R_{n-j}^{m-mm}(delta)) M_j^mm(C)
+//   L2L: L_j^k(C) += 2^-(j+1) sum_{n >= j} sum_m L_n^m(P) conj(R_{n-j}^{m-k}(delta))
+// are fixed real linear maps of the stored coefficients, one per octant.  A
+// block takes a tile of boxes of one level and one octant (16 columns: boxes
+// x channels): the input coefficients sit in LDS, thread (row, column group)
+// streams its operator row (coalesced over rows) and skips the inputs that the
+// triangular structure zeroes.  M2M writes per-child terms that k_m2m_sum adds
+// up per parent in child order; L2L adds into the child.  Stokes: the fourth
+// channel changes centre with the first three (M2M: + d . Z, L2L: - d . Z,
+// d = c_C - c_P).
+template <typename R, int NCH, bool L2L>
+__global__ __launch_bounds__(256) void k_octant_apply(int p, int ncs, int D, const R *__restrict__ ops,
+                                                      const int4 *__restrict__ tiles, int tile0,
+                                                      const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ box_i,
+                                                      const double *__restrict__ box_r, const cplx<R> *__restrict__ X,
+                                                      cplx<R> *__restrict__ Y)
 {
+    constexpr int NCOL = 16, CW = 8, BPG = CW / NCH;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int P = box0 + blockIdx.x;
-    const int nchild = box_i[6 * P + 5];
-    if (nchild == 0)
-        return;
-    const int nc = ncoef(p);
-    const int nslot = max(1, min(8, (int)blockDim.x / nc));
-    const int slot = threadIdx.x / nc, idx = threadIdx.x - slot * nc;
-    cplx<R> *red = reinterpret_cast<cplx<R> *>(smem_raw);  // [nslot][NCH][nc]
-    const int c0 = box_i[6 * P + 4];
-    const double *cP = box_r + 5 * (int64_t)P;
-    if (slot < nslot) {
+    R *xs = reinterpret_cast<R *>(smem_raw);  // [Dp][NCOL]
+    const int4 tl = tiles[tile0 + blockIdx.x];
+    const int o = tl.x, e0 = tl.y, cnt = tl.z;
+    const int Dp = 2 * ncoef(p);
+    for (int t = threadIdx.x; t < NCOL * Dp; t += blockDim.x) {
+        const int col = t / Dp, k = t - col * Dp;
+        const int b = col / NCH, ch = col - b * NCH;
+        R v = 0;
+        if (b < cnt) {
+            const int box = list[e0 + b];
+            const int from = L2L ? box_i[6 * box + 3] : box;
+            v = reinterpret_cast<const R *>(X + ((int64_t)from * NCH + ch) * ncs)[k];
+        }
+        xs[k * NCOL + col] = v;
+    }
+    __syncthreads();
+    const R *A = ops + (int64_t)o * D * D;
+    for (int task = threadIdx.x; task < Dp * (NCOL / CW); task += blockDim.x) {
+        const int cg = task / Dp, r = task - cg * Dp;
+        if (cg * BPG >= cnt)
+            continue;
         int n, m;
-        idx_to_nm(idx, n, m);
-        R acc_re[NCH], acc_im[NCH];
+        idx_to_nm(r >> 1, n, m);
+        const int k0 = L2L ? 2 * cidx(n, 0) : 0;     // L2L: inputs of degree >= n
+        const int k1 = L2L ? Dp : 2 * ncoef(n);      // M2M: inputs of degree <= n
+        R acc[CW];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-            acc_re[ch] = acc_im[ch] = 0;
-        for (int cc = slot; cc < nchild; cc += nslot) {
-            const int C = c0 + cc;
-            const cplx<R> *Rc = oct_tab + (int64_t)box_oct[C] * fpm;
-            const cplx<R> *MC = M + (int64_t)C * NCH * ncs;
-            R sre[NCH], sim[NCH];
+        for (int q = 0; q < CW; ++q)
+            acc[q] = 0;
+        const R *x = xs + cg * CW;
+#pragma unroll 2
+        for (int k = k0; k < k1; ++k) {
+            const R a = A[(int64_t)k * D + r];
+#pragma unroll
+            for (int q = 0; q < CW; ++q)
+                acc[q] += a * x[k * NCOL + q];
+        }
+#pragma unroll
+        for (int bq = 0; bq < BPG; ++bq) {
+            const int b = cg * BPG + bq;
+            if (b >= cnt)
+                continue;
+            const int box = list[e0 + b];
+            R v[NCH];
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch)
-                sre[ch] = sim[ch] = 0;
-            for (int k = 0; k <= n; ++k) {
-                const int j = n - k;
-                const R sc = (R)ldexp(1.0, -j);
-                const int l0 = max(-k, m - j), l1 = min(k, m + j);
-                for (int l = l0; l <= l1; ++l) {
-                    const cplx<R> rv = Rc[full_idx(k, l)];  // conj applied below
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch) {
-                        const cplx<R> mv = load_full(MC + ch * ncs, j, m - l);
-                        sre[ch] += sc * (rv.re * mv.re + rv.im * mv.im);
-                        sim[ch] += sc * (rv.re * mv.im - rv.im * mv.re);
-                    }
-                }
+                v[ch] = acc[bq * NCH + ch];
+            if constexpr (NCH == 4) {
+                const double *cC = box_r + 5 * (int64_t)box, *cP = box_r + 5 * (int64_t)box_i[6 * box + 3];
+                const R d0 = (R)(cC[0] - cP[0]), d1 = (R)(cC[1] - cP[1]), d2 = (R)(cC[2] - cP[2]);
+                const R dv = d0 * v[0] + d1 * v[1] + d2 * v[2];
+                v[3] = L2L ? v[3] - dv : v[3] + dv;
             }
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
-                acc_re[ch] += sre[ch];
-                acc_im[ch] += sim[ch];
-            }
-            if constexpr (NCH == 4) {
-                const double *cC = box_r + 5 * (int64_t)C;
-                const R d0 = (R)(cC[0] - cP[0]), d1 = (R)(cC[1] - cP[1]), d2 = (R)(cC[2] - cP[2]);
-                acc_re[3] += d0 * sre[0] + d1 * sre[1] + d2 * sre[2];
-                acc_im[3] += d0 * sim[0] + d1 * sim[1] + d2 * sim[2];
+                R *dst = reinterpret_cast<R *>(Y + ((int64_t)box * NCH + ch) * ncs) + r;
+                if constexpr (L2L)
+                    *dst += v[ch];
+                else
+                    *dst = v[ch];
             }
         }
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-            red[(slot * NCH + ch) * nc + idx] = cplx<R>{acc_re[ch], acc_im[ch]};
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < NCH * nc; t += blockDim.x) {
-        R sr = 0, si = 0;
-        for (int sl = 0; sl < nslot; ++sl) {
-            sr += red[sl * NCH * nc + t].re;
-            si += red[sl * NCH * nc + t].im;
-        }
-        const int ch = t / nc, id = t - ch * nc;
-        M[((int64_t)P * NCH + ch) * ncs + id] = cplx<R>{sr, si};
+}
+
+// M_P = sum of the per-child terms Z_C over the children of P, in child order
+template <typename R, int NCH>
+__global__ void k_m2m_sum(int p, int ncs, int npar, const int32_t *__restrict__ parents,
+                          const int32_t *__restrict__ box_i, const cplx<R> *__restrict__ Z, cplx<R> *__restrict__ M)
+{
+    const int nc = ncoef(p);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)npar * NCH * nc)
+        return;
+    const int i = (int)(t / (NCH * nc)), rem = (int)(t - (int64_t)i * NCH * nc);
+    const int ch = rem / nc, c = rem - ch * nc;
+    const int P = parents[i];
+    const int c0 = box_i[6 * P + 4], c1 = c0 + box_i[6 * P + 5];
+    R sr = 0, si = 0;
+    for (int C = c0; C < c1; ++C) {
+        const cplx<R> v = Z[((int64_t)C * NCH + ch) * ncs + c];
+        sr += v.re;
+        si += v.im;
     }
+    M[((int64_t)P * NCH + ch) * ncs + c] = cplx<R>{sr, si};
 }
 
 // ---------------------------------------------------------------------------
@@ -493,55 +527,6 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_
 }
 
 // ---------------------------------------------------------------------------
-// L2L (a8): one block per box of a level >= 1, adds its parent's local expansion:
-// L_j^k(C) += 2^-(j+1) sum_{n >= j, m} L_n^m(P) conj(R_{n-j}^{m-k}(delta_C)).
-template <typename R, int NCH>
-__global__ __launch_bounds__(256) void k_l2l(int p, int ncs, int fpm, int box0, const int32_t *__restrict__ box_i,
-                                             const double *__restrict__ box_r, const int8_t *__restrict__ box_oct,
-                                             const cplx<R> *__restrict__ oct_tab, cplx<R> *__restrict__ L)
-{
-    const int nc = ncoef(p);
-    const int C = box0 + blockIdx.x;
-    const int P = box_i[6 * C + 3];
-    const cplx<R> *Rt = oct_tab + (int64_t)box_oct[C] * fpm;
-    const cplx<R> *LP = L + (int64_t)P * NCH * ncs;
-    const double *cP = box_r + 5 * (int64_t)P, *cC = box_r + 5 * (int64_t)C;
-    for (int idx = threadIdx.x; idx < nc; idx += blockDim.x) {
-        int j, kk;
-        idx_to_nm(idx, j, kk);
-        R sre[NCH], sim[NCH];
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-            sre[ch] = sim[ch] = 0;
-        for (int n = j; n <= p; ++n) {
-            const int a = n - j;
-            const int m0 = max(-n, kk - a), m1 = min(n, kk + a);
-            for (int m = m0; m <= m1; ++m) {
-                const cplx<R> rv = Rt[full_idx(a, m - kk)];  // conj below
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    const cplx<R> lv = load_full(LP + ch * ncs, n, m);
-                    sre[ch] += lv.re * rv.re + lv.im * rv.im;
-                    sim[ch] += lv.im * rv.re - lv.re * rv.im;
-                }
-            }
-        }
-        const R f = (R)ldexp(1.0, -(j + 1));
-        if constexpr (NCH == 4) {
-            const R d0 = (R)(cC[0] - cP[0]), d1 = (R)(cC[1] - cP[1]), d2 = (R)(cC[2] - cP[2]);
-            sre[3] -= d0 * sre[0] + d1 * sre[1] + d2 * sre[2];
-            sim[3] -= d0 * sim[0] + d1 * sim[1] + d2 * sim[2];
-        }
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            cplx<R> &dst = L[((int64_t)C * NCH + ch) * ncs + idx];
-            dst.re += f * sre[ch];
-            dst.im += f * sim[ch];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // L2P (a9): one block per leaf, one thread per target.
 template <typename R, bool STOKES>
 __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__restrict__ leaves,
@@ -657,21 +642,40 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
 }
 
 // ---------------------------------------------------------------------------
-// P2P (a10): one block per target leaf, one target per lane, the NW waves of
-// the block splitting the leaf's source leaves.  Source indices are
-// wave-uniform, so each packed source is fetched once per wave through the
-// scalar cache and feeds 64 targets; the NW partial sums are reduced in a fixed
-// order.  FP32 works in leaf-relative coordinates:
-// r = (t - c_T) + (c_T - c_S) - (y - c_S).
-constexpr int P2P_WAVES = 16;
+// P2P (a10): one block per work unit (at most 64 targets of one leaf).  The
+// NW waves of the block take the unit's source chunks round robin.  With n
+// targets a wave runs P = floor(64 / n) phases: lane (ph, t) sums over the
+// sources ph, ph + P, ... of the chunk, so that a small leaf still fills the
+// wave.  A wave stages its chunk into its own LDS tile phase-major (phase ph's
+// sources contiguous) and pads each phase to the same length with zero-charge
+// sources placed far away, so every lane runs the same trip count; the next
+// chunk is fetched into registers while the current one is evaluated.  The
+// partial sums of the waves and phases are reduced in a fixed order, in FP64.
+// FP32 works in leaf-relative coordinates: r = (t - c_T) + (c_T - c_S) - (y - c_S).
+constexpr int P2P_WAVES = 8;
+
+template <typename R, bool STOKES> __device__ __forceinline__ Src<R, STOKES> far_zero_source()
+{
+    // at 1e18 from every target r^2 ~ 3e36 stays finite in FP32 and the
+    // contribution is an exact zero
+    Src<R, STOKES> v;
+    v.x = v.y = v.z = R(1e18);
+    if constexpr (STOKES) {
+        v.f0 = v.f1 = v.f2 = 0;
+        v.pad0 = v.pad1 = 0;
+    } else {
+        v.q = 0;
+    }
+    return v;
+}
 
 template <typename R, bool STOKES, bool SELF>
-__device__ __forceinline__ void p2p_leaf(int k0, int k1, int i, R px, R py, R pz,
-                                         const Src<R, STOKES> *__restrict__ src, R *acc)
+__device__ __forceinline__ void p2p_phase(const Src<R, STOKES> *__restrict__ row, int nj, int k, int kstep, int i,
+                                          R px, R py, R pz, R *acc)
 {
 #pragma unroll 4
-    for (int k = k0; k < k1; ++k) {
-        const Src<R, STOKES> sv = src[k];
+    for (int j = 0; j < nj; ++j) {
+        const Src<R, STOKES> sv = row[j];
         const R dx = px - sv.x, dy = py - sv.y, dz = pz - sv.z;
         const R r2 = dx * dx + dy * dy + dz * dz;
         R rinv;
@@ -686,8 +690,10 @@ __device__ __forceinline__ void p2p_leaf(int k0, int k1, int i, R px, R py, R pz
         } else {
             rinv = __builtin_amdgcn_rsqf(r2);
         }
-        if constexpr (SELF)
+        if constexpr (SELF) {
             rinv = (k >> 2) == i ? R(0) : rinv;  // the target's own panel: integrated by the correction
+            k += kstep;
+        }
         if constexpr (!STOKES) {
             acc[0] += sv.q * rinv;
         } else {
@@ -700,82 +706,112 @@ __device__ __forceinline__ void p2p_leaf(int k0, int k1, int i, R px, R py, R pz
 }
 
 template <typename R, bool STOKES>
-__global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int ngrp, int per_xcd, const int32_t *__restrict__ ginfo,
-                                                        const int32_t *__restrict__ gptr,
-                                                        const int32_t *__restrict__ gsrc,
-                                                        const int32_t *__restrict__ gmask,
-                                                        const int32_t *__restrict__ box_i,
-                                                        const double *__restrict__ box_r, int64_t nt,
-                                                        const double *__restrict__ tc, const float *__restrict__ tcg32,
+__global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, const int4 *__restrict__ units,
+                                                        const int2 *__restrict__ chunks,
+                                                        const float4 *__restrict__ choff, int64_t nt,
+                                                        const double *__restrict__ tc, const float *__restrict__ tc32,
                                                         const Src<R, STOKES> *__restrict__ src,
                                                         double *__restrict__ ynear)
 {
+    static_assert(P2P_TILE == 128, "two staged sources per lane");
     constexpr int NQ = STOKES ? 3 : 1;
+    __shared__ Src<R, STOKES> tile[P2P_WAVES][P2P_TILE];
     __shared__ R red[P2P_WAVES][NQ][64];
     // blocks are dealt to the 8 XCDs round robin; give each XCD a contiguous
-    // run of groups so that neighbouring groups share its L2
+    // run of units so that neighbouring units share its L2
     const int g = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
-    if (g >= ngrp)
+    if (g >= nunit)
         return;
-    const int32_t *gi = ginfo + 8 * (int64_t)g;
-    const int tb = gi[0], te = gi[1];
-    const int me0 = gi[3], me1 = gi[4], me2 = gi[5];
+    const int4 u = units[g];
+    const int tb = u.x, n = u.y - u.x;  // 1 <= n <= 64; chunks hold at most (128 / P) P sources
+    const int P = 64 / n;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int e0 = gptr[g], e1 = gptr[g + 1];
-    const double *cG = box_r + 5 * (int64_t)gi[7];
-    for (int t0 = tb; t0 < te; t0 += 64) {
-        const int i = t0 + lane;
-        const bool active = i < te;
-        const int gm = (i >= me0) + (i >= me1) + (i >= me2);  // member holding target i
-        R tx = 0, ty = 0, tz = 0;
+    const int ph = lane / n, tl = lane - ph * n;
+    const bool active = ph < P;
+    const int i = tb + tl;  // < tb + n for every lane
+    R tx, ty, tz;
+    if constexpr (sizeof(R) == 8) {
+        tx = tc[i];
+        ty = tc[nt + i];
+        tz = tc[2 * nt + i];
+    } else {
+        tx = tc32[i];
+        ty = tc32[nt + i];
+        tz = tc32[2 * nt + i];
+    }
+    R acc[NQ];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a)
+        acc[a] = 0;
+    Src<R, STOKES> *my = tile[w];
+    // staged slots of this lane: t = lane and t = lane + 64, at phase t % P, position t / P
+    const int ta = lane, tb2 = lane + 64;
+    const int pa = ta / P, qa = ta - pa * P;
+    const int pb = tb2 / P, qb = tb2 - pb * P;
+    int c = u.z + w;
+    int2 ch = make_int2(0, 0);
+    Src<R, STOKES> ra = far_zero_source<R, STOKES>(), rb = ra;
+    if (c < u.w) {
+        ch = chunks[c];
+        const int cnt = ch.y & 0xffff;
+        if (ta < cnt)
+            ra = src[ch.x + ta];
+        if (tb2 < cnt)
+            rb = src[ch.x + tb2];
+    }
+    while (c < u.w) {
+        const int k0 = ch.x, cnt = ch.y & 0xffff;
+        const bool self = (ch.y >> 16) != 0;
+        const int nj = (cnt + P - 1) / P;  // P * nj <= 128
+        // the wave's reads of its previous tile are issued before these writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (ta < P * nj)
+            my[qa * nj + pa] = ra;  // slots past cnt keep the far zero source
+        if (tb2 < P * nj)
+            my[qb * nj + pb] = rb;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        R px = tx, py = ty, pz = tz;
+        if constexpr (sizeof(R) == 4) {
+            const float4 o = choff[c];
+            px += o.x;
+            py += o.y;
+            pz += o.z;
+        }
+        // fetch the next chunk while this one is evaluated
+        const int cn = c + P2P_WAVES;
+        if (cn < u.w) {
+            ch = chunks[cn];
+            const int cnt2 = ch.y & 0xffff;
+            ra = far_zero_source<R, STOKES>();
+            rb = ra;
+            if (ta < cnt2)
+                ra = src[ch.x + ta];
+            if (tb2 < cnt2)
+                rb = src[ch.x + tb2];
+        }
         if (active) {
-            if constexpr (sizeof(R) == 8) {
-                tx = tc[i];
-                ty = tc[nt + i];
-                tz = tc[2 * nt + i];
-            } else {
-                tx = tcg32[i];
-                ty = tcg32[nt + i];
-                tz = tcg32[2 * nt + i];
-            }
+            if (self)
+                p2p_phase<R, STOKES, true>(my + ph * nj, nj, k0 + ph, P, i, px, py, pz, acc);
+            else
+                p2p_phase<R, STOKES, false>(my + ph * nj, nj, 0, 0, i, px, py, pz, acc);
         }
-        R acc[NQ];
+        c = cn;
+    }
 #pragma unroll
-        for (int a = 0; a < NQ; ++a)
-            acc[a] = 0;
-        for (int e = e0 + w; e < e1; e += P2P_WAVES) {
-            const int sb = gsrc[e];
-            const int mask = gmask[e];
-            const int s0 = box_i[6 * sb + 1], s1 = box_i[6 * sb + 2];
-            R px = tx, py = ty, pz = tz;
-            if constexpr (sizeof(R) == 4) {
-                const double *cS = box_r + 5 * (int64_t)sb;
-                px += (float)(cG[0] - cS[0]);
-                py += (float)(cG[1] - cS[1]);
-                pz += (float)(cG[2] - cS[2]);
-            }
-            if (active && ((mask >> gm) & 1)) {
-                if (s0 >= tb && s0 < te)  // a member leaf: skip each target's own panel
-                    p2p_leaf<R, STOKES, true>(4 * s0, 4 * s1, i, px, py, pz, src, acc);
-                else
-                    p2p_leaf<R, STOKES, false>(4 * s0, 4 * s1, i, px, py, pz, src, acc);
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < NQ; ++a)
-            red[w][a][lane] = acc[a];
-        __syncthreads();
-        if (w == 0 && active) {
-#pragma unroll
-            for (int a = 0; a < NQ; ++a) {
-                double sum = 0.0;
-                for (int v = 0; v < P2P_WAVES; ++v)
-                    sum += (double)red[v][a][lane];
-                ynear[(int64_t)NQ * i + a] = sum;
-            }
-        }
-        __syncthreads();
+    for (int a = 0; a < NQ; ++a)
+        red[w][a][lane] = active ? acc[a] : R(0);
+    __syncthreads();
+    for (int x = threadIdx.x; x < NQ * n; x += 64 * P2P_WAVES) {
+        const int a = x / n, tt = x - a * n;
+        double sum = 0.0;
+        for (int v = 0; v < P2P_WAVES; ++v)
+            for (int q = 0; q < P; ++q)
+                sum += (double)red[v][a][q * n + tt];
+        ynear[(int64_t)NQ * (tb + tt) + a] = sum;
     }
 }
 
@@ -851,17 +887,28 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
             FB_HIP(hipGetLastError());
         }
         const M2LPlan &P = ctx->m2l;
-        const int fpm = (ctx->prm.p_max + 1) * (ctx->prm.p_max + 1);
-        const cplx<R> *oct;
-        if constexpr (sizeof(R) == 8)
-            oct = P.oct64;
-        else
-            oct = P.oct32;
-        for (int l = T.nlevels - 2; l >= 0; --l) {
-            int b0 = T.level_begin[l], nb = T.level_begin[l + 1] - b0;
-            const int nslot = std::max(1, std::min(8, 256 / ncoef(p)));
-            const size_t shm = sizeof(cplx<R>) * (size_t)nslot * NCH * ncoef(p);
-            k_m2m<R, NCH><<<nb, 256, shm, st>>>(p, ncs, fpm, b0, T.box_i, T.box_r, P.box_oct, oct, M);
+        const R *m2m_op, *l2l_op;
+        if constexpr (sizeof(R) == 8) {
+            m2m_op = P.m2m64;
+            l2l_op = P.l2l64;
+        } else {
+            m2m_op = P.m2m32;
+            l2l_op = P.l2l32;
+        }
+        const size_t op_shm = sizeof(R) * 16 * 2 * (size_t)ncoef(p);
+        cplx<R> *Z = static_cast<cplx<R> *>(P.Z);
+        // children of level l into parents of level l - 1, deepest first; levels
+        // above the coarsest M2L source are never read
+        for (int l = T.nlevels - 1; l >= 1 && l - 1 >= P.lmin_src; --l) {
+            const int t0 = P.tile_begin[l], ntile = P.tile_begin[l + 1] - t0;
+            const int q0 = P.par_begin[l - 1], npar = P.par_begin[l] - q0;
+            if (ntile == 0 || npar == 0)
+                continue;
+            k_octant_apply<R, NCH, false><<<ntile, 256, op_shm, st>>>(p, ncs, P.op_dim, m2m_op, P.tiles, t0,
+                                                                      P.level_list, T.box_i, T.box_r, M, Z);
+            FB_HIP(hipGetLastError());
+            k_m2m_sum<R, NCH><<<grid_for((int64_t)npar * NCH * ncoef(p), 256), 256, 0, st>>>(
+                p, ncs, npar, P.parents + q0, T.box_i, Z, M);
             FB_HIP(hipGetLastError());
         }
         stage_end(ctx, SO + 2, st, ev);
@@ -887,9 +934,14 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
         stage_end(ctx, SO + 1, st, ev, 4.0 * (p + 1) * (p + 1) * (p + 1) * (p + 2) * NCH * (double)T.n_m2l);
 
         stage_begin(ctx, SO + 3, st, &ev);
-        for (int l = 1; l < T.nlevels; ++l) {
-            int b0 = T.level_begin[l], nb = T.level_begin[l + 1] - b0;
-            k_l2l<R, NCH><<<nb, std::min(256, 64 * ((ncoef(p) + 63) / 64)), 0, st>>>(p, ncs, fpm, b0, T.box_i, T.box_r, P.box_oct, oct, L);
+        // parents of level l - 1 into children of level l; levels above the
+        // coarsest M2L target hold no local expansion
+        for (int l = std::max(1, P.lmin_tgt + 1); l < T.nlevels; ++l) {
+            const int t0 = P.tile_begin[l], ntile = P.tile_begin[l + 1] - t0;
+            if (ntile == 0)
+                continue;
+            k_octant_apply<R, NCH, true><<<ntile, 256, op_shm, st>>>(p, ncs, P.op_dim, l2l_op, P.tiles, t0,
+                                                                     P.level_list, T.box_i, T.box_r, L, L);
             FB_HIP(hipGetLastError());
         }
         k_l2p<R, STOKES><<<T.nleaf, 64, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L,
@@ -902,10 +954,11 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
 
     stage_begin(ctx, SO + 0, st, &ev);
     {
-        const int per_xcd = (T.n_grp + 7) / 8;
-        k_p2p<R, STOKES><<<8 * per_xcd, 64 * P2P_WAVES, 0, st>>>(T.n_grp, per_xcd, T.grp_info, T.grp_src_ptr,
-                                                                T.grp_src, T.grp_src_mask, T.box_i, T.box_r, nt,
-                                                                G.tc, T.tcg32, src, ctx->y_near);
+        const int per_xcd = (T.n_unit + 7) / 8;
+        if (T.n_unit > 0)
+            k_p2p<R, STOKES><<<8 * per_xcd, 64 * P2P_WAVES, 0, st>>>(T.n_unit, per_xcd, T.p2p_unit, T.p2p_chunk,
+                                                                    T.p2p_choff, nt, G.tc, G.tc32, src,
+                                                                    ctx->y_near);
     }
     FB_HIP(hipGetLastError());
     // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target

@@ -161,6 +161,155 @@ __global__ void k_octant_tables(int p, cplx<double> *__restrict__ t64, cplx<floa
     }
 }
 
+__device__ inline void index_nm(int c, int &n, int &m)
+{
+    n = (int)((sqrt(8.0 * c + 1.0) - 1.0) * 0.5);
+    while ((n + 1) * (n + 2) / 2 <= c)
+        ++n;
+    while (n * (n + 1) / 2 > c)
+        --n;
+    m = c - n * (n + 1) / 2;
+}
+
+// (a + ib) u with u = 1 (part 0) or i (part 1); conj_u takes conj(u) instead
+__device__ inline void add_unit(double a, double b, int part, bool conj_u, double &re, double &im)
+{
+    if (part == 0) {
+        re += a;
+        im += b;
+    } else if (!conj_u) {
+        re -= b;
+        im += a;
+    } else {
+        re += b;
+        im -= a;
+    }
+}
+
+// Entry (output r, input k) of the octant operators, from the same sums as
+// the translation theorems: the unit input X = 1 or i in coefficient (j, mu)
+// also stands for X_j^-mu = (-1)^mu conj(X), so each entry collects at most
+// two terms.
+//   M2M: M_n^m(P) = sum_{j <= n} 2^-j sum_mm conj(R_{n-j}^{m-mm}(delta)) M_j^mm(C)
+//   L2L: L_j^k(C) = 2^-(j+1) sum_{n >= j} sum_m L_n^m(P) conj(R_{n-j}^{m-k}(delta))
+__global__ void k_octant_operators(int pm, int D, const cplx<double> *__restrict__ oct, double *__restrict__ m2m64,
+                                   float *__restrict__ m2m32, double *__restrict__ l2l64, float *__restrict__ l2l32)
+{
+    const int o = blockIdx.y;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)D * D)
+        return;
+    const int k = (int)(e / D), r = (int)(e - (int64_t)(e / D) * D);
+    const int pin = k & 1, pout = r & 1;
+    int j, mu, n, m;
+    index_nm(k >> 1, j, mu);
+    index_nm(r >> 1, n, m);
+    const cplx<double> *Rt = oct + (int64_t)o * (pm + 1) * (pm + 1);
+    const double smu = (mu & 1) ? -1.0 : 1.0;
+    double re = 0.0, im = 0.0;
+    if (j <= n) {  // M2M, output (n, m), input (j, mu)
+        const int a = n - j;
+        const double sc = ldexp(1.0, -j);
+        if (abs(m - mu) <= a) {
+            const cplx<double> c = Rt[full_index(a, m - mu)];
+            add_unit(sc * c.re, -sc * c.im, pin, false, re, im);
+        }
+        if (mu > 0 && abs(m + mu) <= a) {
+            const cplx<double> c = Rt[full_index(a, m + mu)];
+            add_unit(smu * sc * c.re, -smu * sc * c.im, pin, true, re, im);
+        }
+    }
+    const int64_t at = (int64_t)o * D * D + e;
+    m2m64[at] = pout ? im : re;
+    m2m32[at] = (float)(pout ? im : re);
+    re = im = 0.0;
+    if (j >= n) {  // L2L, output (n, m), input (j, mu)
+        const int a = j - n;
+        const double f = ldexp(1.0, -(n + 1));
+        if (abs(mu - m) <= a) {
+            const cplx<double> c = Rt[full_index(a, mu - m)];
+            add_unit(f * c.re, -f * c.im, pin, false, re, im);
+        }
+        if (mu > 0 && abs(mu + m) <= a) {
+            const cplx<double> c = Rt[full_index(a, -mu - m)];
+            add_unit(smu * f * c.re, -smu * f * c.im, pin, true, re, im);
+        }
+    }
+    l2l64[at] = pout ? im : re;
+    l2l32[at] = (float)(pout ? im : re);
+}
+
+// Octant operators, per-level tiles and the levels the far field uses.
+void build_level_plan(fmmbem_ctx *ctx, hipStream_t st)
+{
+    Tree &T = ctx->tree;
+    M2LPlan &P = ctx->m2l;
+    const int pm = ctx->prm.p_max;
+    const int D = 2 * ncoef(pm);
+    P.op_dim = D;
+    const size_t nop = (size_t)8 * D * D;
+    P.m2m64 = ctx->arena.alloc<double>(nop);
+    P.l2l64 = ctx->arena.alloc<double>(nop);
+    P.m2m32 = ctx->arena.alloc<float>(nop);
+    P.l2l32 = ctx->arena.alloc<float>(nop);
+    {
+        dim3 grid((unsigned)(((int64_t)D * D + 255) / 256), 8);
+        k_octant_operators<<<grid, 256, 0, st>>>(pm, D, P.oct64, P.m2m64, P.m2m32, P.l2l64, P.l2l32);
+        FB_HIP(hipGetLastError());
+    }
+    P.Z = ctx->arena.alloc<cplx<double>>((size_t)T.nbox * ctx->nch * ncoef(pm));
+    std::vector<int8_t> oct(T.nbox);
+    FB_HIP(hipMemcpyAsync(oct.data(), P.box_oct, T.nbox, hipMemcpyDeviceToHost, st));
+    // coarsest M2L source and target levels
+    std::vector<int32_t> ptr(T.nbox + 1), srcs(std::max<int64_t>(T.n_m2l, 1));
+    FB_HIP(hipMemcpyAsync(ptr.data(), T.m2l_ptr, sizeof(int32_t) * (T.nbox + 1), hipMemcpyDeviceToHost, st));
+    if (T.n_m2l > 0)
+        FB_HIP(hipMemcpyAsync(srcs.data(), T.m2l_src, sizeof(int32_t) * T.n_m2l, hipMemcpyDeviceToHost, st));
+    FB_HIP(hipStreamSynchronize(st));
+    const std::vector<int32_t> &hb = T.h_box_i;
+    P.lmin_src = P.lmin_tgt = T.nlevels;
+    for (int b = 0; b < T.nbox; ++b)
+        if (ptr[b + 1] > ptr[b])
+            P.lmin_tgt = std::min(P.lmin_tgt, hb[6 * b]);
+    for (int64_t i = 0; i < T.n_m2l; ++i)
+        P.lmin_src = std::min(P.lmin_src, hb[6 * srcs[i]]);
+    const int per_tile = 16 / ctx->nch;
+    std::vector<int4> tiles;
+    std::vector<int32_t> list, parents;
+    P.tile_begin.assign(T.nlevels + 1, 0);
+    P.par_begin.assign(T.nlevels + 1, 0);
+    for (int l = 0; l < T.nlevels; ++l) {
+        P.tile_begin[l] = (int)tiles.size();
+        P.par_begin[l] = (int)parents.size();
+        const int b0 = T.level_begin[l], b1 = T.level_begin[l + 1];
+        for (int b = b0; b < b1; ++b)
+            if (hb[6 * b + 5] > 0)
+                parents.push_back(b);
+        if (l == 0)
+            continue;
+        for (int o = 0; o < 8; ++o) {
+            const int first = (int)list.size();
+            for (int b = b0; b < b1; ++b)
+                if (oct[b] == o)
+                    list.push_back(b);
+            for (int e = first; e < (int)list.size(); e += per_tile)
+                tiles.push_back(make_int4(o, e, std::min(per_tile, (int)list.size() - e), 0));
+        }
+    }
+    P.tile_begin[T.nlevels] = (int)tiles.size();
+    P.par_begin[T.nlevels] = (int)parents.size();
+    P.tiles = ctx->arena.alloc<int4>(std::max<size_t>(tiles.size(), 1));
+    P.level_list = ctx->arena.alloc<int32_t>(std::max<size_t>(list.size(), 1));
+    P.parents = ctx->arena.alloc<int32_t>(std::max<size_t>(parents.size(), 1));
+    if (!tiles.empty()) {
+        FB_HIP(hipMemcpyAsync(P.tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, st));
+        FB_HIP(hipMemcpyAsync(P.level_list, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, st));
+    }
+    if (!parents.empty())
+        FB_HIP(hipMemcpyAsync(P.parents, parents.data(), sizeof(int32_t) * parents.size(), hipMemcpyHostToDevice, st));
+    FB_HIP(hipStreamSynchronize(st));
+}
+
 }  // namespace
 
 void build_translations(fmmbem_ctx *ctx, hipStream_t st)
@@ -179,6 +328,7 @@ void build_translations(fmmbem_ctx *ctx, hipStream_t st)
         k_octant_tables<<<8, 64, 0, st>>>(pm, P.oct64, P.oct32);
         FB_HIP(hipGetLastError());
     }
+    build_level_plan(ctx, st);
     if (n == 0)
         return;
     DevArena tmp;

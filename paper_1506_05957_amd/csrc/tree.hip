@@ -383,29 +383,20 @@ template <typename T> void exclusive_scan(const T *in, T *out, int64_t n, hipStr
     FB_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, st));
 }
 
-// target coordinates relative to the reference leaf centre of their P2P group
-__global__ void k_group_relative(int ngrp, const int32_t *__restrict__ ginfo, const double *__restrict__ box_r,
-                                 const double *__restrict__ tc, int64_t nt, float *__restrict__ tcg32)
-{
-    const int g = blockIdx.x;
-    if (g >= ngrp)
-        return;
-    const int32_t *gi = ginfo + 8 * (int64_t)g;
-    const double *c = box_r + 5 * (int64_t)gi[7];
-    for (int i = gi[0] + threadIdx.x; i < gi[1]; i += blockDim.x)
-        for (int d = 0; d < 3; ++d)
-            tcg32[d * nt + i] = (float)(tc[d * nt + i] - c[d]);
-}
-
-// Consecutive leaves in Morton (panel) order are packed while they fit one
-// wave (<= 64 targets, <= 4 leaves); a leaf with more than 64 targets is a
-// group of its own.  For every group: the sorted union of its members' P2P
-// source leaves, each with the bit mask of the members that list it.
-void build_p2p_groups(fmmbem_ctx *ctx, const std::vector<int32_t> &hp, int64_t n_p2p, hipStream_t st)
+// P2P work units.  Each leaf gives ceil(n / 64) units of at most 64 targets
+// (one per lane when the wave runs one phase).  A unit of n targets runs
+// P = floor(64 / n) phases; its sources are the leaf's P2P source leaves cut
+// into chunks of at most floor(P2P_TILE / P) P consecutive sources, so that a
+// chunk padded to a multiple of P still fits one tile.  The chunks are sorted
+// by decreasing size so that dealing them round robin to the waves of a block
+// balances the waves.  The FP32 offset of a chunk
+// is the difference of the two leaf centres, rounded once from FP64.
+void build_p2p_units(fmmbem_ctx *ctx, const std::vector<int32_t> &hp, int64_t n_p2p, hipStream_t st)
 {
     Tree &T = ctx->tree;
     const std::vector<int32_t> &hb = T.h_box_i;
-    std::vector<int32_t> leaves = T.h_leaves;
+    const std::vector<double> &hr = T.h_box_r;
+    std::vector<int> leaves = T.h_leaves;
     std::sort(leaves.begin(), leaves.end(), [&](int a, int b) { return hb[6 * a + 1] < hb[6 * b + 1]; });
     // per-leaf source lists (hp is sorted by target)
     std::vector<int64_t> first(T.nbox + 1, 0);
@@ -413,56 +404,48 @@ void build_p2p_groups(fmmbem_ctx *ctx, const std::vector<int32_t> &hp, int64_t n
         first[hp[2 * i] + 1]++;
     for (int b = 0; b < T.nbox; ++b)
         first[b + 1] += first[b];
-    std::vector<int32_t> info, sptr(1, 0), src, mask;
-    size_t i = 0;
-    while (i < leaves.size()) {
-        std::vector<int> mem{leaves[i]};
-        int nt_g = hb[6 * leaves[i] + 2] - hb[6 * leaves[i] + 1];
-        size_t j = i + 1;
-        while (nt_g <= 64 && j < leaves.size() && mem.size() < 4) {
-            int c = hb[6 * leaves[j] + 2] - hb[6 * leaves[j] + 1];
-            if (nt_g + c > 64 || hb[6 * leaves[j] + 1] != hb[6 * mem.back() + 2])
-                break;
-            mem.push_back(leaves[j]);
-            nt_g += c;
-            ++j;
+    std::vector<int4> units;
+    std::vector<int2> chunks;
+    std::vector<float4> offs;
+    struct Piece { int32_t begin, count, self, leaf; };
+    std::vector<Piece> pieces;
+    for (int t : leaves) {
+        const int tb = hb[6 * t + 1], te = hb[6 * t + 2];
+        for (int u0 = tb; u0 < te; u0 += 64) {
+            const int nu = std::min(te, u0 + 64) - u0;
+            const int cap = (P2P_TILE / (64 / nu)) * (64 / nu);  // a multiple of the unit's phase count
+            pieces.clear();
+            for (int64_t e = first[t]; e < first[t + 1]; ++e) {
+                const int s = hp[2 * e + 1];
+                const int32_t k0 = 4 * hb[6 * s + 1], k1 = 4 * hb[6 * s + 2];
+                for (int32_t k = k0; k < k1; k += cap)
+                    pieces.push_back({k, std::min(cap, k1 - k), s == t ? 1 : 0, s});
+            }
+            std::stable_sort(pieces.begin(), pieces.end(),
+                             [](const Piece &a, const Piece &b) { return a.count > b.count; });
+            const int32_t c0 = (int32_t)chunks.size();
+            for (const Piece &pc : pieces) {
+                chunks.push_back(make_int2(pc.begin, pc.count | (pc.self << 16)));
+                offs.push_back(make_float4((float)(hr[5 * t] - hr[5 * pc.leaf]),
+                                           (float)(hr[5 * t + 1] - hr[5 * pc.leaf + 1]),
+                                           (float)(hr[5 * t + 2] - hr[5 * pc.leaf + 2]), 0.0f));
+            }
+            FB_REQUIRE(chunks.size() < ((size_t)1 << 31), FMMBEM_ENOMEM, "P2P chunk list exceeds 2^31 entries");
+            units.push_back(make_int4(u0, u0 + nu, c0, (int32_t)chunks.size()));
         }
-        int32_t gi[8] = {hb[6 * mem[0] + 1], hb[6 * mem.back() + 2], (int32_t)mem.size(), 0, 0, 0, 0, mem[0]};
-        for (size_t k = 0; k < 4; ++k)
-            gi[3 + k] = k < mem.size() ? hb[6 * mem[k] + 2] : gi[1];
-        info.insert(info.end(), gi, gi + 8);
-        std::vector<std::pair<int32_t, int32_t>> u;
-        for (size_t k = 0; k < mem.size(); ++k)
-            for (int64_t e = first[mem[k]]; e < first[mem[k] + 1]; ++e)
-                u.push_back({hp[2 * e + 1], 1 << k});
-        std::sort(u.begin(), u.end());
-        for (size_t a = 0; a < u.size();) {
-            int32_t m = 0;
-            size_t b = a;
-            while (b < u.size() && u[b].first == u[a].first)
-                m |= u[b++].second;
-            src.push_back(u[a].first);
-            mask.push_back(m);
-            a = b;
-        }
-        sptr.push_back((int32_t)src.size());
-        i = j;
     }
-    T.n_grp = (int32_t)(info.size() / 8);
+    T.n_unit = (int32_t)units.size();
+    T.n_chunk = (int64_t)chunks.size();
     DevArena &A = ctx->arena;
-    T.grp_info = A.alloc<int32_t>(info.size());
-    T.grp_src_ptr = A.alloc<int32_t>(sptr.size());
-    T.grp_src = A.alloc<int32_t>(std::max<size_t>(src.size(), 1));
-    T.grp_src_mask = A.alloc<int32_t>(std::max<size_t>(mask.size(), 1));
-    FB_HIP(hipMemcpyAsync(T.grp_info, info.data(), sizeof(int32_t) * info.size(), hipMemcpyHostToDevice, st));
-    FB_HIP(hipMemcpyAsync(T.grp_src_ptr, sptr.data(), sizeof(int32_t) * sptr.size(), hipMemcpyHostToDevice, st));
-    if (!src.empty()) {
-        FB_HIP(hipMemcpyAsync(T.grp_src, src.data(), sizeof(int32_t) * src.size(), hipMemcpyHostToDevice, st));
-        FB_HIP(hipMemcpyAsync(T.grp_src_mask, mask.data(), sizeof(int32_t) * mask.size(), hipMemcpyHostToDevice, st));
+    T.p2p_unit = A.alloc<int4>(std::max<size_t>(units.size(), 1));
+    T.p2p_chunk = A.alloc<int2>(std::max<size_t>(chunks.size(), 1));
+    T.p2p_choff = A.alloc<float4>(std::max<size_t>(offs.size(), 1));
+    if (!units.empty())
+        FB_HIP(hipMemcpyAsync(T.p2p_unit, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice, st));
+    if (!chunks.empty()) {
+        FB_HIP(hipMemcpyAsync(T.p2p_chunk, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice, st));
+        FB_HIP(hipMemcpyAsync(T.p2p_choff, offs.data(), sizeof(float4) * offs.size(), hipMemcpyHostToDevice, st));
     }
-    T.tcg32 = A.alloc<float>(3 * T.nt);
-    k_group_relative<<<T.n_grp, 64, 0, st>>>(T.n_grp, T.grp_info, T.box_r, ctx->geo.tc, T.nt, T.tcg32);
-    FB_HIP(hipGetLastError());
     FB_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
 }
 
@@ -700,7 +683,7 @@ void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream
             int a = hp[2 * i], b = hp[2 * i + 1];
             T.p2p_interactions += (int64_t)(hb[6 * a + 2] - hb[6 * a + 1]) * 4 * (hb[6 * b + 2] - hb[6 * b + 1]);
         }
-        build_p2p_groups(ctx, hp, n_p2p, st);
+        build_p2p_units(ctx, hp, n_p2p, st);
         tmp.release();
     } catch (...) {
         (void)hipStreamSynchronize(st);
