@@ -162,6 +162,9 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         ctx->nsrc = 4 * ctx->nt;
         ctx->n = kernel == FMMBEM_STOKES_SL ? 3 * ctx->nt : ctx->nt;
         ctx->nch = kernel == FMMBEM_STOKES_SL ? 4 : 1;
+        FB_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        FB_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        FB_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
         build_geometry_and_tree(ctx, mesh, st);
         build_correction(ctx, st);
         build_translations(ctx, st);
@@ -294,6 +297,12 @@ void fmmbem_destroy(fmmbem_ctx_t *ctx)
         (void)hipEventDestroy(e);
     free_krylov(ctx);
     ctx->arena.release();
+    if (ctx->ev_fork)
+        (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join)
+        (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side)
+        (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }
 

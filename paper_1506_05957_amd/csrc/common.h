@@ -205,6 +205,10 @@ struct fmmbem_ctx {
     double *y_far = nullptr;   // [n]
     fmmbem::Timing timing;
     fmmbem::KrylovWork *kw = nullptr;
+    // P2P runs on a stream of its own, concurrently with the far-field chain
+    // (fork after the charges, join before the combine)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace fmmbem {

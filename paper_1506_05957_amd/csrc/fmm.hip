@@ -262,9 +262,9 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
 //   L2L: L_j^k(C) += 2^-(j+1) sum_{n >= j} sum_m L_n^m(P) conj(R_{n-j}^{m-k}(delta))
 // are fixed real linear maps of the stored coefficients, one per octant.  A
 // block takes a tile of boxes of one level and one octant (16 columns: boxes
-// x channels): the input coefficients sit in LDS, thread (row, column group)
-// streams its operator row (coalesced over rows) and skips the inputs that the
-// triangular structure zeroes.  M2M writes per-child terms that k_m2m_sum adds
+// x channels) and a chunk of 64 output rows: the input coefficients sit in
+// LDS, lane r streams operator row r (coalesced over rows) and skips the
+// inputs that the triangular structure zeroes.  M2M writes per-child terms that k_m2m_sum adds
 // up per parent in child order; L2L adds into the child.  Stokes: the fourth
 // channel changes centre with the first three (M2M: + d . Z, L2L: - d . Z,
 // d = c_C - c_P).
@@ -276,9 +276,13 @@ __global__ __launch_bounds__(256) void k_octant_apply(int p, int ncs, int D, con
                                                       const double *__restrict__ box_r, const cplx<R> *__restrict__ X,
                                                       cplx<R> *__restrict__ Y)
 {
-    constexpr int NCOL = 16, CW = 8, BPG = CW / NCH;
+    // block = (tile, chunk of 64 rows); lane = row, the 4 waves split the
+    // inputs k (wave w takes k = w, w + 4, ...) and are summed in wave order
+    constexpr int NCOL = 16, NW = 4;
+    constexpr int BPT = NCOL / NCH;  // boxes per tile
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *xs = reinterpret_cast<R *>(smem_raw);  // [Dp][NCOL]
+    R *xs = reinterpret_cast<R *>(smem_raw);    // [Dp][NCOL], then
+    R *part = reinterpret_cast<R *>(smem_raw);  // [NW - 1][NCOL][64]
     const int4 tl = tiles[tile0 + blockIdx.x];
     const int o = tl.x, e0 = tl.y, cnt = tl.z;
     const int Dp = 2 * ncoef(p);
@@ -294,51 +298,63 @@ __global__ __launch_bounds__(256) void k_octant_apply(int p, int ncs, int D, con
         xs[k * NCOL + col] = v;
     }
     __syncthreads();
-    const R *A = ops + (int64_t)o * D * D;
-    for (int task = threadIdx.x; task < Dp * (NCOL / CW); task += blockDim.x) {
-        const int cg = task / Dp, r = task - cg * Dp;
-        if (cg * BPG >= cnt)
-            continue;
-        int n, m;
-        idx_to_nm(r >> 1, n, m);
-        const int k0 = L2L ? 2 * cidx(n, 0) : 0;     // L2L: inputs of degree >= n
-        const int k1 = L2L ? Dp : 2 * ncoef(n);      // M2M: inputs of degree <= n
-        R acc[CW];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r = blockIdx.y * 64 + lane;
+    const bool active = r < Dp;
+    int n = 0, m = 0;
+    idx_to_nm(active ? r >> 1 : 0, n, m);
+    const int k0 = L2L ? 2 * cidx(n, 0) : 0;  // L2L: inputs of degree >= n
+    const int k1 = L2L ? Dp : 2 * ncoef(n);   // M2M: inputs of degree <= n
+    const R *A = ops + (int64_t)o * D * D + (active ? r : 0);
+    R acc[NCOL];
 #pragma unroll
-        for (int q = 0; q < CW; ++q)
-            acc[q] = 0;
-        const R *x = xs + cg * CW;
-#pragma unroll 2
-        for (int k = k0; k < k1; ++k) {
-            const R a = A[(int64_t)k * D + r];
+    for (int q = 0; q < NCOL; ++q)
+        acc[q] = 0;
+    if (active) {
+        // the first k of this wave's residue class at or above k0
+        for (int k = k0 + ((w - k0) % NW + NW) % NW; k < k1; k += NW) {
+            const R a = A[(int64_t)k * D];
+            const R *x = xs + k * NCOL;
 #pragma unroll
-            for (int q = 0; q < CW; ++q)
-                acc[q] += a * x[k * NCOL + q];
+            for (int q = 0; q < NCOL; ++q)
+                acc[q] += a * x[q];
+        }
+    }
+    __syncthreads();  // xs is dead from here on
+    if (w > 0) {
+#pragma unroll
+        for (int q = 0; q < NCOL; ++q)
+            part[((w - 1) * NCOL + q) * 64 + lane] = acc[q];
+    }
+    __syncthreads();
+    if (w != 0 || !active)
+        return;
+#pragma unroll
+    for (int q = 0; q < NCOL; ++q)
+        for (int v = 0; v < NW - 1; ++v)
+            acc[q] += part[(v * NCOL + q) * 64 + lane];
+#pragma unroll
+    for (int bq = 0; bq < BPT; ++bq) {
+        if (bq >= cnt)
+            break;
+        const int box = list[e0 + bq];
+        R v[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+            v[ch] = acc[bq * NCH + ch];
+        if constexpr (NCH == 4) {
+            const double *cC = box_r + 5 * (int64_t)box, *cP = box_r + 5 * (int64_t)box_i[6 * box + 3];
+            const R d0 = (R)(cC[0] - cP[0]), d1 = (R)(cC[1] - cP[1]), d2 = (R)(cC[2] - cP[2]);
+            const R dv = d0 * v[0] + d1 * v[1] + d2 * v[2];
+            v[3] = L2L ? v[3] - dv : v[3] + dv;
         }
 #pragma unroll
-        for (int bq = 0; bq < BPG; ++bq) {
-            const int b = cg * BPG + bq;
-            if (b >= cnt)
-                continue;
-            const int box = list[e0 + b];
-            R v[NCH];
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-                v[ch] = acc[bq * NCH + ch];
-            if constexpr (NCH == 4) {
-                const double *cC = box_r + 5 * (int64_t)box, *cP = box_r + 5 * (int64_t)box_i[6 * box + 3];
-                const R d0 = (R)(cC[0] - cP[0]), d1 = (R)(cC[1] - cP[1]), d2 = (R)(cC[2] - cP[2]);
-                const R dv = d0 * v[0] + d1 * v[1] + d2 * v[2];
-                v[3] = L2L ? v[3] - dv : v[3] + dv;
-            }
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                R *dst = reinterpret_cast<R *>(Y + ((int64_t)box * NCH + ch) * ncs) + r;
-                if constexpr (L2L)
-                    *dst += v[ch];
-                else
-                    *dst = v[ch];
-            }
+        for (int ch = 0; ch < NCH; ++ch) {
+            R *dst = reinterpret_cast<R *>(Y + ((int64_t)box * NCH + ch) * ncs) + r;
+            if constexpr (L2L)
+                *dst += v[ch];
+            else
+                *dst = v[ch];
         }
     }
 }
@@ -869,6 +885,21 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
     FB_HIP(hipGetLastError());
     stage_end(ctx, SO + 4, st, ev);
 
+    // near field on the side stream
+    FB_HIP(hipEventRecord(ctx->ev_fork, st));
+    FB_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    stage_begin(ctx, SO + 0, ctx->side, &ev);
+    if (T.n_unit > 0) {
+        const int per_xcd = (T.n_unit + 7) / 8;
+        k_p2p<R, STOKES><<<8 * per_xcd, 64 * P2P_WAVES, 0, ctx->side>>>(T.n_unit, per_xcd, T.p2p_unit, T.p2p_chunk,
+                                                                       T.p2p_choff, nt, G.tc, G.tc32, src,
+                                                                       ctx->y_near);
+        FB_HIP(hipGetLastError());
+    }
+    // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
+    stage_end(ctx, SO + 0, ctx->side, ev, (STOKES ? 30.0 : 12.0) * (double)(T.p2p_interactions - 4 * nt));
+    FB_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+
     if (T.n_m2l > 0) {
         stage_begin(ctx, SO + 2, st, &ev);
         {
@@ -895,7 +926,8 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
             m2m_op = P.m2m32;
             l2l_op = P.l2l32;
         }
-        const size_t op_shm = sizeof(R) * 16 * 2 * (size_t)ncoef(p);
+        const size_t op_shm = sizeof(R) * 16 * std::max<size_t>(2 * (size_t)ncoef(p), 3 * 64);
+        const int row_chunks = (2 * ncoef(p) + 63) / 64;
         cplx<R> *Z = static_cast<cplx<R> *>(P.Z);
         // children of level l into parents of level l - 1, deepest first; levels
         // above the coarsest M2L source are never read
@@ -904,7 +936,7 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
             const int q0 = P.par_begin[l - 1], npar = P.par_begin[l] - q0;
             if (ntile == 0 || npar == 0)
                 continue;
-            k_octant_apply<R, NCH, false><<<ntile, 256, op_shm, st>>>(p, ncs, P.op_dim, m2m_op, P.tiles, t0,
+            k_octant_apply<R, NCH, false><<<dim3(ntile, row_chunks), 256, op_shm, st>>>(p, ncs, P.op_dim, m2m_op, P.tiles, t0,
                                                                       P.level_list, T.box_i, T.box_r, M, Z);
             FB_HIP(hipGetLastError());
             k_m2m_sum<R, NCH><<<grid_for((int64_t)npar * NCH * ncoef(p), 256), 256, 0, st>>>(
@@ -940,7 +972,7 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
             const int t0 = P.tile_begin[l], ntile = P.tile_begin[l + 1] - t0;
             if (ntile == 0)
                 continue;
-            k_octant_apply<R, NCH, true><<<ntile, 256, op_shm, st>>>(p, ncs, P.op_dim, l2l_op, P.tiles, t0,
+            k_octant_apply<R, NCH, true><<<dim3(ntile, row_chunks), 256, op_shm, st>>>(p, ncs, P.op_dim, l2l_op, P.tiles, t0,
                                                                      P.level_list, T.box_i, T.box_r, L, L);
             FB_HIP(hipGetLastError());
         }
@@ -952,17 +984,7 @@ void launch_fmm(fmmbem_ctx *ctx, int p, const double *x, hipStream_t st)
         FB_HIP(hipMemsetAsync(ctx->y_far, 0, sizeof(double) * ctx->n, st));
     }
 
-    stage_begin(ctx, SO + 0, st, &ev);
-    {
-        const int per_xcd = (T.n_unit + 7) / 8;
-        if (T.n_unit > 0)
-            k_p2p<R, STOKES><<<8 * per_xcd, 64 * P2P_WAVES, 0, st>>>(T.n_unit, per_xcd, T.p2p_unit, T.p2p_chunk,
-                                                                    T.p2p_choff, nt, G.tc, G.tc32, src,
-                                                                    ctx->y_near);
-    }
-    FB_HIP(hipGetLastError());
-    // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
-    stage_end(ctx, SO + 0, st, ev, (STOKES ? 30.0 : 12.0) * (double)(T.p2p_interactions - 4 * nt));
+    FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
 }
 
 }  // namespace

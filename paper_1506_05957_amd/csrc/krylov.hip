@@ -22,84 +22,79 @@ namespace {
 constexpr int DOT_BLOCK = 256;
 constexpr int DOT_PER_THREAD = 4;
 
-// part[j][b] = sum over rows of block b of V_j . w   (grid: nb x nvec)
-__global__ __launch_bounds__(DOT_BLOCK) void k_multidot(int64_t n, const double *__restrict__ V, int64_t ldv,
-                                                         const double *__restrict__ w, double *__restrict__ part,
-                                                         int nb)
+// Classical Gram-Schmidt pass over a block of rows for all nv vectors at once:
+// optionally w -= sum_j hprev[j] V_j first (the update of the previous pass),
+// then part[j][b] = V_j . w over the block's rows.  The last block to arrive
+// (atomic ticket) sums part[j][0..nb) in block order into out[j] for every j
+// and re-arms the ticket.
+constexpr int CGS_MAX = 64;
+__global__ __launch_bounds__(DOT_BLOCK) void k_cgs_dots(int64_t n, const double *__restrict__ V, int64_t ldv, int nv,
+                                                         const double *__restrict__ hprev, double *__restrict__ w,
+                                                         double *__restrict__ part, int nb, double *__restrict__ out,
+                                                         unsigned int *__restrict__ ticket)
 {
-    __shared__ double sh[DOT_BLOCK / 64];
-    const int b = blockIdx.x, j = blockIdx.y;
-    const double *v = V + (int64_t)j * ldv;
-    double s = 0.0;
-    const int64_t base = (int64_t)b * DOT_BLOCK * DOT_PER_THREAD;
-    for (int k = 0; k < DOT_PER_THREAD; ++k) {
-        int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
-        if (i < n)
-            s += v[i] * w[i];
-    }
-    for (int off = 32; off > 0; off >>= 1)
-        s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0)
-        sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < DOT_BLOCK / 64; ++k)
-            t += sh[k];
-        part[(int64_t)j * nb + b] = t;
-    }
-}
-
-// part[j][b] as above; the last block to finish column j (atomic ticket)
-// sums part[j][0..nb) in block order into out[j] and re-arms the ticket.
-__global__ __launch_bounds__(DOT_BLOCK) void k_multidot_fused(int64_t n, const double *__restrict__ V, int64_t ldv,
-                                                               const double *__restrict__ w, double *__restrict__ part,
-                                                               int nb, double *__restrict__ out,
-                                                               unsigned int *__restrict__ ticket)
-{
-    __shared__ double sh[DOT_BLOCK / 64];
+    constexpr int NWV = DOT_BLOCK / 64;
+    __shared__ double sh[CGS_MAX][NWV];
     __shared__ bool last;
-    const int b = blockIdx.x, j = blockIdx.y;
-    const double *v = V + (int64_t)j * ldv;
-    double s = 0.0;
+    const int b = blockIdx.x;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t base = (int64_t)b * DOT_BLOCK * DOT_PER_THREAD;
+    double wl[DOT_PER_THREAD];
+#pragma unroll
     for (int k = 0; k < DOT_PER_THREAD; ++k) {
-        int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
-        if (i < n)
-            s += v[i] * w[i];
+        const int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
+        double x = 0.0;
+        if (i < n) {
+            x = w[i];
+            if (hprev) {
+                for (int j = 0; j < nv; ++j)
+                    x -= hprev[j] * V[(int64_t)j * ldv + i];
+                w[i] = x;
+            }
+        }
+        wl[k] = x;
     }
-    for (int off = 32; off > 0; off >>= 1)
-        s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0)
-        sh[threadIdx.x >> 6] = s;
+    for (int j0 = 0; j0 < nv; j0 += CGS_MAX) {
+        const int nj = min(CGS_MAX, nv - j0);
+        for (int jj = 0; jj < nj; ++jj) {
+            const double *v = V + (int64_t)(j0 + jj) * ldv;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < DOT_PER_THREAD; ++k) {
+                const int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
+                if (i < n)
+                    s += v[i] * wl[k];
+            }
+            for (int off = 32; off > 0; off >>= 1)
+                s += __shfl_down(s, off, 64);
+            if (lane == 0)
+                sh[jj][wv] = s;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nj) {
+            double t = 0.0;
+            for (int k = 0; k < NWV; ++k)
+                t += sh[threadIdx.x][k];
+            part[(int64_t)(j0 + threadIdx.x) * nb + b] = t;
+        }
+        __syncthreads();
+    }
+    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < DOT_BLOCK / 64; ++k)
-            t += sh[k];
-        part[(int64_t)j * nb + b] = t;
-        __threadfence();
-        last = atomicAdd(&ticket[j], 1u) == (unsigned)(nb - 1);
-    }
+    if (threadIdx.x == 0)
+        last = atomicAdd(ticket, 1u) == (unsigned)(nb - 1);
     __syncthreads();
     if (!last)
         return;
     __threadfence();
-    double t = 0.0;
-    for (int k = threadIdx.x; k < nb; k += DOT_BLOCK)
-        t += __builtin_nontemporal_load(&part[(int64_t)j * nb + k]);
-    for (int off = 32; off > 0; off >>= 1)
-        t += __shfl_down(t, off, 64);
-    if ((threadIdx.x & 63) == 0)
-        sh[threadIdx.x >> 6] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = 0.0;
-        for (int k = 0; k < DOT_BLOCK / 64; ++k)
-            r += sh[k];
-        out[j] = r;
-        ticket[j] = 0u;
+    for (int j = threadIdx.x; j < nv; j += DOT_BLOCK) {
+        double t = 0.0;
+        for (int k = 0; k < nb; ++k)
+            t += __builtin_nontemporal_load(&part[(int64_t)j * nb + k]);
+        out[j] = t;
     }
+    if (threadIdx.x == 0)
+        *ticket = 0u;
 }
 
 // w -= sum_{j<nv} h[j] V_j, and |w|^2 into *nrm2 (same last-block scheme)
@@ -155,38 +150,6 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_update_norm(int64_t n, const doub
         *nrm2 = r;
         *ticket = 0u;
     }
-}
-
-// out[j] = sum_b part[j][b] in block order (one block per j)
-__global__ void k_reduce_parts(const double *__restrict__ part, int nb, double *__restrict__ out)
-{
-    __shared__ double sh[256];
-    const int j = blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-        s += part[(int64_t)j * nb + b];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        out[j] = sh[0];
-}
-
-// w -= sum_{j<nv} h[j] V_j
-__global__ void k_update(int64_t n, const double *__restrict__ V, int64_t ldv, int nv, const double *__restrict__ h,
-                         double *__restrict__ w)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    double s = w[i];
-    for (int j = 0; j < nv; ++j)
-        s -= h[j] * V[(int64_t)j * ldv + i];
-    w[i] = s;
 }
 
 // v = w / sqrt(nrm2[0])
@@ -251,11 +214,11 @@ KrylovWork *get_work(fmmbem_ctx *ctx, int m)
     return kw;
 }
 
-// out[0..nv) = V_j . w  (device)
-void multidot(KrylovWork *kw, const double *V, int nv, const double *w, double *out, hipStream_t st)
+// out[0..nv) = V_j . w  (device); with hprev, w -= sum_j hprev[j] V_j first
+void multidot(KrylovWork *kw, const double *V, int nv, double *w, double *out, hipStream_t st,
+              const double *hprev = nullptr)
 {
-    dim3 grid(kw->nb, nv);
-    k_multidot_fused<<<grid, DOT_BLOCK, 0, st>>>(kw->n, V, kw->n, w, kw->part, kw->nb, out, kw->ticket);
+    k_cgs_dots<<<kw->nb, DOT_BLOCK, 0, st>>>(kw->n, V, kw->n, nv, hprev, w, kw->part, kw->nb, out, kw->ticket);
     FB_HIP(hipGetLastError());
 }
 
@@ -362,16 +325,14 @@ void GmresState::enqueue_step()
     run_matvec(ctx, cur.p, cur.prec, vk, kw->w, st);
     ++matvecs;
     multidot(kw, kw->V, k + 1, kw->w, kw->h, st);
-    k_update<<<grid_for(n, DOT_BLOCK), DOT_BLOCK, 0, st>>>(n, kw->V, n, k + 1, kw->h, kw->w);
-    FB_HIP(hipGetLastError());
-    multidot(kw, kw->V, k + 1, kw->w, kw->h + (m + 2), st);
+    multidot(kw, kw->V, k + 1, kw->w, kw->h + (m + 2), st, kw->h);
     k_update_norm<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->V, n, k + 1, kw->h + (m + 2), kw->w, kw->part, kw->nb,
                                                 kw->h + (k + 1), kw->ticket + (m + 1));
     FB_HIP(hipGetLastError());
     k_normalize<<<grid_for(n, 256), 256, 0, st>>>(n, kw->w, kw->h + (k + 1), vn);
     FB_HIP(hipGetLastError());
-    FB_HIP(hipMemcpyAsync(hbuf, kw->h, sizeof(double) * (k + 2), hipMemcpyDeviceToHost, st));
-    FB_HIP(hipMemcpyAsync(hbuf + (m + 2), kw->h + (m + 2), sizeof(double) * (k + 1), hipMemcpyDeviceToHost, st));
+    // h1[0..k], |w|^2 at k + 1, and h2[0..k] at m + 2: one copy
+    FB_HIP(hipMemcpyAsync(hbuf, kw->h, sizeof(double) * (m + 2 + k + 1), hipMemcpyDeviceToHost, st));
 }
 
 void GmresState::end_cycle()
