@@ -36,6 +36,36 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
+def p2p_source_sha1() -> str:
+    """Hash of the P2P kernel and its work-list builder (the code the HBM counters measured)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1506_05957_amd", "csrc")
+    with open(os.path.join(csrc, "fmm.hip")) as f:
+        s = f.read()
+    a = s.index("// P2P (a10)")
+    b = s.index("// ----", a)
+    with open(os.path.join(csrc, "tree.hip")) as f:
+        t = f.read()
+    a2 = t.index("// P2P work units.")
+    b2 = t.index("}  // namespace", a2)
+    return hashlib.sha1((s[a:b] + t[a2:b2]).encode()).hexdigest()
+
+
+def p2p_traffic(kernel: str):
+    """HBM bytes per launch of the P2P kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None once the kernel changed."""
+    path = os.path.join(ROOT, "profiles", "k_p2p_fp32_laplace_sphere32768_hbm_counters.md")
+    try:
+        with open(path) as f:
+            text = f.read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_sha1") != p2p_source_sha1():
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,7 +182,7 @@ def main():
              "m2l_fp32": "k_m2l_group<float, 1, 4> + k_m2l_reduce<float, 1>",
              "m2l_fp64": "k_m2l_group<double, 1, 4> + k_m2l_reduce<double, 1>"}[dom]
     roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": p2p_traffic(kname),
                 "avg_launch_us": avg_s * 1e6, "launches": launches,
                 "flops_per_launch": flops / max(launches, 1)}
 

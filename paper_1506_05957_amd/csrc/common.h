@@ -209,6 +209,11 @@ struct fmmbem_ctx {
     // (fork after the charges, join before the combine)
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool near_pending = false;  // a near field launched on the side stream that no stream has joined yet
+    // near field (charges + P2P) already launched for this input and precision
+    // ahead of the mat-vec that will use it (see prefetch_near)
+    const double *spec_x = nullptr;
+    int spec_prec = -1;
 };
 
 namespace fmmbem {
@@ -233,9 +238,11 @@ struct GmresState {
     KrylovWork *kw = nullptr;
     std::vector<double> H, cs, sn, g, yv;
     double *hbuf = nullptr;  // pinned host
+    hipEvent_t ev_h = nullptr;  // the Hessenberg column has reached hbuf
     int it = 0, restarts = 0, converged = 0, k = 0;
     int64_t matvecs = 0;
     double bnorm = 0, beta = 0, rel = 1, true_rel = 1, rho_prev = 1;
+    double rho_prev2 = -1;  // the residual before rho_prev, < 0 if none
     bool done = false;
     Sched cur{0, 0};
     std::vector<int32_t> p_hist;
@@ -262,6 +269,9 @@ void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream
 void build_correction(fmmbem_ctx *ctx, hipStream_t st);
 void build_translations(fmmbem_ctx *ctx, hipStream_t st);
 void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hipStream_t st);
+// launch the near field (charges + P2P) of a mat-vec on x at precision prec
+// ahead of time; the next run_matvec with the same x and prec uses it
+void prefetch_near(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
 int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
               fmmbem_report *rep, hipStream_t st);
 void free_krylov(fmmbem_ctx *ctx);

@@ -20,23 +20,25 @@ namespace fmmbem {
 namespace {
 
 constexpr int DOT_BLOCK = 256;
-constexpr int DOT_PER_THREAD = 4;
+constexpr int DOT_PER_THREAD = 2;
 
-// Classical Gram-Schmidt pass over a block of rows for all nv vectors at once:
-// optionally w -= sum_j hprev[j] V_j first (the update of the previous pass),
-// then part[j][b] = V_j . w over the block's rows.  The last block to arrive
-// (atomic ticket) sums part[j][0..nb) in block order into out[j] for every j
-// and re-arms the ticket.
-constexpr int CGS_MAX = 64;
+// Classical Gram-Schmidt dots: block (b, g) takes the rows of block b and the
+// vectors j = g CGS_JG .. + CGS_JG - 1 and writes part[j][b] = V_j . w' over its
+// rows, where w' = w - sum_{j < nv} hprev[j] V_j when hprev is given (the
+// first pass's update, recomputed per block and not stored) and w' = w
+// otherwise.  The last block to arrive (atomic ticket) sums part[j][0..nb) in
+// block order into out[j] for every j and re-arms the ticket.
+constexpr int CGS_JG = 8;
 __global__ __launch_bounds__(DOT_BLOCK) void k_cgs_dots(int64_t n, const double *__restrict__ V, int64_t ldv, int nv,
-                                                         const double *__restrict__ hprev, double *__restrict__ w,
+                                                         const double *__restrict__ hprev, const double *__restrict__ w,
                                                          double *__restrict__ part, int nb, double *__restrict__ out,
                                                          unsigned int *__restrict__ ticket)
 {
     constexpr int NWV = DOT_BLOCK / 64;
-    __shared__ double sh[CGS_MAX][NWV];
+    __shared__ double sh[CGS_JG][NWV];
     __shared__ bool last;
-    const int b = blockIdx.x;
+    const int b = blockIdx.x, j0 = blockIdx.y * CGS_JG;
+    const int nj = min(CGS_JG, nv - j0);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t base = (int64_t)b * DOT_BLOCK * DOT_PER_THREAD;
     double wl[DOT_PER_THREAD];
@@ -46,43 +48,37 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_cgs_dots(int64_t n, const double 
         double x = 0.0;
         if (i < n) {
             x = w[i];
-            if (hprev) {
+            if (hprev)
                 for (int j = 0; j < nv; ++j)
                     x -= hprev[j] * V[(int64_t)j * ldv + i];
-                w[i] = x;
-            }
         }
         wl[k] = x;
     }
-    for (int j0 = 0; j0 < nv; j0 += CGS_MAX) {
-        const int nj = min(CGS_MAX, nv - j0);
-        for (int jj = 0; jj < nj; ++jj) {
-            const double *v = V + (int64_t)(j0 + jj) * ldv;
-            double s = 0.0;
+    for (int jj = 0; jj < nj; ++jj) {
+        const double *v = V + (int64_t)(j0 + jj) * ldv;
+        double s = 0.0;
 #pragma unroll
-            for (int k = 0; k < DOT_PER_THREAD; ++k) {
-                const int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
-                if (i < n)
-                    s += v[i] * wl[k];
-            }
-            for (int off = 32; off > 0; off >>= 1)
-                s += __shfl_down(s, off, 64);
-            if (lane == 0)
-                sh[jj][wv] = s;
+        for (int k = 0; k < DOT_PER_THREAD; ++k) {
+            const int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
+            if (i < n)
+                s += v[i] * wl[k];
         }
-        __syncthreads();
-        if ((int)threadIdx.x < nj) {
-            double t = 0.0;
-            for (int k = 0; k < NWV; ++k)
-                t += sh[threadIdx.x][k];
-            part[(int64_t)(j0 + threadIdx.x) * nb + b] = t;
-        }
-        __syncthreads();
+        for (int off = 32; off > 0; off >>= 1)
+            s += __shfl_down(s, off, 64);
+        if (lane == 0)
+            sh[jj][wv] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nj) {
+        double t = 0.0;
+        for (int k = 0; k < NWV; ++k)
+            t += sh[threadIdx.x][k];
+        part[(int64_t)(j0 + threadIdx.x) * nb + b] = t;
     }
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0)
-        last = atomicAdd(ticket, 1u) == (unsigned)(nb - 1);
+        last = atomicAdd(ticket, 1u) == (unsigned)(nb * gridDim.y - 1);
     __syncthreads();
     if (!last)
         return;
@@ -97,10 +93,12 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_cgs_dots(int64_t n, const double 
         *ticket = 0u;
 }
 
-// w -= sum_{j<nv} h[j] V_j, and |w|^2 into *nrm2 (same last-block scheme)
+// w -= sum_{j<nv} (h1[j] + h2[j]) V_j (both Gram-Schmidt passes), and |w|^2
+// into *nrm2 (same last-block scheme)
 __global__ __launch_bounds__(DOT_BLOCK) void k_update_norm(int64_t n, const double *__restrict__ V, int64_t ldv,
-                                                            int nv, const double *__restrict__ h,
-                                                            double *__restrict__ w, double *__restrict__ part, int nb,
+                                                            int nv, const double *__restrict__ h1,
+                                                            const double *__restrict__ h2, double *__restrict__ w,
+                                                            double *__restrict__ part, int nb,
                                                             double *__restrict__ nrm2, unsigned int *__restrict__ ticket)
 {
     __shared__ double sh[DOT_BLOCK / 64];
@@ -113,7 +111,7 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_update_norm(int64_t n, const doub
         if (i < n) {
             double x = w[i];
             for (int j = 0; j < nv; ++j)
-                x -= h[j] * V[(int64_t)j * ldv + i];
+                x -= (h1[j] + h2[j]) * V[(int64_t)j * ldv + i];
             w[i] = x;
             s += x * x;
         }
@@ -215,10 +213,11 @@ KrylovWork *get_work(fmmbem_ctx *ctx, int m)
 }
 
 // out[0..nv) = V_j . w  (device); with hprev, w -= sum_j hprev[j] V_j first
-void multidot(KrylovWork *kw, const double *V, int nv, double *w, double *out, hipStream_t st,
+void multidot(KrylovWork *kw, const double *V, int nv, const double *w, double *out, hipStream_t st,
               const double *hprev = nullptr)
 {
-    k_cgs_dots<<<kw->nb, DOT_BLOCK, 0, st>>>(kw->n, V, kw->n, nv, hprev, w, kw->part, kw->nb, out, kw->ticket);
+    dim3 grid(kw->nb, (nv + CGS_JG - 1) / CGS_JG);
+    k_cgs_dots<<<grid, DOT_BLOCK, 0, st>>>(kw->n, V, kw->n, nv, hprev, w, kw->part, kw->nb, out, kw->ticket);
     FB_HIP(hipGetLastError());
 }
 
@@ -262,10 +261,13 @@ GmresState::GmresState(fmmbem_ctx *c, const double *b_, double tol_, const fmmbe
     g.assign(m + 1, 0.0);
     yv.assign(m, 0.0);
     FB_HIP(hipHostMalloc((void **)&hbuf, sizeof(double) * 2 * (m + 2), hipHostMallocDefault));
+    FB_HIP(hipEventCreateWithFlags(&ev_h, hipEventDisableTiming));
 }
 
 GmresState::~GmresState()
 {
+    if (ev_h)
+        (void)hipEventDestroy(ev_h);
     if (hbuf)
         (void)hipHostFree(hbuf);
 }
@@ -326,13 +328,25 @@ void GmresState::enqueue_step()
     ++matvecs;
     multidot(kw, kw->V, k + 1, kw->w, kw->h, st);
     multidot(kw, kw->V, k + 1, kw->w, kw->h + (m + 2), st, kw->h);
-    k_update_norm<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->V, n, k + 1, kw->h + (m + 2), kw->w, kw->part, kw->nb,
-                                                kw->h + (k + 1), kw->ticket + (m + 1));
+    k_update_norm<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->V, n, k + 1, kw->h, kw->h + (m + 2), kw->w, kw->part,
+                                                kw->nb, kw->h + (k + 1), kw->ticket + (m + 1));
     FB_HIP(hipGetLastError());
     k_normalize<<<grid_for(n, 256), 256, 0, st>>>(n, kw->w, kw->h + (k + 1), vn);
     FB_HIP(hipGetLastError());
     // h1[0..k], |w|^2 at k + 1, and h2[0..k] at m + 2: one copy
     FB_HIP(hipMemcpyAsync(hbuf, kw->h, sizeof(double) * (m + 2 + k + 1), hipMemcpyDeviceToHost, st));
+    FB_HIP(hipEventRecord(ev_h, st));
+    // While the host waits for the column, start the near field of the next
+    // mat-vec (its input is v_{k+1}).  Its precision follows the schedule at
+    // a residual extrapolated from the last two (a hundredth of the last one when
+    // there is no ratio yet); nothing is started where the extrapolated
+    // residual already meets the tolerance or the cycle ends.
+    if (k + 1 < m && it + 1 < s.max_iter) {
+        const double ratio = rho_prev2 > 0.0 ? std::min(1.0, rho_prev / rho_prev2) : 0.01;
+        const double rho_next = rho_prev * ratio;
+        if (rho_next > tol)
+            prefetch_near(ctx, choose(&s, rho_next, tol).prec, vn, st);
+    }
 }
 
 void GmresState::end_cycle()
@@ -369,6 +383,7 @@ void GmresState::end_cycle()
     } else {
         ++restarts;
         rho_prev = true_rel;  // the schedule continues from the true residual
+        rho_prev2 = -1.0;
         begin_cycle();
     }
 }
@@ -376,7 +391,7 @@ void GmresState::end_cycle()
 void GmresState::complete_step()
 {
     const int m = s.restart;
-    FB_HIP(hipStreamSynchronize(st));
+    FB_HIP(hipEventSynchronize(ev_h));
     for (int j = 0; j <= k; ++j)
         H[(size_t)j * m + k] = hbuf[j] + hbuf[m + 2 + j];
     double hn = std::sqrt(hbuf[k + 1]);
@@ -397,6 +412,7 @@ void GmresState::complete_step()
     rel = std::fabs(g[k + 1]) / bnorm;
     FB_REQUIRE(std::isfinite(rel), FMMBEM_EINTERNAL, "non-finite residual in GMRES");
     record(cur.p, cur.prec, rel);
+    rho_prev2 = rho_prev;
     rho_prev = rel;
     ++it;
     ++k;
