@@ -382,25 +382,173 @@ __global__ void k_m2m_sum(int p, int ncs, int npar, const int32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// M2L (a7), in two passes.
-// Pass 1, one block per chunk of pairs sharing a translation (D, eT, eS): the
-// tabulated I_n^m(D 2^-e) sits in LDS; thread (slot, k, l) computes, for PB
-// pairs at once,
-//   L_k^l = (-1)^k 2^(-eT (k+1)) sum_{n,m} 2^(-eS n) M_n^m I_{n+k}^{m+l}
-// (the scaled form of L = sum M I with sigma the larger half-size), and writes
-// it to Y[pair].  Pass 2 sums Y over each target's pairs in list order.
+// M2L (a7), in two passes.  Pass 1, one block per chunk of pairs sharing a
+// translation (D, eT, eS), computes per pair the scaled translation
+//   L_k^l = (-1)^k 2^(-eT (k+1)) sum_{n,m} 2^(-eS n) M_n^m I_{n+k}^{m+l}(D 2^-e)
+// (sigma the larger half-size) and writes it to Y[pair]; pass 2 sums Y over
+// each target's pairs in list order.
+// Pass 1 is a dense product per chunk, on the matrix cores.  With
+// X = a + ib a stored coefficient (m >= 0) and X_n^-m = (-1)^m conj(X), the
+// terms of m and -m combine into a real map: for output (k, l) and input
+// (n, m), with P = I_{n+k}^{m+l}, Q = (-1)^m I_{n+k}^{l-m} (Q = 0 for m = 0),
+// S = P + Q and D = P - Q,
+//   Re L += a S.re - b D.im,   Im L += a S.im + b D.re,
+// times (-1)^k 2^(-eT (k+1)) 2^(-eS n).  Rows of the real operator A are
+// (k, l, re/im), inputs (n, m, re/im), columns (pair, channel): Y = A X.
+// Wave w takes the 16-row tiles w, w + 4, ...; each lane generates its
+// element of A for every 16x16x4 step from the key's table in LDS, and the
+// step runs all (at most 4) column tiles of the chunk, whose inputs the lanes
+// load from the multipole array (L2-resident).  Lane layout
+// (both precisions): A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; the
+// result D[i][j] is element i % 4 of lane j + 16 (i / 4) in FP32 and element
+// i / 4 of lane j + 16 (i % 4) in FP64.  The Stokes
+// change of centre of the fourth channel is applied when Y is summed.
+template <typename R> struct Acc4;
+template <> struct Acc4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+template <> struct Acc4<float> { typedef float type __attribute__((ext_vector_type(4))); };
+
+__device__ __forceinline__ Acc4<double>::type mfma_16x16x4(double a, double b, Acc4<double>::type c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ Acc4<float>::type mfma_16x16x4(float a, float b, Acc4<float>::type c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename R, int NCH>
+__global__ __launch_bounds__(256) void k_m2l_mfma(int p, int ncs, int q_tab, const int32_t *__restrict__ chunk_begin,
+                                                  const int32_t *__restrict__ chunk_trans,
+                                                  const uint64_t *__restrict__ trans_key,
+                                                  const int32_t *__restrict__ pair_sorted,
+                                                  const int32_t *__restrict__ pairs, const cplx<R> *__restrict__ table,
+                                                  const cplx<R> *__restrict__ M, cplx<R> *__restrict__ Y)
+{
+    typedef typename Acc4<R>::type acc_t;
+    constexpr int NT = 4;  // column tiles of a chunk (at most 64 columns)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int q = 2 * p;
+    const int fq = (q + 1) * (q + 1), nc = ncoef(p), Dp = 2 * nc, Kp = (Dp + 3) & ~3, nrt = (Dp + 15) / 16;
+    cplx<R> *It = reinterpret_cast<cplx<R> *>(smem_raw);    // [(q+1)^2]
+    uint16_t *qnm = reinterpret_cast<uint16_t *>(It + fq);  // [nc]: n | m << 8
+    const int c = blockIdx.x;
+    const int u = chunk_trans[c], pb = chunk_begin[c], pe = chunk_begin[c + 1];
+    const uint64_t key = trans_key[u];
+    const int eT = (int)((key >> 48) & 63), eS = (int)((key >> 54) & 63);
+    const cplx<R> *tab = table + (int64_t)u * (q_tab + 1) * (q_tab + 1);
+    for (int t = threadIdx.x; t < fq; t += blockDim.x)
+        It[t] = tab[t];
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+        int n, m;
+        idx_to_nm(t, n, m);
+        qnm[t] = (uint16_t)(n | (m << 8));
+    }
+    __syncthreads();
+    const int ncol = (pe - pb) * NCH, nct = (ncol + 15) / 16;  // nct <= NT
+    const int nwave = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int pin = lk & 1;  // re/im part of this lane's input (fixed: steps advance k by 4)
+    // this lane's B column of each tile: the multipole coefficients of a source box, as reals
+    const R *bcol[NT];
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+        const int col = ct * 16 + li;
+        bcol[ct] = nullptr;
+        if (col < ncol) {
+            const int pl = col / NCH, ch = col - pl * NCH;
+            const int S = pairs[2 * pair_sorted[pb + pl] + 1];
+            bcol[ct] = reinterpret_cast<const R *>(M + ((int64_t)S * NCH + ch) * ncs);
+        }
+    }
+    for (int rt = w; rt < nrt; rt += nwave) {
+        const int r = rt * 16 + li;  // operator row of this lane's A elements
+        const bool rv = r < Dp;
+        int k = 0, l = 0;
+        if (rv) {
+            const int e = qnm[r >> 1];
+            k = e & 0xff;
+            l = e >> 8;
+        }
+        const int po = r & 1;
+        // sign of the whole entry and the component (re/im) it takes from P and Q
+        const R sall = (po == 0 && pin == 1) ? R(-1) : R(1);
+        const bool take_im = (po ^ pin) != 0;
+        const R f = rv ? sall * (R)ldexp((k & 1) ? -1.0 : 1.0, -eT * (k + 1)) : R(0);
+        acc_t acc[NT];
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+            acc[ct] = acc_t{0, 0, 0, 0};
+#pragma unroll 2
+        for (int q0 = 0; q0 < Kp; q0 += 4) {
+            const int qi = q0 + lk;
+            const bool qv = qi < Dp;
+            R a = 0;
+            if (rv && qv) {
+                const int e = qnm[qi >> 1];
+                const int n = e & 0xff, m = e >> 8;
+                const cplx<R> *row = It + (n + k) * (n + k + 1);  // I_{n+k}^{0}
+                const cplx<R> P = row[l + m];
+                R pc = take_im ? P.im : P.re;
+                if (m > 0) {
+                    const cplx<R> Q = row[l - m];
+                    const R qc = take_im ? Q.im : Q.re;
+                    // (-1)^m from Q, and + for S (pin 0) or - for D (pin 1)
+                    pc += (((m & 1) != 0) != (pin != 0)) ? -qc : qc;
+                }
+                a = (R)ldexp(f * pc, -eS * n);
+            }
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                if (ct < nct) {
+                    const R b = (qv && bcol[ct]) ? bcol[ct][qi] : R(0);
+                    acc[ct] = mfma_16x16x4(a, b, acc[ct]);
+                }
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+            const int col = ct * 16 + li;
+            if (ct >= nct || col >= ncol)
+                continue;
+            const int pl = col / NCH, ch = col - pl * NCH;
+            R *dst = reinterpret_cast<R *>(Y + ((int64_t)pair_sorted[pb + pl] * NCH + ch) * nc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // output element v of this lane: row 4 lk + v (FP32 form), 4 v + lk (FP64 form)
+                const int row = rt * 16 + (sizeof(R) == 8 ? 4 * v + lk : 4 * lk + v);
+                if (row < Dp)
+                    dst[row] = acc[ct][v];
+            }
+        }
+    }
+}
+
+// LDS of k_m2l_mfma: the key's table and the (n, m) index
+template <typename R> size_t m2l_mfma_shm(int p)
+{
+    const int q = 2 * p;
+    return sizeof(cplx<R>) * (size_t)(q + 1) * (q + 1) + sizeof(uint16_t) * (size_t)ncoef(p);
+}
+
+// The same pass 1 on the vector units, used for FP64 (where the generated
+// operator is reused too little for the matrix cores to pay): lane = real
+// output row r = (k, l, re/im) of one 64-row group; for PB pairs of the chunk
+// at once (their coefficients wave-uniform, scalar loads) and every input
+// (n, m), the lane forms its two operator entries (for a and b) from P and Q
+// in LDS and adds them times (a, b) of each pair; Horner in n applies the
+// 2^(-eS n) scaling.
 template <typename R, int NCH, int PB>
-__global__ __launch_bounds__(256) void k_m2l_group(int p, int ncs, int q_tab, const int32_t *__restrict__ chunk_begin,
-                                                   const int32_t *__restrict__ chunk_trans,
-                                                   const uint64_t *__restrict__ trans_key,
-                                                   const int32_t *__restrict__ pair_sorted,
-                                                   const int32_t *__restrict__ pairs, const double *__restrict__ box_r,
-                                                   const cplx<R> *__restrict__ table, const cplx<R> *__restrict__ M,
-                                                   cplx<R> *__restrict__ Y)
+__global__ __launch_bounds__(256) void k_m2l_valu(int p, int ncs, int q_tab, const int32_t *__restrict__ chunk_begin,
+                                                  const int32_t *__restrict__ chunk_trans,
+                                                  const uint64_t *__restrict__ trans_key,
+                                                  const int32_t *__restrict__ pair_sorted,
+                                                  const int32_t *__restrict__ pairs, const cplx<R> *__restrict__ table,
+                                                  const cplx<R> *__restrict__ M, cplx<R> *__restrict__ Y)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int q = 2 * p;
-    const int fq = (q + 1) * (q + 1), nc = ncoef(p);
+    const int fq = (q + 1) * (q + 1), nc = ncoef(p), Dp = 2 * nc;
     cplx<R> *It = reinterpret_cast<cplx<R> *>(smem_raw);
     const int c = blockIdx.x;
     const int u = chunk_trans[c], pb = chunk_begin[c], pe = chunk_begin[c + 1];
@@ -410,121 +558,111 @@ __global__ __launch_bounds__(256) void k_m2l_group(int p, int ncs, int q_tab, co
     for (int t = threadIdx.x; t < fq; t += blockDim.x)
         It[t] = tab[t];
     __syncthreads();
-    // waves take PB-pair batches in turn; lanes are output coefficients (k, l)
     const int nwave = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const R rS = (R)ldexp(1.0, -eS);
-    for (int o0 = 0; o0 < nc; o0 += 64) {
-        const int idx = o0 + lane;
-        const bool active = idx < nc;
+    const int ngrp = (Dp + 63) / 64, nbat = (pe - pb + PB - 1) / PB;
+    for (int task = wv; task < ngrp * nbat; task += nwave) {
+        const int g = task % ngrp, base = pb + (task / ngrp) * PB;
+        const int r = g * 64 + lane;
+        const bool active = r < Dp;
         int k = 0, l = 0;
-        idx_to_nm(active ? idx : 0, k, l);
+        idx_to_nm(active ? r >> 1 : 0, k, l);
+        const bool po = (r & 1) != 0;
         const R f = (R)ldexp((k & 1) ? -1.0 : 1.0, -eT * (k + 1));
-        for (int base = pb + wv * PB; base < pe; base += nwave * PB) {
-            int Sb[PB];
+        const cplx<R> *Mb[PB];
 #pragma unroll
-            for (int j = 0; j < PB; ++j)
-                Sb[j] = base + j < pe ? pairs[2 * pair_sorted[base + j] + 1] : pairs[2 * pair_sorted[base] + 1];
-            R are[PB][NCH], aim[PB][NCH];
+        for (int j = 0; j < PB; ++j) {
+            const int e = base + j < pe ? base + j : base;  // a short batch repeats its first pair
+            // wave-uniform: the coefficients come through the scalar cache
+            const int S = __builtin_amdgcn_readfirstlane(pairs[2 * pair_sorted[e] + 1]);
+            Mb[j] = M + (int64_t)S * NCH * ncs;
+        }
+        R acc[PB][NCH];
+#pragma unroll
+        for (int j = 0; j < PB; ++j)
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                acc[j][ch] = 0;
+        for (int n = p; n >= 0; --n) {
 #pragma unroll
             for (int j = 0; j < PB; ++j)
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch)
-                    are[j][ch] = aim[j][ch] = 0;
-            // Horner in n: acc = acc * 2^-eS + sum_m M_n^m I_{n+k}^{m+l}, n = p..0
-            for (int n = p; n >= 0; --n) {
+                    acc[j][ch] *= rS;
+            const cplx<R> *row = It + (n + k) * (n + k + 1) + l;  // I_{n+k}^{l + .}
+#pragma unroll 2
+            for (int m = 0; m <= n; ++m) {
+                const cplx<R> P = row[m];
+                R qr = 0, qi = 0;
+                if (m > 0) {
+                    const cplx<R> Q = row[-m];
+                    const R sg = (m & 1) ? R(-1) : R(1);
+                    qr = sg * Q.re;
+                    qi = sg * Q.im;
+                }
+                // entries for a (re part of the input) and b (im part)
+                const R ea = po ? P.im + qi : P.re + qr;
+                const R eb = po ? P.re - qr : qi - P.im;
+                const int ci = cidx(n, m);
 #pragma unroll
                 for (int j = 0; j < PB; ++j)
 #pragma unroll
                     for (int ch = 0; ch < NCH; ++ch) {
-                        are[j][ch] *= rS;
-                        aim[j][ch] *= rS;
+                        const cplx<R> x = Mb[j][ch * ncs + ci];
+                        acc[j][ch] += ea * x.re;
+                        acc[j][ch] += eb * x.im;
                     }
-                const cplx<R> *Irow = It + (n + k) * (n + k) + (n + k) + l;
-                // m = 0 and the pairs (m, -m), m > 0, with M_n^-m = (-1)^m conj(M_n^m):
-                // M_n^m I^{l+m} + (-1)^m conj(M_n^m) I^{l-m}
-                {
-                    const cplx<R> iv = Irow[0];
-#pragma unroll
-                    for (int j = 0; j < PB; ++j)
-#pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch) {
-                            const cplx<R> mv = M[((int64_t)Sb[j] * NCH + ch) * ncs + cidx(n, 0)];
-                            are[j][ch] += mv.re * iv.re;
-                            are[j][ch] -= mv.im * iv.im;
-                            aim[j][ch] += mv.re * iv.im;
-                            aim[j][ch] += mv.im * iv.re;
-                        }
-                }
-#pragma unroll 2
-                for (int m = 1; m <= n; ++m) {
-                    const cplx<R> ip = Irow[m], in0 = Irow[-m];
-                    const R sg = (m & 1) ? R(-1) : R(1);
-                    const cplx<R> iq{sg * in0.re, sg * in0.im};
-#pragma unroll
-                    for (int j = 0; j < PB; ++j)
-#pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch) {
-                            const cplx<R> mv = M[((int64_t)Sb[j] * NCH + ch) * ncs + cidx(n, m)];
-                            are[j][ch] += mv.re * ip.re;
-                            are[j][ch] -= mv.im * ip.im;
-                            aim[j][ch] += mv.re * ip.im;
-                            aim[j][ch] += mv.im * ip.re;
-                            are[j][ch] += mv.re * iq.re;
-                            are[j][ch] += mv.im * iq.im;
-                            aim[j][ch] += mv.re * iq.im;
-                            aim[j][ch] -= mv.im * iq.re;
-                        }
-                }
             }
-            if (!active)
+        }
+        if (!active)
+            continue;
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            if (base + j >= pe)
                 continue;
+            const int orig = pair_sorted[base + j];
 #pragma unroll
-            for (int j = 0; j < PB; ++j) {
-                if (base + j >= pe)
-                    continue;
-                const int orig = pair_sorted[base + j];
-                R o_re[NCH], o_im[NCH];
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    o_re[ch] = f * are[j][ch];
-                    o_im[ch] = f * aim[j][ch];
-                }
-                if constexpr (NCH == 4) {
-                    // change of centre of Phi_4 from c_S to c_T
-                    const double *cT = box_r + 5 * (int64_t)pairs[2 * orig], *cS = box_r + 5 * (int64_t)pairs[2 * orig + 1];
-                    const R g0 = (R)(cS[0] - cT[0]), g1 = (R)(cS[1] - cT[1]), g2 = (R)(cS[2] - cT[2]);
-                    o_re[3] += g0 * o_re[0] + g1 * o_re[1] + g2 * o_re[2];
-                    o_im[3] += g0 * o_im[0] + g1 * o_im[1] + g2 * o_im[2];
-                }
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch)
-                    Y[((int64_t)orig * NCH + ch) * nc + idx] = cplx<R>{o_re[ch], o_im[ch]};
-            }
+            for (int ch = 0; ch < NCH; ++ch)
+                reinterpret_cast<R *>(Y + ((int64_t)orig * NCH + ch) * nc)[r] = f * acc[j][ch];
         }
     }
 }
 
 // Pass 2: L(T) = sum of Y over T's pairs (CSR order), all boxes; thread =
-// (pair slice, output), slices summed in a fixed order.
-template <typename R, int NCH>
+// (pair slice, output), slices summed in a fixed order.  With FIXC (Stokes
+// after k_m2l_mfma) the fourth channel of each pair also changes centre from
+// c_S to c_T: Y_3 + (c_S - c_T) . (Y_0, Y_1, Y_2).
+template <typename R, int NCH, bool FIXC>
 __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ src, const double *__restrict__ box_r,
                                                     const cplx<R> *__restrict__ Y, cplx<R> *__restrict__ L)
 {
     __shared__ cplx<R> red[256];
     const int T = blockIdx.x;
-    const int no = NCH * ncoef(p);
+    const int nc = ncoef(p), no = NCH * nc;
     const int e0 = ptr[T], e1 = ptr[T + 1];
+    const double *cT = box_r + 5 * (int64_t)T;
     for (int o0 = 0; o0 < no; o0 += blockDim.x) {
         const int span = min((int)blockDim.x, no - o0);
         const int sl = threadIdx.x / span, t = o0 + threadIdx.x % span;
         const int nsl_here = max(1, (int)blockDim.x / span);
+        const int ch = t / nc, idx = t - ch * nc;
         R sr = 0, si = 0;
         if (sl < nsl_here) {
             for (int e = e0 + sl; e < e1; e += nsl_here) {
                 const cplx<R> v = Y[(int64_t)e * no + t];
                 sr += v.re;
                 si += v.im;
+                if constexpr (FIXC) {
+                    if (ch == 3) {
+                        const double *cS = box_r + 5 * (int64_t)src[e];
+                        const R g0 = (R)(cS[0] - cT[0]), g1 = (R)(cS[1] - cT[1]), g2 = (R)(cS[2] - cT[2]);
+                        const cplx<R> *y = Y + (int64_t)e * no + idx;
+                        sr += g0 * y[0].re + g1 * y[nc].re + g2 * y[2 * nc].re;
+                        si += g0 * y[0].im + g1 * y[nc].im + g2 * y[2 * nc].im;
+                    }
+                }
             }
         }
         __syncthreads();
@@ -536,7 +674,6 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_
                 ar += red[k * span + threadIdx.x].re;
                 ai += red[k * span + threadIdx.x].im;
             }
-            const int ch = t / ncoef(p), idx = t - ch * ncoef(p);
             L[((int64_t)T * NCH + ch) * ncs + idx] = cplx<R>{ar, ai};
         }
     }
@@ -963,20 +1100,26 @@ void launch_fmm(fmmbem_ctx *ctx, int p, hipStream_t st)
 
         stage_begin(ctx, SO + 1, st, &ev);
         {
-            constexpr int PB = NCH == 1 ? 4 : 1;
-            const int threads = 256;
-            const size_t shm = sizeof(cplx<R>) * ((size_t)(2 * p + 1) * (2 * p + 1));
             const cplx<R> *table;
             if constexpr (sizeof(R) == 8)
                 table = P.table64;
             else
                 table = P.table32;
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
-            k_m2l_group<R, NCH, PB><<<P.n_chunks, threads, shm, st>>>(p, ncs, P.q, P.chunk_begin, P.chunk_trans,
-                                                                      P.trans_key, P.pair_sorted, T.m2l_pairs,
-                                                                      T.box_r, table, M, Y);
+            if constexpr (sizeof(R) == 4) {
+                k_m2l_mfma<R, NCH><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), st>>>(
+                    p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
+            } else {
+                constexpr int PB = NCH == 1 ? 8 : 2;
+                const size_t shm = sizeof(cplx<R>) * (size_t)(2 * p + 1) * (2 * p + 1);
+                k_m2l_valu<R, NCH, PB><<<P.n_chunks, 256, shm, st>>>(
+                    p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
+            }
             FB_HIP(hipGetLastError());
-            k_m2l_reduce<R, NCH><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, Y, L);
+            if constexpr (NCH == 4)
+                k_m2l_reduce<R, NCH, true><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
+            else
+                k_m2l_reduce<R, NCH, false><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             FB_HIP(hipGetLastError());
         }
         stage_end(ctx, SO + 1, st, ev, 4.0 * (p + 1) * (p + 1) * (p + 1) * (p + 2) * NCH * (double)T.n_m2l);

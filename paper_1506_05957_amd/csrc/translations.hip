@@ -351,7 +351,9 @@ void build_translations(fmmbem_ctx *ctx, hipStream_t st)
         FB_HIP(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st));
         FB_HIP(hipStreamSynchronize(st));
         FB_REQUIRE(hovf == 0, FMMBEM_EINTERNAL, "M2L translation key out of range");
-        // distinct keys and chunks of at most M2L_CHUNK pairs with one key
+        // distinct keys and chunks of at most M2L_CHUNK / nch pairs with one key
+        // (at most 64 columns of pair x channel)
+        const int chunk = M2L_CHUNK / ctx->nch;
         std::vector<uint64_t> ukeys;
         std::vector<int32_t> cbeg, cu;
         for (int64_t i = 0; i < n;) {
@@ -360,7 +362,7 @@ void build_translations(fmmbem_ctx *ctx, hipStream_t st)
                 ++j;
             int u = (int)ukeys.size();
             ukeys.push_back(hk[i]);
-            for (int64_t a = i; a < j; a += M2L_CHUNK) {
+            for (int64_t a = i; a < j; a += chunk) {
                 cbeg.push_back((int32_t)a);
                 cu.push_back(u);
             }
