@@ -10,9 +10,12 @@ FP32 P2P/expansions once eps_k >= 1e-5, FP64 Arnoldi), cycling over the five
 right-hand sides; inputs are resident in device memory before timing starts.
 The line also reports the fixed-p (p = 12, FP64) solve time, the FP64-only
 relaxed solve time, mat-vec rates, the per-stage split, the roofline of the
-dominant kernel and the oracle's CPU rate on a bounded sample.
+dominant kernel and the oracle's CPU rate on a bounded sample.  Two more
+sections, outside the timed region: the 64-cell Stokes case (131072 panels,
+relaxed mixed vs fixed p = 16 FP64) and a 512-request serving stream through
+the request loop (latency p50/p99 from arrival to done).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
 """
 from __future__ import annotations
 
@@ -66,6 +69,74 @@ def p2p_traffic(kernel: str):
     return float(rec["traffic_bytes_per_launch"])
 
 
+def stokes_cells(fb, syn, torch, dev):
+    """64 red-blood-cell surfaces (Evans-Fung, 2048 panels each, 131072 panels, 393216
+    unknowns) in uniform flow u = (1, 0, 0): relaxed mixed-precision solve (p 16 -> 4)
+    against fixed p = 16 in FP64, both to a relative residual of 1e-6."""
+    m = syn.rbc_scene(64, 4, 0)
+    t0 = time.perf_counter()
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=64, p_max=16))
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    u = torch.tensor(np.tile([1.0, 0.0, 0.0], m.n_panels), device=dev)
+    x = torch.empty_like(u)
+    relaxed = fb.schedule(fb.STOKES)
+    fixed = fb.schedule(fb.STOKES, rule=fb.FIXED, p_min=16, mixed=0)
+    fb.fmmbem_solve_ctx(ctx, u, 1e-6, relaxed, x)  # warm-up
+    out = {"workload": "stokes_sl_64rbc_2048panels_uniform_flow_tol1e-6", "panels": m.n_panels,
+           "unknowns": 3 * m.n_panels, "build_s": t_build}
+    for name, sched in (("relaxed_mixed", relaxed), ("fixed_p16_fp64", fixed)):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        rep = fb.fmmbem_solve_ctx(ctx, u, 1e-6, sched, x)
+        torch.cuda.synchronize()
+        out[name] = {"solve_s": time.perf_counter() - ts, "iterations": rep["iterations"],
+                     "restarts": rep["restarts"], "rel_res_true": rep["rel_res_true"],
+                     "converged": bool(rep["converged"])}
+    out["speedup_relaxed_vs_fixed"] = out["fixed_p16_fp64"]["solve_s"] / out["relaxed_mixed"]["solve_s"]
+    fb.fmmbem_destroy(ctx)
+    return out
+
+
+def serving(fb, syn, n_req=512, rate_hz=30.0):
+    """Serving stream: n_req solve requests with Poisson arrivals at rate_hz, each Laplace or
+    Stokes (1/2 each) on a sphere, ellipsoid (axes uniform in [0.5, 2]) or red-blood-cell
+    surface of 512 to 32768 panels (log-uniform), tol 1e-6, relaxed mixed schedule; the
+    request loop admits them by device-memory footprint.  Latency = arrival to done."""
+    reqs = syn.request_stream(n_req, rate_hz, 0)
+    work = []
+    for r in reqs:  # meshes and data before the clock starts
+        mesh = r.mesh()
+        kernel = fb.LAPLACE if r.kernel == "laplace" else fb.STOKES
+        bc = np.ones(mesh.n_panels) if kernel == fb.LAPLACE else np.tile([1.0, 0.0, 0.0], mesh.n_panels)
+        work.append((r, mesh, kernel, bc))
+    scheds = {fb.LAPLACE: fb.schedule(fb.LAPLACE), fb.STOKES: fb.schedule(fb.STOKES)}
+    srv = fb.fmmbem_server_create(hbm_budget_bytes=64 << 30, max_active=16, n_streams=4)
+    tickets = []
+    t0 = time.perf_counter()
+    for r, mesh, kernel, bc in work:
+        dt = r.arrival_s - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append((fb.fmmbem_submit(srv, mesh.xyz, mesh.tri, bc, kernel, 1e-6, scheds[kernel]),
+                        bc.shape[0], kernel, mesh.n_panels))
+    infos = []
+    for tk, n, kernel, npan in tickets:
+        _, info = fb.fmmbem_wait(srv, tk, n)
+        infos.append((info, kernel, npan))
+    fb.fmmbem_server_destroy(srv)
+    lat = np.array([i["finish_s"] - i["arrival_s"] for i, _, _ in infos])
+    wait = np.array([i["admit_s"] - i["arrival_s"] for i, _, _ in infos])
+    span = max(i["finish_s"] for i, _, _ in infos) - min(i["arrival_s"] for i, _, _ in infos)
+    return {"workload": f"{n_req} requests, Poisson {rate_hz:g}/s, Laplace|Stokes on sphere|ellipsoid|RBC, "
+                        f"512-32768 panels, tol 1e-6",
+            "latency_ms": {"p50": 1e3 * pct(lat, 50), "p99": 1e3 * pct(lat, 99), "max": 1e3 * float(lat.max())},
+            "queue_wait_ms": {"p50": 1e3 * pct(wait, 50), "p99": 1e3 * pct(wait, 99)},
+            "solves_per_s": n_req / span,
+            "converged": int(sum(int(i["converged"]) for i, _, _ in infos)),
+            "unknowns_per_s": sum((3 if k == fb.STOKES else 1) * p for _, k, p in infos) / span}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +144,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--level", type=int, default=6, help="sphere refinement: 8*4^level panels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 64-cell Stokes comparison and the serving stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -207,6 +280,13 @@ def main():
                          f"mat-vec ({t_mv:.1f}s) times {n_mv} mat-vecs (fixed-p iterations + true residual)",
                "matvec_s": t_mv}
 
+    cells = serve = None
+    if not args.no_extra:
+        print("bench: 64-cell Stokes case", file=sys.stderr, flush=True)
+        cells = stokes_cells(fb, syn, torch, dev)
+        print("bench: serving stream", file=sys.stderr, flush=True)
+        serve = serving(fb, syn)
+
     ms = 1e3 * t_total / args.steps
     out = {
         "metric": METRIC,
@@ -236,6 +316,8 @@ def main():
         "stage_ms": stage_split,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "stokes_64cells": cells,
+        "serving": serve,
         "build_s": t_build,
         "tree": {k: stats[k] for k in ("n_boxes", "n_leaves", "n_levels", "n_m2l", "n_p2p", "nnz_correction")},
     }
