@@ -85,3 +85,27 @@ def test_matvec_deterministic_and_argument_checks(orc):
     with pytest.raises(fb.FmmbemError):
         fb.fmmbem_matvec(ctx, 5, fb.FP64, xd, xd)
     fb.fmmbem_destroy(ctx)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_matvec_unchanged_by_solves(orc, kernel):
+    """A solve leaves work of its own in flight (the near field of an iteration
+    that never runs, on the context's second stream).  Mat-vecs after it, in
+    both precisions, must equal the same mat-vecs before it bit for bit."""
+    from paper_1506_05957_amd import fmmbem as fb
+    announce(f"mat-vec before/after solves, kernel {kernel}")
+    m = MESHES["sphere2048"]()
+    k = fb.LAPLACE if kernel == 0 else fb.STOKES
+    ctx = fb.fmmbem_build(m.xyz, m.tri, k, fb.params(p_max=12))
+    n = m.n_panels * (1 if kernel == 0 else 3)
+    x = syn.random_vector(n, 11)
+    before = [matvec(fb, ctx, p, prec, x) for p, prec in ((12, fb.FP64), (5, fb.FP32))]
+    b = to_dev(np.ones(n) if kernel == 0 else np.tile([1.0, 0.0, 0.0], m.n_panels))
+    for tol in (1e-6, 1e-8):
+        xs = torch.empty_like(b)
+        rep = fb.fmmbem_solve_ctx(ctx, b, tol, fb.schedule(k, p_init=12), xs)
+        assert rep["converged"]
+    after = [matvec(fb, ctx, p, prec, x) for p, prec in ((12, fb.FP64), (5, fb.FP32))]
+    for u, v in zip(before, after):
+        assert np.array_equal(u, v)
+    fb.fmmbem_destroy(ctx)
