@@ -49,7 +49,7 @@ def p2p_source_sha1() -> str:
     b = s.index("// ----", a)
     with open(os.path.join(csrc, "tree.hip")) as f:
         t = f.read()
-    a2 = t.index("// P2P work units.")
+    a2 = t.index("// P2P work units")
     b2 = t.index("}  // namespace", a2)
     return hashlib.sha1((s[a:b] + t[a2:b2]).encode()).hexdigest()
 
@@ -64,7 +64,11 @@ def p2p_traffic(kernel: str):
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    if rec.get("kernel") != kernel or rec.get("source_sha1") != p2p_source_sha1():
+    try:
+        sha = p2p_source_sha1()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_sha1") != sha:
         return None
     return float(rec["traffic_bytes_per_launch"])
 
