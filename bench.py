@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GMRES solve time & FMM matvec/s, relaxed vs fixed p at 1e-6 resid; p50/p99"
 PEAK_FP32_VALU = 157.3e12  # MI355X published FP32 vector peak
 PEAK_FP64_VALU = 78.6e12
+PEAK_HBM = 8.0e12  # bytes/s
 
 
 def pct(a, q):
@@ -73,13 +74,13 @@ def p2p_traffic(kernel: str):
     return float(rec["traffic_bytes_per_launch"])
 
 
-def stokes_cells(fb, syn, torch, dev):
+def stokes_cells(fb, syn, torch, dev, ncrit=64):
     """64 red-blood-cell surfaces (Evans-Fung, 2048 panels each, 131072 panels, 393216
     unknowns) in uniform flow u = (1, 0, 0): relaxed mixed-precision solve (p 16 -> 4)
     against fixed p = 16 in FP64, both to a relative residual of 1e-6."""
     m = syn.rbc_scene(64, 4, 0)
     t0 = time.perf_counter()
-    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=64, p_max=16))
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=ncrit, p_max=16))
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     u = torch.tensor(np.tile([1.0, 0.0, 0.0], m.n_panels), device=dev)
@@ -88,7 +89,7 @@ def stokes_cells(fb, syn, torch, dev):
     fixed = fb.schedule(fb.STOKES, rule=fb.FIXED, p_min=16, mixed=0)
     fb.fmmbem_solve_ctx(ctx, u, 1e-6, relaxed, x)  # warm-up
     out = {"workload": "stokes_sl_64rbc_2048panels_uniform_flow_tol1e-6", "panels": m.n_panels,
-           "unknowns": 3 * m.n_panels, "build_s": t_build}
+           "unknowns": 3 * m.n_panels, "ncrit": ncrit, "build_s": t_build}
     for name, sched in (("relaxed_mixed", relaxed), ("fixed_p16_fp64", fixed)):
         torch.cuda.synchronize()
         ts = time.perf_counter()
@@ -147,9 +148,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--level", type=int, default=6, help="sphere refinement: 8*4^level panels")
+    ap.add_argument("--ncrit", type=int, default=64, help="panels per leaf (N_CRIT) of the main workload")
+    ap.add_argument("--near", choices=("stored", "fly"), default="stored",
+                    help="near field of the main workload: stored block-sparse matrix or evaluated per mat-vec")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 64-cell Stokes comparison and the serving stream")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--cells-ncrit", type=int, default=64, help="N_CRIT of the 64-cell Stokes case")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -177,7 +183,7 @@ def main():
     nt = mesh.n_panels
     orders = syn.ylm_orders(0)
     rhs = [torch.tensor(syn.ylm_rhs(mesh, l, m), device=dev) for l, m in orders]
-    prm = fb.params(theta=0.5, ncrit=64, p_max=12)
+    prm = fb.params(theta=0.5, ncrit=args.ncrit, p_max=12, near_stored=int(args.near == "stored"))
     t0 = time.time()
     ctx = fb.fmmbem_build(mesh.xyz, mesh.tri, fb.LAPLACE, prm)
     torch.cuda.synchronize()
@@ -253,15 +259,27 @@ def main():
     dom = max(("p2p_fp32", "p2p_fp64", "m2l_fp32", "m2l_fp64"), key=lambda s: stage[s][0])
     t_ms, launches, flops = stage[dom]
     avg_s = t_ms / 1e3 / max(launches, 1)
-    achieved = flops / max(launches, 1) / avg_s
-    peak = PEAK_FP32_VALU if dom.endswith("fp32") else PEAK_FP64_VALU
-    kname = {"p2p_fp32": "k_p2p<float, false>", "p2p_fp64": "k_p2p<double, false>",
-             "m2l_fp32": "k_m2l_group<float, 1, 4> + k_m2l_reduce<float, 1>",
-             "m2l_fp64": "k_m2l_group<double, 1, 4> + k_m2l_reduce<double, 1>"}[dom]
-    roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": p2p_traffic(kname),
-                "avg_launch_us": avg_s * 1e6, "launches": launches,
-                "flops_per_launch": flops / max(launches, 1)}
+    stored = args.near == "stored"
+    if stored and dom.startswith("p2p"):
+        # the stored near field is an HBM-bound product: matrix entries plus the
+        # sorted input (read per unit from cache, counted once) and the result
+        word = 4 if dom.endswith("fp32") else 8
+        nbytes = stats["near_entries"] * word + 3 * 8 * nt
+        kname = "k_near_spmv<float, false>" if word == 4 else "k_near_spmv<double, false>"
+        achieved = nbytes / avg_s
+        roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None, "avg_launch_us": avg_s * 1e6,
+                    "launches": launches, "bytes_per_launch": nbytes}
+    else:
+        achieved = flops / max(launches, 1) / avg_s
+        peak = PEAK_FP32_VALU if dom.endswith("fp32") else PEAK_FP64_VALU
+        kname = {"p2p_fp32": "k_p2p<float, false>", "p2p_fp64": "k_p2p<double, false>",
+                 "m2l_fp32": "k_m2l_mfma<float, 1> + k_m2l_reduce<float, 1, false>",
+                 "m2l_fp64": "k_m2l_valu<double, 1, 8> + k_m2l_reduce<double, 1, false>"}[dom]
+        roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": peak / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": p2p_traffic(kname),
+                    "avg_launch_us": avg_s * 1e6, "launches": launches,
+                    "flops_per_launch": flops / max(launches, 1)}
 
     stage_split = {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in stage.items() if v[1]}
 
@@ -287,9 +305,10 @@ def main():
     cells = serve = None
     if not args.no_extra:
         print("bench: 64-cell Stokes case", file=sys.stderr, flush=True)
-        cells = stokes_cells(fb, syn, torch, dev)
-        print("bench: serving stream", file=sys.stderr, flush=True)
-        serve = serving(fb, syn)
+        cells = stokes_cells(fb, syn, torch, dev, args.cells_ncrit)
+        if not args.no_serving:
+            print("bench: serving stream", file=sys.stderr, flush=True)
+            serve = serving(fb, syn)
 
     ms = 1e3 * t_total / args.steps
     out = {
@@ -306,7 +325,7 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "laplace_sl_sphere32768_ylm_relaxed12to3_tol1e-6", "panels": nt,
-                   "rhs": [f"Y_{l}^{m}" for l, m in orders], "ncrit": 64, "theta": 0.5, "restart": 50},
+                   "rhs": [f"Y_{l}^{m}" for l, m in orders], "ncrit": args.ncrit, "theta": 0.5, "restart": 50, "near_field": args.near},
         "solve_ms": {"relaxed_mixed_p50": 1e3 * pct(times, 50), "relaxed_mixed_p99": 1e3 * pct(times, 99),
                      "relaxed_fp64_p50": 1e3 * pct(t_rel64, 50), "relaxed_fp64_p99": 1e3 * pct(t_rel64, 99),
                      "fixed_p12_fp64_p50": 1e3 * pct(t_fixed, 50), "fixed_p12_fp64_p99": 1e3 * pct(t_fixed, 99)},

@@ -86,6 +86,14 @@ typedef struct {
     int32_t ncrit;    /* most panels in a leaf box (Sec. 2.5), default 64, 1..1024 */
     int32_t p_max;    /* largest p the context will be asked for, 1..FMMBEM_P_MAX, default 16 */
     double mu;        /* Stokes viscosity, default 1 */
+    /* 1: the regular near field (the 4-point rule between neighbouring leaves,
+     * Sec. 2.3, the P2P of Sec. 2.5) is assembled once at build as a
+     * block-sparse matrix, FP64 and FP32 copies, and every mat-vec multiplies
+     * it (the paper's sparse near field).  Memory: 12 B per panel pair
+     * (Laplace), 108 B (Stokes); see fmmbem_stats.near_entries.
+     * 0 (default): evaluated on the fly by every mat-vec. */
+    int32_t near_stored;
+    int32_t reserved;  /* must be 0 */
 } fmmbem_params;
 
 typedef struct {
@@ -118,6 +126,7 @@ typedef struct {
     int64_t p2p_interactions;    /* sum over P2P pairs of |targets| * |sources| */
     int64_t nnz_correction;      /* near-singular + self entries (blocks for Stokes) */
     int64_t device_bytes;        /* device memory held by the context */
+    int64_t near_entries;        /* panel pairs of the stored near field (0 unless near_stored) */
 } fmmbem_stats;
 
 /* Defaults described above. */

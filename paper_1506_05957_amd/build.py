@@ -25,6 +25,7 @@ SOURCES = [
     ("near.hip", ["-ffp-contract=off"]),
     ("translations.hip", []),
     ("fmm.hip", []),
+    ("nearfield.hip", []),
     ("krylov.hip", []),
     ("api.hip", []),
     ("server.cpp", []),

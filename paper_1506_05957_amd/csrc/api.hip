@@ -100,6 +100,8 @@ void fmmbem_params_default(fmmbem_params *prm)
     prm->ncrit = 64;
     prm->p_max = 16;
     prm->mu = 1.0;
+    prm->near_stored = 0;
+    prm->reserved = 0;
 }
 
 void fmmbem_schedule_default(fmmbem_schedule *s, int kernel)
@@ -137,6 +139,8 @@ static void validate_params(const fmmbem_params *p)
     FB_REQUIRE(p->ncrit >= 1 && p->ncrit <= 1024, FMMBEM_EINVAL, "ncrit must be in [1, 1024]");
     FB_REQUIRE(p->p_max >= 1 && p->p_max <= FMMBEM_P_MAX, FMMBEM_EINVAL, "p_max must be in [1, 20]");
     FB_REQUIRE(p->mu > 0.0 && std::isfinite(p->mu), FMMBEM_EINVAL, "mu must be positive");
+    FB_REQUIRE(p->near_stored == 0 || p->near_stored == 1, FMMBEM_EINVAL, "near_stored must be 0 or 1");
+    FB_REQUIRE(p->reserved == 0, FMMBEM_EINVAL, "reserved must be 0");
 }
 
 int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *params, void *hip_stream,
@@ -168,6 +172,8 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         build_geometry_and_tree(ctx, mesh, st);
         build_correction(ctx, st);
         build_translations(ctx, st);
+        if (prm.near_stored)
+            build_near_matrix(ctx, st);
         const int ncs = ncoef(prm.p_max);
         ctx->charges = ctx->arena.alloc<double>((size_t)(kernel == FMMBEM_STOKES_SL ? 8 : 4) * ctx->nsrc);
         ctx->Y = ctx->arena.alloc<double>(2 * (size_t)std::max<int64_t>(ctx->tree.n_m2l, 1) * ctx->nch * ncs);
@@ -280,6 +286,7 @@ int fmmbem_get_stats(const fmmbem_ctx_t *ctx, fmmbem_stats *o)
     o->p2p_interactions = ctx->tree.p2p_interactions;
     o->nnz_correction = ctx->corr.nnz;
     o->device_bytes = ctx->arena.bytes + (ctx->kw ? ctx->kw->arena.bytes : 0);
+    o->near_entries = ctx->nearm.entries;
     return FMMBEM_OK;
     API_END
 }

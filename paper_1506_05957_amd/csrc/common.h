@@ -165,6 +165,25 @@ struct M2LPlan {
     void *Z = nullptr;                  // [nbox][nch][ncoef(p_max)] complex FP64: per-child M2M terms
 };
 
+// The regular near field stored as a block-sparse matrix (nearfield.hip): per
+// P2P unit (targets [tb, te) of one leaf), one dense block per source leaf of
+// its P2P list, n_u x n_S entries stored source-major ([j][i], Stokes
+// [j][a*3+b][i]), the target's own panel zero (it enters through the
+// correction).  FP64 values and an FP32 copy rounded from them.
+struct NearBlock {
+    int32_t j0, ns;  // first source panel (sorted order), source panels
+    int64_t off;     // first value
+};
+struct NearMatrix {
+    int64_t entries = 0;            // panel pairs
+    int64_t nblk = 0;
+    int32_t *blk_ptr = nullptr;     // [n_unit + 1]
+    NearBlock *blk = nullptr;       // [nblk]
+    double *v64 = nullptr;
+    float *v32 = nullptr;
+    double *xs = nullptr;           // [n] the mat-vec input in sorted panel order
+};
+
 // GMRES workspace, one per context (krylov.hip)
 struct KrylovWork {
     int m = 0;
@@ -205,6 +224,7 @@ struct fmmbem_ctx {
     double *y_far = nullptr;   // [n]
     fmmbem::Timing timing;
     fmmbem::KrylovWork *kw = nullptr;
+    fmmbem::NearMatrix nearm;
     // P2P runs on a stream of its own, concurrently with the far-field chain
     // (fork after the charges, join before the combine)
     hipStream_t side = nullptr;
@@ -272,6 +292,9 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
 // launch the near field (charges + P2P) of a mat-vec on x at precision prec
 // ahead of time; the next run_matvec with the same x and prec uses it
 void prefetch_near(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
+// stored near field (nearfield.hip): assemble at build; one product on stream st
+void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st);
+void launch_near_stored(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
 int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
               fmmbem_report *rep, hipStream_t st);
 void free_krylov(fmmbem_ctx *ctx);

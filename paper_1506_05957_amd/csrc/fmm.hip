@@ -1024,15 +1024,20 @@ void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
     FB_HIP(hipEventRecord(ctx->ev_fork, st));
     FB_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
     stage_begin(ctx, SO + 0, ctx->side, &ev);
-    if (T.n_unit > 0) {
-        const int per_xcd = (T.n_unit + 7) / 8;
-        k_p2p<R, STOKES><<<8 * per_xcd, 64 * P2P_WAVES, 0, ctx->side>>>(T.n_unit, per_xcd, T.p2p_unit, T.p2p_chunk,
-                                                                       T.p2p_choff, nt, G.tc, G.tc32, src,
-                                                                       ctx->y_near);
-        FB_HIP(hipGetLastError());
+    if (ctx->nearm.v64) {
+        // stored near field: 2 flops per matrix entry
+        launch_near_stored(ctx, sizeof(R) == 8 ? FMMBEM_FP64 : FMMBEM_FP32, x, ctx->side);
+        stage_end(ctx, SO + 0, ctx->side, ev, 2.0 * (STOKES ? 9.0 : 1.0) * (double)ctx->nearm.entries);
+    } else {
+        if (T.n_unit > 0) {
+            const int per_xcd = (T.n_unit + 7) / 8;
+            k_p2p<R, STOKES><<<8 * per_xcd, 64 * P2P_WAVES, 0, ctx->side>>>(
+                T.n_unit, per_xcd, T.p2p_unit, T.p2p_chunk, T.p2p_choff, nt, G.tc, G.tc32, src, ctx->y_near);
+            FB_HIP(hipGetLastError());
+        }
+        // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
+        stage_end(ctx, SO + 0, ctx->side, ev, (STOKES ? 30.0 : 12.0) * (double)(T.p2p_interactions - 4 * nt));
     }
-    // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
-    stage_end(ctx, SO + 0, ctx->side, ev, (STOKES ? 30.0 : 12.0) * (double)(T.p2p_interactions - 4 * nt));
     FB_HIP(hipEventRecord(ctx->ev_join, ctx->side));
     ctx->near_pending = true;
 }
@@ -1122,7 +1127,8 @@ void launch_fmm(fmmbem_ctx *ctx, int p, hipStream_t st)
                 k_m2l_reduce<R, NCH, false><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             FB_HIP(hipGetLastError());
         }
-        stage_end(ctx, SO + 1, st, ev, 4.0 * (p + 1) * (p + 1) * (p + 1) * (p + 2) * NCH * (double)T.n_m2l);
+        // real form: a (2 nc) x (2 nc) operator times each pair's coefficients, per channel
+        stage_end(ctx, SO + 1, st, ev, 8.0 * ncoef(p) * ncoef(p) * NCH * (double)T.n_m2l);
 
         stage_begin(ctx, SO + 3, st, &ev);
         // parents of level l - 1 into children of level l; levels above the

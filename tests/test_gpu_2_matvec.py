@@ -23,12 +23,13 @@ def matvec(fb, ctx, p, prec, x):
     return yd.cpu().numpy()
 
 
+@pytest.mark.parametrize("near_stored", [0, 1])
 @pytest.mark.parametrize("kernel,name", [(0, "sphere512"), (0, "rbc2048"), (1, "sphere512"), (1, "cells8x512")])
-def test_all_p2p_equals_dense(orc, kernel, name):
+def test_all_p2p_equals_dense(orc, kernel, name, near_stored):
     from paper_1506_05957_amd import fmmbem as fb
-    announce(f"all-P2P kernel={kernel} {name}")
+    announce(f"all-P2P kernel={kernel} {name} near_stored={near_stored}")
     m = MESHES[name]()
-    ctx = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(theta=1e-6, ncrit=32))
+    ctx = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(theta=1e-6, ncrit=32, near_stored=near_stored))
     assert fb.fmmbem_get_stats(ctx)["n_m2l"] == 0
     n = m.n_panels * (3 if kernel else 1)
     x = syn.random_vector(n, 5)
@@ -109,3 +110,27 @@ def test_matvec_unchanged_by_solves(orc, kernel):
     for u, v in zip(before, after):
         assert np.array_equal(u, v)
     fb.fmmbem_destroy(ctx)
+
+
+@pytest.mark.parametrize("kernel,name", [(0, "sphere8192"), (1, "cells8x512")])
+def test_stored_near_field_matches_on_the_fly(orc, kernel, name):
+    """Full FMM mat-vec with the near field stored vs evaluated on the fly: the
+    same operator up to rounding (FP64), FP32 within its rounding."""
+    from paper_1506_05957_amd import fmmbem as fb
+    announce(f"stored vs on-the-fly near field kernel={kernel} {name}")
+    m = MESHES[name]()
+    prm = dict(ncrit=64, p_max=12)
+    a = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(**prm))
+    b = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(**prm, near_stored=1))
+    sa, sb = fb.fmmbem_get_stats(a), fb.fmmbem_get_stats(b)
+    assert sa["near_entries"] == 0 and 4 * sb["near_entries"] == sb["p2p_interactions"]
+    n = m.n_panels * (3 if kernel else 1)
+    x = syn.random_vector(n, 21)
+    for p, prec, bar in ((12, fb.FP64, 1e-12), (6, fb.FP32, 1e-5)):
+        ya = matvec(fb, a, p, prec, x)
+        yb = matvec(fb, b, p, prec, x)
+        e = rel_l2(yb, ya)
+        announce(f"  p={p} prec={prec}: rel diff {e:.1e}")
+        assert e <= bar
+    fb.fmmbem_destroy(a)
+    fb.fmmbem_destroy(b)

@@ -109,6 +109,27 @@ def test_solve_parity_tight(orc, case, rule, mixed):
     fb.fmmbem_destroy(ctx)
 
 
+@pytest.mark.parametrize("case", ["laplace_sphere_ylm", "stokes_cells_u"])
+def test_solve_parity_stored_near_field(orc, case):
+    """Relaxed mixed solve with the near field stored as a block-sparse matrix
+    (the paper's configuration): the same parity bar as on the fly."""
+    from paper_1506_05957_amd import fmmbem as fb
+    kernel, mesh_name, rhs, p_init, p_min = CASES[case]
+    announce(f"solve parity {case} stored near field tol=1e-8")
+    m = MESHES[mesh_name]()
+    b = rhs(m)
+    xo = orc.solve(kernel, m.xyz, m.tri, b, tol=1e-11)[0]
+    ctx = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(ncrit=64, p_max=p_init, near_stored=1))
+    st = fb.fmmbem_get_stats(ctx)
+    assert 4 * st["near_entries"] == st["p2p_interactions"]
+    x, rep = solve(fb, ctx, b, 1e-8, fb.schedule(kernel, p_init=p_init, p_min=p_min))
+    err = compare(orc, kernel, mesh_name, m, x, xo)
+    announce(describe(rep, x, xo) + f" cmp={err:.1e}")
+    assert rep["converged"] and rep["rel_res_true"] <= 1e-7
+    assert err <= 1e-5
+    fb.fmmbem_destroy(ctx)
+
+
 @pytest.mark.parametrize("case", ["laplace_sphere_one", "stokes_sphere_u"])
 def test_solve_bench_tolerance(orc, case):
     from paper_1506_05957_amd import fmmbem as fb
