@@ -40,38 +40,50 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def p2p_source_sha1() -> str:
-    """Hash of the P2P kernel and its work-list builder (the code the HBM counters measured)."""
+# source regions the HBM counter records were taken on: file, first marker, end marker
+COUNTED_SOURCES = {
+    "k_p2p<float, false>": [("fmm.hip", "// P2P (a10)", "// ----"), ("tree.hip", "// P2P work units", "}  // namespace")],
+    "k_near_spmv<float, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
+    "k_near_spmv<double, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
+    "k_m2l_valu<double, 1, 8>": [("fmm.hip", "// The same pass 1 on the vector units", "// Pass 2:")],
+}
+
+
+def source_sha1(kernel: str) -> str:
+    """Hash of the source of a kernel (and of what builds its work lists)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1506_05957_amd", "csrc")
-    with open(os.path.join(csrc, "fmm.hip")) as f:
-        s = f.read()
-    a = s.index("// P2P (a10)")
-    b = s.index("// ----", a)
-    with open(os.path.join(csrc, "tree.hip")) as f:
-        t = f.read()
-    a2 = t.index("// P2P work units")
-    b2 = t.index("}  // namespace", a2)
-    return hashlib.sha1((s[a:b] + t[a2:b2]).encode()).hexdigest()
+    text = ""
+    for fname, first, end in COUNTED_SOURCES[kernel]:
+        with open(os.path.join(csrc, fname)) as f:
+            s = f.read()
+        a = s.index(first)
+        text += s[a:s.index(end, a + len(first))]
+    return hashlib.sha1(text.encode()).hexdigest()
 
 
-def p2p_traffic(kernel: str):
-    """HBM bytes per launch of the P2P kernel from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None once the kernel changed."""
-    path = os.path.join(ROOT, "profiles", "k_p2p_fp32_laplace_sphere32768_hbm_counters.md")
-    try:
-        with open(path) as f:
-            text = f.read()
-        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    except (OSError, IndexError, ValueError):
-        return None
-    try:
-        sha = p2p_source_sha1()
-    except (OSError, ValueError):
-        return None
-    if rec.get("kernel") != kernel or rec.get("source_sha1") != sha:
-        return None
-    return float(rec["traffic_bytes_per_launch"])
+def kernel_traffic(kernel: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter records
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when there is no
+    record or the kernel's source changed since the counters were taken."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*hbm_counters*.md"))):
+        try:
+            with open(path) as f:
+                text = f.read()
+            recs = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        except (OSError, IndexError, ValueError):
+            continue
+        for rec in recs if isinstance(recs, list) else [recs]:
+            if rec.get("kernel") != kernel:
+                continue
+            try:
+                if rec.get("source_sha1") != source_sha1(kernel):
+                    return None
+            except (OSError, ValueError, KeyError):
+                return None
+            return float(rec["traffic_bytes_per_launch"])
+    return None
 
 
 def stokes_cells(fb, syn, torch, dev, ncrit_relaxed=128, ncrit_fixed=256):
@@ -270,7 +282,7 @@ def main():
         kname = "k_near_spmv<float, false>" if word == 4 else "k_near_spmv<double, false>"
         achieved = nbytes / avg_s
         roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
-                    "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": None, "avg_launch_us": avg_s * 1e6,
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": kernel_traffic(kname), "avg_launch_us": avg_s * 1e6,
                     "launches": launches, "bytes_per_launch": nbytes}
     else:
         achieved = flops / max(launches, 1) / avg_s
@@ -279,7 +291,7 @@ def main():
                  "m2l_fp32": "k_m2l_mfma<float, 1> + k_m2l_reduce<float, 1, false>",
                  "m2l_fp64": "k_m2l_valu<double, 1, 8> + k_m2l_reduce<double, 1, false>"}[dom]
         roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": p2p_traffic(kname),
+                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": kernel_traffic(kname.split(" + ")[0]),
                     "avg_launch_us": avg_s * 1e6, "launches": launches,
                     "flops_per_launch": flops / max(launches, 1)}
 

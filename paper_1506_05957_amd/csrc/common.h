@@ -292,9 +292,11 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
 // launch the near field (charges + P2P) of a mat-vec on x at precision prec
 // ahead of time; the next run_matvec with the same x and prec uses it
 void prefetch_near(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
-// stored near field (nearfield.hip): assemble at build; one product on stream st
+// stored near field (nearfield.hip): assemble at build; copy the input in
+// sorted order (nearm.xs), then one product on stream st
 void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st);
-void launch_near_stored(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
+void sort_near_input(fmmbem_ctx *ctx, const double *x, hipStream_t st);
+void launch_near_stored(fmmbem_ctx *ctx, int prec, hipStream_t st);
 int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
               fmmbem_report *rep, hipStream_t st);
 void free_krylov(fmmbem_ctx *ctx);

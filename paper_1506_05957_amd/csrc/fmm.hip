@@ -1019,6 +1019,8 @@ void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
     stage_begin(ctx, SO + 4, st, &ev);
     k_charges<R, STOKES><<<grid_for(ns, 256), 256, 0, st>>>(nt, T.perm, G.sp, G.sp32, x, src);
     FB_HIP(hipGetLastError());
+    if (ctx->nearm.v64)
+        sort_near_input(ctx, x, st);
     stage_end(ctx, SO + 4, st, ev);
 
     FB_HIP(hipEventRecord(ctx->ev_fork, st));
@@ -1026,7 +1028,7 @@ void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
     stage_begin(ctx, SO + 0, ctx->side, &ev);
     if (ctx->nearm.v64) {
         // stored near field: 2 flops per matrix entry
-        launch_near_stored(ctx, sizeof(R) == 8 ? FMMBEM_FP64 : FMMBEM_FP32, x, ctx->side);
+        launch_near_stored(ctx, sizeof(R) == 8 ? FMMBEM_FP64 : FMMBEM_FP32, ctx->side);
         stage_end(ctx, SO + 0, ctx->side, ev, 2.0 * (STOKES ? 9.0 : 1.0) * (double)ctx->nearm.entries);
     } else {
         if (T.n_unit > 0) {

@@ -197,16 +197,21 @@ void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st)
     FB_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
 }
 
-void launch_near_stored(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
+void sort_near_input(fmmbem_ctx *ctx, const double *x, hipStream_t st)
+{
+    Tree &T = ctx->tree;
+    if (ctx->kernel == FMMBEM_STOKES_SL)
+        k_sort_input<3><<<grid_for(T.nt, 256), 256, 0, st>>>(T.nt, T.perm, x, ctx->nearm.xs);
+    else
+        k_sort_input<1><<<grid_for(T.nt, 256), 256, 0, st>>>(T.nt, T.perm, x, ctx->nearm.xs);
+    FB_HIP(hipGetLastError());
+}
+
+void launch_near_stored(fmmbem_ctx *ctx, int prec, hipStream_t st)
 {
     Tree &T = ctx->tree;
     NearMatrix &N = ctx->nearm;
     const bool stokes = ctx->kernel == FMMBEM_STOKES_SL;
-    if (stokes)
-        k_sort_input<3><<<grid_for(T.nt, 256), 256, 0, st>>>(T.nt, T.perm, x, N.xs);
-    else
-        k_sort_input<1><<<grid_for(T.nt, 256), 256, 0, st>>>(T.nt, T.perm, x, N.xs);
-    FB_HIP(hipGetLastError());
     if (T.n_unit == 0)
         return;
     const int per_xcd = (T.n_unit + 7) / 8;
