@@ -16,7 +16,7 @@ _BUILD = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_BUILD, "liboracle.so")
 _SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "tree.c")]
 
-LAPLACE, STOKES = 0, 1
+LAPLACE, STOKES, LAPLACE_DL = 0, 1, 2  # single layer, Stokes single layer, 1/2 I - K (exterior Neumann)
 
 
 def build(force: bool = True) -> str:
@@ -53,6 +53,9 @@ def lib():
         L.or_stokes_self.argtypes = [pd, pd, pd, pd, pd, pd]
         L.or_matvec_laplace.argtypes = [i64, pd, pi32, pd, pd, i64, pi64]
         L.or_matvec_stokes.argtypes = [i64, pd, pi32, d, pd, pd, i64, pi64]
+        L.or_matvec_laplace_dl.argtypes = [i64, pd, pi32, pd, pd, i64, pi64]
+        L.or_laplace_dl_entry.argtypes = [i64, pd, pi32, i64, i64]
+        L.or_laplace_dl_entry.restype = d
         L.or_laplace_entry.argtypes = [i64, pd, pi32, i64, i64]
         L.or_laplace_entry.restype = d
         L.or_classify.argtypes = [i64, pd, pi32, i64, i64]
@@ -140,6 +143,9 @@ def matvec(kernel: int, xyz, tri, x, mu: float = 1.0, rows=None):
     if kernel == LAPLACE:
         y = np.empty(ny)
         rc = lib().or_matvec_laplace(nt, _p(xyz), _p(tri, ctypes.c_int32), _p(x), _p(y), nr, rp)
+    elif kernel == LAPLACE_DL:
+        y = np.empty(ny)
+        rc = lib().or_matvec_laplace_dl(nt, _p(xyz), _p(tri, ctypes.c_int32), _p(x), _p(y), nr, rp)
     else:
         y = np.empty(3 * ny)
         rc = lib().or_matvec_stokes(nt, _p(xyz), _p(tri, ctypes.c_int32), mu, _p(x), _p(y), nr, rp)
@@ -151,6 +157,12 @@ def matvec(kernel: int, xyz, tri, x, mu: float = 1.0, rows=None):
 def laplace_entry(xyz, tri, i: int, j: int) -> float:
     xyz, tri = _mesh_args(xyz, tri)
     return float(lib().or_laplace_entry(tri.shape[0], _p(xyz), _p(tri, ctypes.c_int32), i, j))
+
+
+def laplace_dl_entry(xyz, tri, i: int, j: int) -> float:
+    """int_j n_j . (x_i - y) / |x_i - y|^3 dA (no 1/(4 pi)) by the panel pair's rule."""
+    xyz, tri = _mesh_args(xyz, tri)
+    return float(lib().or_laplace_dl_entry(tri.shape[0], _p(xyz), _p(tri, ctypes.c_int32), i, j))
 
 
 def laplace_row(xyz, tri, i: int):
@@ -192,7 +204,7 @@ def solve(kernel: int, xyz, tri, b, tol: float = 1e-6, restart: int = 50, max_it
     """Dense-operator GMRES solve; returns (x, info, iters, hist, true_res)."""
     xyz, tri = _mesh_args(xyz, tri)
     nt = tri.shape[0]
-    n = nt if kernel == LAPLACE else 3 * nt
+    n = 3 * nt if kernel == STOKES else nt
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.empty(n); hist = np.zeros(max_iter); it = ctypes.c_int(0); tr = np.empty(1)
     info = lib().or_solve(kernel, nt, _p(xyz), _p(tri, ctypes.c_int32), mu, _p(b), tol, restart,

@@ -11,6 +11,9 @@
  *   - constant flat triangular panels, collocation at centroids (Sec. 2.1, Eq. 2-3);
  *   - Laplace single layer, G = 1/(4 pi r) (Sec. 2.1, Eq. 4); the 1/(4 pi) is kept;
  *   - Stokes single layer, u = -1/(8 pi mu) sum_J t_J int G (Sec. 2.2, Eq. 6, 7, 9);
+ *   - Laplace double layer, second kind (Sec. 2.1, Eq. 5 and 11): with outward
+ *     unit normals, the exterior Neumann problem (1/2 I - K) u = -V du/dn,
+ *     K u = sum_j u_j int_j dG/dn_y, dG/dn_y = n_j . (x - y) / (4 pi |x - y|^3);
  *   - far panels: a K=4 Gauss rule, weights q_k S_j (Sec. 2.3, Eq. 10);
  *   - near-singular panels, within 2 sqrt(2 S_j) of the target (Sec. 2.3,
  *     figure on integration domains): a 25-point collapsed Gauss-Legendre rule;
@@ -240,7 +243,7 @@ typedef struct {
     int64_t nt;
     const double *xyz;
     const int32_t *tri;
-    double *c, *S;
+    double *c, *S, *n;      /* centroids, areas, unit normals */
     double fb[12], fw[4];   /* far rule */
     double nb[75], nw[25];  /* near rule */
     int nfar, nnear;
@@ -253,9 +256,10 @@ static int mesh_init(mesh_t *m, int64_t nt, const double *xyz, const int32_t *tr
     m->tri = tri;
     m->c = (double *)malloc(sizeof(double) * 3 * (size_t)nt);
     m->S = (double *)malloc(sizeof(double) * (size_t)nt);
-    if (!m->c || !m->S)
+    m->n = (double *)malloc(sizeof(double) * 3 * (size_t)nt);
+    if (!m->c || !m->S || !m->n)
         return -1;
-    or_panels(nt, xyz, tri, m->c, m->S, NULL);
+    or_panels(nt, xyz, tri, m->c, m->S, m->n);
     m->nfar = or_far_rule(m->fb, m->fw);
     m->nnear = or_near_rule(5, m->nb, m->nw);
     return 0;
@@ -265,6 +269,7 @@ static void mesh_free(mesh_t *m)
 {
     free(m->c);
     free(m->S);
+    free(m->n);
 }
 
 #define VTX(m, j, a) ((m)->xyz + 3 * (int64_t)(m)->tri[3 * (j) + (a)])
@@ -300,6 +305,32 @@ static double laplace_entry(const mesh_t *m, int64_t i, int64_t j)
         double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
         double r = sqrt((dx * dx + dy * dy) + dz * dz);
         acc += W[k] * m->S[j] / r;
+    }
+    return acc;
+}
+
+/* int_{panel j} n_j . (x - y) / |x - y|^3 dA (Eq. 11 without 1/(4 pi)) by the rule
+ * for its class.  On the target's own flat panel x and every y lie in one plane,
+ * n_j . (x - y) = 0, so the principal value is 0 (the 1/2 of the jump is the
+ * identity term of the operator). */
+static double dl_entry(const mesh_t *m, int64_t i, int64_t j)
+{
+    int cls = classify(m, i, j);
+    if (cls == 2)
+        return 0.0;
+    const double *v0 = VTX(m, j, 0), *v1 = VTX(m, j, 1), *v2 = VTX(m, j, 2);
+    const double *x = m->c + 3 * i, *nj = m->n + 3 * j;
+    const double *B = cls ? m->nb : m->fb, *W = cls ? m->nw : m->fw;
+    int np = cls ? m->nnear : m->nfar;
+    double acc = 0.0;
+    for (int k = 0; k < np; ++k) {
+        double y[3];
+        bary_point(v0, v1, v2, B + 3 * k, y);
+        double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+        double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+        double r = sqrt(r2);
+        double nd = (nj[0] * d[0] + nj[1] * d[1]) + nj[2] * d[2];
+        acc += W[k] * m->S[j] * nd / (r2 * r);
     }
     return acc;
 }
@@ -380,6 +411,37 @@ int or_matvec_stokes(int64_t nt, const double *xyz, const int32_t *tri, double m
     }
     mesh_free(&m);
     return 0;
+}
+
+/* y = (1/2 I - K) x, the second-kind operator of the exterior Neumann problem:
+ * y_i = x_i / 2 - (1/4pi) sum_j x_j int_j n_j . (x_i - y) / |x_i - y|^3. */
+int or_matvec_laplace_dl(int64_t nt, const double *xyz, const int32_t *tri,
+                         const double *x, double *y, int64_t nrows, const int64_t *rows)
+{
+    mesh_t m;
+    if (mesh_init(&m, nt, xyz, tri))
+        return -1;
+    int64_t nr = rows ? nrows : nt;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        double acc = 0.0;
+        for (int64_t j = 0; j < nt; ++j)
+            acc += dl_entry(&m, i, j) * x[j];
+        y[r] = 0.5 * x[i] - acc / (4.0 * OR_PI);
+    }
+    mesh_free(&m);
+    return 0;
+}
+
+double or_laplace_dl_entry(int64_t nt, const double *xyz, const int32_t *tri, int64_t i, int64_t j)
+{
+    mesh_t m;
+    if (mesh_init(&m, nt, xyz, tri))
+        return NAN;
+    double v = dl_entry(&m, i, j);
+    mesh_free(&m);
+    return v;
 }
 
 /* Single entries, for tests: the Laplace entry int_j 1/r and the Stokes block. */
@@ -563,14 +625,20 @@ static void mv_stokes(void *u, const double *x, double *y)
     or_matvec_stokes(s->nt, s->xyz, s->tri, s->mu, x, y, 0, NULL);
 }
 
+static void mv_laplace_dl(void *u, const double *x, double *y)
+{
+    solve_ctx *s = (solve_ctx *)u;
+    or_matvec_laplace_dl(s->nt, s->xyz, s->tri, x, y, 0, NULL);
+}
+
 int or_solve(int kernel, int64_t nt, const double *xyz, const int32_t *tri, double mu,
              const double *b, double tol, int restart, int max_iter, double *x,
              double *res_hist, int hist_cap, int *iters, double *true_res)
 {
     solve_ctx s = {nt, xyz, tri, mu};
-    int64_t n = kernel == 0 ? nt : 3 * nt;
-    return or_gmres(n, kernel == 0 ? mv_laplace : mv_stokes, &s, b, tol, restart, max_iter, x,
-                    res_hist, hist_cap, iters, true_res);
+    int64_t n = kernel == 1 ? 3 * nt : nt;
+    or_mv_fn mv = kernel == 0 ? mv_laplace : kernel == 1 ? mv_stokes : mv_laplace_dl;
+    return or_gmres(n, mv, &s, b, tol, restart, max_iter, x, res_hist, hist_cap, iters, true_res);
 }
 
 /* Drag and torque (Eq. 20): F = sum_j t_j S_j, T = sum_j c_j x t_j S_j. */
