@@ -56,7 +56,13 @@ typedef enum {
     FMMBEM_EINTERNAL = -6  /* internal invariant violated */
 } fmmbem_status;
 
-typedef enum { FMMBEM_LAPLACE_SL = 0, FMMBEM_STOKES_SL = 1 } fmmbem_kernel;
+/* Operators (Sec. 2.1, 2.2; unknowns per panel):
+ *   LAPLACE_SL: y = V x, (V x)_i = sum_j x_j int_j G, G = 1/(4 pi r)  (first kind, 1)
+ *   STOKES_SL:  y = -1/(8 pi mu) sum_j int_j G_Stokes t_j             (first kind, 3)
+ *   LAPLACE_DL: y = (1/2 I - K) x, (K x)_i = sum_j x_j int_j dG/dn_y, outward
+ *               normals: the second-kind operator of the exterior Neumann
+ *               problem, (1/2 I - K) u = -V du/dn (Eq. 5, 11)             (second kind, 1) */
+typedef enum { FMMBEM_LAPLACE_SL = 0, FMMBEM_STOKES_SL = 1, FMMBEM_LAPLACE_DL = 2 } fmmbem_kernel;
 
 /* Arithmetic of the P2P and expansion (P2M ... L2P) kernels.  Inputs, outputs,
  * the near-field correction and all Krylov arithmetic are FP64 in both cases. */

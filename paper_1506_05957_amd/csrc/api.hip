@@ -150,7 +150,8 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
     FB_REQUIRE(out != nullptr, FMMBEM_EINVAL, "out is NULL");
     *out = nullptr;
     validate_mesh(mesh);
-    FB_REQUIRE(kernel == FMMBEM_LAPLACE_SL || kernel == FMMBEM_STOKES_SL, FMMBEM_EINVAL, "unknown kernel");
+    FB_REQUIRE(kernel == FMMBEM_LAPLACE_SL || kernel == FMMBEM_STOKES_SL || kernel == FMMBEM_LAPLACE_DL,
+               FMMBEM_EINVAL, "unknown kernel");
     fmmbem_params prm;
     fmmbem_params_default(&prm);
     if (params)
@@ -175,7 +176,7 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         if (prm.near_stored)
             build_near_matrix(ctx, st);
         const int ncs = ncoef(prm.p_max);
-        ctx->charges = ctx->arena.alloc<double>((size_t)(kernel == FMMBEM_STOKES_SL ? 8 : 4) * ctx->nsrc);
+        ctx->charges = ctx->arena.alloc<double>((size_t)(kernel == FMMBEM_LAPLACE_SL ? 4 : 8) * ctx->nsrc);
         ctx->Y = ctx->arena.alloc<double>(2 * (size_t)std::max<int64_t>(ctx->tree.n_m2l, 1) * ctx->nch * ncs);
         ctx->M = ctx->arena.alloc<double>(2 * (size_t)ctx->tree.nbox * ctx->nch * ncs);
         ctx->L = ctx->arena.alloc<double>(2 * (size_t)ctx->tree.nbox * ctx->nch * ncs);

@@ -105,6 +105,7 @@ struct Geometry {
     double *S = nullptr;     // [nt] areas
     double *vtx = nullptr;   // [nt][9] panel vertices v0, v1, v2
     double *sp = nullptr;    // [4][nsrc] Gauss points x, y, z and weights q_k S_j
+    double *nrm = nullptr;   // [3][nt] outward unit normals (v1 - v0) x (v2 - v0) / |.|
     float *tc32 = nullptr;   // [3][nt] centroid - leaf centre (FP32)
     float *sp32 = nullptr;   // [4][nsrc] Gauss point - leaf centre, weight (FP32)
 };

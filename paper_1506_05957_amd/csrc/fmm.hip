@@ -124,10 +124,14 @@ template <> struct Src<float, false> { float x, y, z, q; };
 template <> struct Src<double, true> { double x, y, z, f0, f1, f2, pad0, pad1; };
 template <> struct Src<float, true> { float x, y, z, f0, f1, f2, pad0, pad1; };
 
-template <typename R, bool STOKES>
+// KIND: FMMBEM_LAPLACE_SL (charges w x), FMMBEM_STOKES_SL (forces w t) or
+// FMMBEM_LAPLACE_DL (dipoles w x n_j of the source panel, n outward).
+template <int KIND> constexpr bool vec_src() { return KIND != FMMBEM_LAPLACE_SL; }
+
+template <typename R, int KIND>
 __global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const double *__restrict__ sp,
-                          const float *__restrict__ sp32, const double *__restrict__ x,
-                          Src<R, STOKES> *__restrict__ src)
+                          const float *__restrict__ sp32, const double *__restrict__ nrm,
+                          const double *__restrict__ x, Src<R, vec_src<KIND>()> *__restrict__ src)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ns = 4 * nt;
@@ -135,7 +139,7 @@ __global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const do
         return;
     const int64_t o = perm[s >> 2];
     const double w = sp[3 * ns + s];
-    Src<R, STOKES> v;
+    Src<R, vec_src<KIND>()> v;
     if constexpr (sizeof(R) == 8) {
         v.x = sp[s];
         v.y = sp[ns + s];
@@ -145,12 +149,19 @@ __global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const do
         v.y = sp32[ns + s];
         v.z = sp32[2 * ns + s];
     }
-    if constexpr (!STOKES) {
+    if constexpr (KIND == FMMBEM_LAPLACE_SL) {
         v.q = (R)(w * x[o]);
-    } else {
+    } else if constexpr (KIND == FMMBEM_STOKES_SL) {
         v.f0 = (R)(w * x[3 * o]);
         v.f1 = (R)(w * x[3 * o + 1]);
         v.f2 = (R)(w * x[3 * o + 2]);
+        v.pad0 = v.pad1 = 0;
+    } else {
+        const int64_t i = s >> 2;
+        const double wx = w * x[o];
+        v.f0 = (R)(wx * nrm[i]);
+        v.f1 = (R)(wx * nrm[nt + i]);
+        v.f2 = (R)(wx * nrm[2 * nt + i]);
         v.pad0 = v.pad1 = 0;
     }
     src[s] = v;
@@ -251,6 +262,145 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
             M[((int64_t)b * NCH + ch) * ncs + t] = cplx<R>{sr, si2};
         }
         __syncthreads();
+    }
+}
+
+// P2M of dipole sources (the double layer, f3): a moment d = w x n at y has
+// the multipole sum conj(d . grad R_n^m(y - c)), and with the gradient
+// identities of the factorial-normalised harmonics
+//   d . grad R_n^m = (dx - i dy)/2 R_{n-1}^{m+1} - (dx + i dy)/2 R_{n-1}^{m-1}
+//                    + dz R_{n-1}^m;
+// in the scaled form (u = (y - c)/s) the sum picks up a factor 1/s.  Thread =
+// (order m, source slice); it runs the columns m - 1, m, m + 1 of R(u) up to
+// degree p - 1 together (column -1 from R_k^-1 = -conj(R_k^1)).
+template <typename R, int PM>
+__global__ __launch_bounds__(256) void k_p2m_dipole(int p, int ncs, const int32_t *__restrict__ leaves,
+                                                    const int32_t *__restrict__ box_i, const double *__restrict__ box_r,
+                                                    double side, const Src<R, true> *__restrict__ src,
+                                                    cplx<R> *__restrict__ M)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cplx<R> *red = reinterpret_cast<cplx<R> *>(smem_raw);  // [nsl][nc]
+    const int b = leaves[blockIdx.x];
+    const int lv = box_i[6 * b], pb = box_i[6 * b + 1], pe = box_i[6 * b + 2];
+    const double s = ldexp(side, -(lv + 1));
+    const double *c = box_r + 5 * (int64_t)b;
+    const int nm = p + 1, nsl = (int)blockDim.x / nm;
+    const int m = threadIdx.x % nm, sl = threadIdx.x / nm;
+    const bool active = sl < nsl;
+    const int nc = ncoef(p);
+    const R is = (R)(1.0 / s);
+    // columns run: m - 1 (|m - 1| = 1 when m = 0), m, m + 1
+    const int colA = m >= 1 ? m - 1 : 1, colB = m, colC = m + 1;
+    R are[PM + 1], aim[PM + 1];
+#pragma unroll
+    for (int n = 0; n <= PM; ++n)
+        are[n] = aim[n] = 0;
+    if (active) {
+        for (int64_t si = 4 * (int64_t)pb + sl; si < 4 * (int64_t)pe; si += nsl) {
+            const Src<R, true> sv = src[si];
+            R x, y, z;  // relative to the leaf centre, then scaled
+            if constexpr (sizeof(R) == 8) {
+                x = sv.x - c[0];
+                y = sv.y - c[1];
+                z = sv.z - c[2];
+            } else {
+                x = sv.x;
+                y = sv.y;
+                z = sv.z;
+            }
+            x *= is;
+            y *= is;
+            z *= is;
+            const R r2 = x * x + y * y + z * z;
+            // diagonal values R_k^k, kept for k = colA, colB, colC
+            R dre = 1, dim = 0, aRe = 0, aIm = 0, bRe = 0, bIm = 0, cRe = 0, cIm = 0;
+            for (int k = 0; k <= colC; ++k) {
+                if (k == colA) {
+                    aRe = dre;
+                    aIm = dim;
+                }
+                if (k == colB) {
+                    bRe = dre;
+                    bIm = dim;
+                }
+                if (k == colC) {
+                    cRe = dre;
+                    cIm = dim;
+                }
+                const R f = -inv_int<R>(2 * (k + 1));
+                const R a = f * (x * dre - y * dim), bb = f * (x * dim + y * dre);
+                dre = a;
+                dim = bb;
+            }
+            // running (current, previous) of the three columns
+            R Ac = 0, Ai = 0, Ap = 0, Api = 0, Bc = 0, Bi = 0, Bp = 0, Bpi = 0, Cc = 0, Ci = 0, Cp = 0, Cpi = 0;
+            const R hx = R(0.5) * sv.f0, hy = R(0.5) * sv.f1, dz = sv.f2;
+#pragma unroll
+            for (int k = 0; k < PM; ++k) {
+                if (k < p) {
+                    // advance each column to degree k
+                    if (k == colA) {
+                        Ac = aRe;
+                        Ai = aIm;
+                    } else if (k > colA) {
+                        const R f = inv_int<R>((k - colA) * (k + colA)), a = R(2 * k - 1) * z;
+                        const R nr = (a * Ac - r2 * Ap) * f, ni = (a * Ai - r2 * Api) * f;
+                        Ap = Ac;
+                        Api = Ai;
+                        Ac = nr;
+                        Ai = ni;
+                    }
+                    if (k == colB) {
+                        Bc = bRe;
+                        Bi = bIm;
+                    } else if (k > colB) {
+                        const R f = inv_int<R>((k - colB) * (k + colB)), a = R(2 * k - 1) * z;
+                        const R nr = (a * Bc - r2 * Bp) * f, ni = (a * Bi - r2 * Bpi) * f;
+                        Bp = Bc;
+                        Bpi = Bi;
+                        Bc = nr;
+                        Bi = ni;
+                    }
+                    if (k == colC) {
+                        Cc = cRe;
+                        Ci = cIm;
+                    } else if (k > colC) {
+                        const R f = inv_int<R>((k - colC) * (k + colC)), a = R(2 * k - 1) * z;
+                        const R nr = (a * Cc - r2 * Cp) * f, ni = (a * Ci - r2 * Cpi) * f;
+                        Cp = Cc;
+                        Cpi = Ci;
+                        Cc = nr;
+                        Ci = ni;
+                    }
+                    // R_k^{m-1}, R_k^m, R_k^{m+1} (zero below their column's order)
+                    R m1r = k >= colA ? Ac : R(0);
+                    const R m1i = k >= colA ? Ai : R(0);
+                    if (m == 0)  // R_k^-1 = -conj(R_k^1): real part negated, imaginary part kept
+                        m1r = -m1r;
+                    const R z0r = k >= colB ? Bc : R(0), z0i = k >= colB ? Bi : R(0);
+                    const R p1r = k >= colC ? Cc : R(0), p1i = k >= colC ? Ci : R(0);
+                    // D = (hx - i hy) R^{m+1} - (hx + i hy) R^{m-1} + dz R^m, degree n = k + 1
+                    const R Dr = (hx * p1r + hy * p1i) - (hx * m1r - hy * m1i) + dz * z0r;
+                    const R Di = (hx * p1i - hy * p1r) - (hx * m1i + hy * m1r) + dz * z0i;
+                    are[k + 1] += is * Dr;
+                    aim[k + 1] -= is * Di;
+                }
+            }
+        }
+#pragma unroll
+        for (int n = 0; n <= PM; ++n)
+            if (n <= p && n >= m)
+                red[sl * nc + cidx(n, m)] = cplx<R>{are[n], aim[n]};
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+        R sr = 0, si2 = 0;
+        for (int k = 0; k < nsl; ++k) {
+            sr += red[k * nc + t].re;
+            si2 += red[k * nc + t].im;
+        }
+        M[(int64_t)b * ncs + t] = cplx<R>{sr, si2};
     }
 }
 
@@ -822,13 +972,13 @@ template <typename R, bool STOKES> __device__ __forceinline__ Src<R, STOKES> far
     return v;
 }
 
-template <typename R, bool STOKES, bool SELF>
-__device__ __forceinline__ void p2p_phase(const Src<R, STOKES> *__restrict__ row, int nj, int k, int kstep, int i,
-                                          R px, R py, R pz, R *acc)
+template <typename R, int KIND, bool SELF>
+__device__ __forceinline__ void p2p_phase(const Src<R, vec_src<KIND>()> *__restrict__ row, int nj, int k, int kstep,
+                                          int i, R px, R py, R pz, R *acc)
 {
 #pragma unroll 4
     for (int j = 0; j < nj; ++j) {
-        const Src<R, STOKES> sv = row[j];
+        const Src<R, vec_src<KIND>()> sv = row[j];
         const R dx = px - sv.x, dy = py - sv.y, dz = pz - sv.z;
         const R r2 = dx * dx + dy * dy + dz * dz;
         R rinv;
@@ -847,28 +997,31 @@ __device__ __forceinline__ void p2p_phase(const Src<R, STOKES> *__restrict__ row
             rinv = (k >> 2) == i ? R(0) : rinv;  // the target's own panel: integrated by the correction
             k += kstep;
         }
-        if constexpr (!STOKES) {
+        if constexpr (KIND == FMMBEM_LAPLACE_SL) {
             acc[0] += sv.q * rinv;
-        } else {
+        } else if constexpr (KIND == FMMBEM_STOKES_SL) {
             const R dot = (dx * sv.f0 + dy * sv.f1 + dz * sv.f2) * (rinv * rinv * rinv);
             acc[0] += sv.f0 * rinv + dx * dot;
             acc[1] += sv.f1 * rinv + dy * dot;
             acc[2] += sv.f2 * rinv + dz * dot;
+        } else {  // dipole w x n: (w x n) . (t - y) / r^3
+            acc[0] += (dx * sv.f0 + dy * sv.f1 + dz * sv.f2) * (rinv * rinv * rinv);
         }
     }
 }
 
-template <typename R, bool STOKES>
+template <typename R, int KIND>
 __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, const int4 *__restrict__ units,
                                                         const int2 *__restrict__ chunks,
                                                         const float4 *__restrict__ choff, int64_t nt,
                                                         const double *__restrict__ tc, const float *__restrict__ tc32,
-                                                        const Src<R, STOKES> *__restrict__ src,
+                                                        const Src<R, vec_src<KIND>()> *__restrict__ src,
                                                         double *__restrict__ ynear)
 {
     static_assert(P2P_TILE == 128, "two staged sources per lane");
-    constexpr int NQ = STOKES ? 3 : 1;
-    __shared__ Src<R, STOKES> tile[P2P_WAVES][P2P_TILE];
+    constexpr bool VS = vec_src<KIND>();
+    constexpr int NQ = KIND == FMMBEM_STOKES_SL ? 3 : 1;
+    __shared__ Src<R, VS> tile[P2P_WAVES][P2P_TILE];
     __shared__ R red[P2P_WAVES][NQ][64];
     // blocks are dealt to the 8 XCDs round robin; give each XCD a contiguous
     // run of units so that neighbouring units share its L2
@@ -897,14 +1050,14 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, 
 #pragma unroll
     for (int a = 0; a < NQ; ++a)
         acc[a] = 0;
-    Src<R, STOKES> *my = tile[w];
+    Src<R, VS> *my = tile[w];
     // staged slots of this lane: t = lane and t = lane + 64, at phase t % P, position t / P
     const int ta = lane, tb2 = lane + 64;
     const int pa = ta / P, qa = ta - pa * P;
     const int pb = tb2 / P, qb = tb2 - pb * P;
     int c = u.z + w;
     int2 ch = make_int2(0, 0);
-    Src<R, STOKES> ra = far_zero_source<R, STOKES>(), rb = ra;
+    Src<R, VS> ra = far_zero_source<R, VS>(), rb = ra;
     if (c < u.w) {
         ch = chunks[c];
         const int cnt = ch.y & 0xffff;
@@ -939,7 +1092,7 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, 
         if (cn < u.w) {
             ch = chunks[cn];
             const int cnt2 = ch.y & 0xffff;
-            ra = far_zero_source<R, STOKES>();
+            ra = far_zero_source<R, VS>();
             rb = ra;
             if (ta < cnt2)
                 ra = src[ch.x + ta];
@@ -948,9 +1101,9 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, 
         }
         if (active) {
             if (self)
-                p2p_phase<R, STOKES, true>(my + ph * nj, nj, k0 + ph, P, i, px, py, pz, acc);
+                p2p_phase<R, KIND, true>(my + ph * nj, nj, k0 + ph, P, i, px, py, pz, acc);
             else
-                p2p_phase<R, STOKES, false>(my + ph * nj, nj, 0, 0, i, px, py, pz, acc);
+                p2p_phase<R, KIND, false>(my + ph * nj, nj, 0, 0, i, px, py, pz, acc);
         }
         c = cn;
     }
@@ -969,8 +1122,9 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, 
 }
 
 // ---------------------------------------------------------------------------
-// a11 + a12: y[perm i] = pref * (far + near + sum_j S_ij x_j)
-template <bool STOKES>
+// a11 + a12: y[perm i] = pref * (far + near + sum_j S_ij x_j), plus x / 2 for
+// the second-kind operator (pref = -1/(4 pi) there)
+template <int KIND>
 __global__ void k_combine(int64_t nt, const int32_t *__restrict__ perm, const int32_t *__restrict__ cptr,
                           const int32_t *__restrict__ ccol, const double *__restrict__ cval,
                           const double *__restrict__ x, const double *__restrict__ ynear,
@@ -980,11 +1134,11 @@ __global__ void k_combine(int64_t nt, const int32_t *__restrict__ perm, const in
     if (i >= nt)
         return;
     const int64_t o = perm[i];
-    if (!STOKES) {
+    if constexpr (KIND != FMMBEM_STOKES_SL) {
         double acc = ynear[i] + yfar[i];
         for (int e = cptr[i]; e < cptr[i + 1]; ++e)
             acc += cval[e] * x[ccol[e]];
-        y[o] = pref * acc;
+        y[o] = KIND == FMMBEM_LAPLACE_DL ? 0.5 * x[o] + pref * acc : pref * acc;
     } else {
         double a0 = ynear[3 * i] + yfar[3 * i], a1 = ynear[3 * i + 1] + yfar[3 * i + 1],
                a2 = ynear[3 * i + 2] + yfar[3 * i + 2];
@@ -1003,21 +1157,22 @@ __global__ void k_combine(int64_t nt, const int32_t *__restrict__ perm, const in
 }
 
 // charges of this mat-vec on st, then P2P on the side stream
-template <typename R, int NCH>
+template <typename R, int KIND>
 void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
 {
-    constexpr bool STOKES = NCH == 4;
+    constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
+    constexpr bool VS = vec_src<KIND>();
     constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
     Tree &T = ctx->tree;
     Geometry &G = ctx->geo;
     const int64_t nt = ctx->nt, ns = ctx->nsrc;
-    Src<R, STOKES> *src = static_cast<Src<R, STOKES> *>(ctx->charges);
+    Src<R, VS> *src = static_cast<Src<R, VS> *>(ctx->charges);
     hipEvent_t ev;
     if (ctx->near_pending)  // the charges buffer may still be read by an earlier P2P
         FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
 
     stage_begin(ctx, SO + 4, st, &ev);
-    k_charges<R, STOKES><<<grid_for(ns, 256), 256, 0, st>>>(nt, T.perm, G.sp, G.sp32, x, src);
+    k_charges<R, KIND><<<grid_for(ns, 256), 256, 0, st>>>(nt, T.perm, G.sp, G.sp32, G.nrm, x, src);
     FB_HIP(hipGetLastError());
     if (ctx->nearm.v64)
         sort_near_input(ctx, x, st);
@@ -1033,29 +1188,32 @@ void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
     } else {
         if (T.n_unit > 0) {
             const int per_xcd = (T.n_unit + 7) / 8;
-            k_p2p<R, STOKES><<<8 * per_xcd, 64 * P2P_WAVES, 0, ctx->side>>>(
+            k_p2p<R, KIND><<<8 * per_xcd, 64 * P2P_WAVES, 0, ctx->side>>>(
                 T.n_unit, per_xcd, T.p2p_unit, T.p2p_chunk, T.p2p_choff, nt, G.tc, G.tc32, src, ctx->y_near);
             FB_HIP(hipGetLastError());
         }
         // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
-        stage_end(ctx, SO + 0, ctx->side, ev, (STOKES ? 30.0 : 12.0) * (double)(T.p2p_interactions - 4 * nt));
+        const double fl = STOKES ? 30.0 : KIND == FMMBEM_LAPLACE_DL ? 18.0 : 12.0;
+        stage_end(ctx, SO + 0, ctx->side, ev, fl * (double)(T.p2p_interactions - 4 * nt));
     }
     FB_HIP(hipEventRecord(ctx->ev_join, ctx->side));
     ctx->near_pending = true;
 }
 
 // far field of order p on st from the charges of launch_near, then st joins the side stream
-template <typename R, int NCH>
+template <typename R, int KIND>
 void launch_fmm(fmmbem_ctx *ctx, int p, hipStream_t st)
 {
-    constexpr bool STOKES = NCH == 4;
+    constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
+    constexpr int NCH = STOKES ? 4 : 1;
+    constexpr bool VS = vec_src<KIND>();
     constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
     Tree &T = ctx->tree;
     Geometry &G = ctx->geo;
     const int64_t nt = ctx->nt;
     const int ncs = ncoef(ctx->prm.p_max);
     const double side = T.cube[3];
-    Src<R, STOKES> *src = static_cast<Src<R, STOKES> *>(ctx->charges);
+    Src<R, VS> *src = static_cast<Src<R, VS> *>(ctx->charges);
     cplx<R> *M = static_cast<cplx<R> *>(ctx->M);
     cplx<R> *L = static_cast<cplx<R> *>(ctx->L);
     hipEvent_t ev;
@@ -1065,16 +1223,29 @@ void launch_fmm(fmmbem_ctx *ctx, int p, hipStream_t st)
         {
             const int nsl = 256 / (p + 1);
             const size_t shm = sizeof(cplx<R>) * (size_t)nsl * ncoef(p);
-            if (p <= 4)
-                k_p2m<R, NCH, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-            else if (p <= 8)
-                k_p2m<R, NCH, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-            else if (p <= 12)
-                k_p2m<R, NCH, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-            else if (p <= 16)
-                k_p2m<R, NCH, 16><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-            else
-                k_p2m<R, NCH, 20><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            if constexpr (KIND == FMMBEM_LAPLACE_DL) {
+                if (p <= 4)
+                    k_p2m_dipole<R, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+                else if (p <= 8)
+                    k_p2m_dipole<R, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+                else if (p <= 12)
+                    k_p2m_dipole<R, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+                else if (p <= 16)
+                    k_p2m_dipole<R, 16><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+                else
+                    k_p2m_dipole<R, 20><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            } else {
+                if (p <= 4)
+                    k_p2m<R, NCH, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+                else if (p <= 8)
+                    k_p2m<R, NCH, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+                else if (p <= 12)
+                    k_p2m<R, NCH, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+                else if (p <= 16)
+                    k_p2m<R, NCH, 16><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+                else
+                    k_p2m<R, NCH, 20><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            }
             FB_HIP(hipGetLastError());
         }
         const M2LPlan &P = ctx->m2l;
@@ -1157,17 +1328,21 @@ void launch_fmm(fmmbem_ctx *ctx, int p, hipStream_t st)
 
 void near_dispatch(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
 {
-    const bool stokes = ctx->kernel == FMMBEM_STOKES_SL;
+    const int kind = ctx->kernel;
     if (prec == FMMBEM_FP64) {
-        if (stokes)
-            launch_near<double, 4>(ctx, x, st);
+        if (kind == FMMBEM_STOKES_SL)
+            launch_near<double, FMMBEM_STOKES_SL>(ctx, x, st);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            launch_near<double, FMMBEM_LAPLACE_DL>(ctx, x, st);
         else
-            launch_near<double, 1>(ctx, x, st);
+            launch_near<double, FMMBEM_LAPLACE_SL>(ctx, x, st);
     } else {
-        if (stokes)
-            launch_near<float, 4>(ctx, x, st);
+        if (kind == FMMBEM_STOKES_SL)
+            launch_near<float, FMMBEM_STOKES_SL>(ctx, x, st);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            launch_near<float, FMMBEM_LAPLACE_DL>(ctx, x, st);
         else
-            launch_near<float, 1>(ctx, x, st);
+            launch_near<float, FMMBEM_LAPLACE_SL>(ctx, x, st);
     }
 }
 
@@ -1182,7 +1357,7 @@ void prefetch_near(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
 
 void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hipStream_t st)
 {
-    const bool stokes = ctx->kernel == FMMBEM_STOKES_SL;
+    const int kind = ctx->kernel;
     // a near field prefetched for exactly this input and precision is used
     // as is; any other is dropped
     const bool have_near = ctx->spec_x == x && ctx->spec_prec == prec;
@@ -1191,26 +1366,33 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
     if (!have_near)
         near_dispatch(ctx, prec, x, st);
     if (prec == FMMBEM_FP64) {
-        if (stokes)
-            launch_fmm<double, 4>(ctx, p, st);
+        if (kind == FMMBEM_STOKES_SL)
+            launch_fmm<double, FMMBEM_STOKES_SL>(ctx, p, st);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            launch_fmm<double, FMMBEM_LAPLACE_DL>(ctx, p, st);
         else
-            launch_fmm<double, 1>(ctx, p, st);
+            launch_fmm<double, FMMBEM_LAPLACE_SL>(ctx, p, st);
     } else {
-        if (stokes)
-            launch_fmm<float, 4>(ctx, p, st);
+        if (kind == FMMBEM_STOKES_SL)
+            launch_fmm<float, FMMBEM_STOKES_SL>(ctx, p, st);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            launch_fmm<float, FMMBEM_LAPLACE_DL>(ctx, p, st);
         else
-            launch_fmm<float, 1>(ctx, p, st);
+            launch_fmm<float, FMMBEM_LAPLACE_SL>(ctx, p, st);
     }
     hipEvent_t ev;
     const int SO = prec == FMMBEM_FP64 ? 0 : 5;
     stage_begin(ctx, SO + 4, st, &ev);
-    const double pref = stokes ? -1.0 / (8.0 * M_PI * ctx->prm.mu) : 1.0 / (4.0 * M_PI);
-    if (stokes)
-        k_combine<true><<<grid_for(ctx->nt, 64), 64, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col_orig,
-                                                                ctx->corr.val, x, ctx->y_near, ctx->y_far, pref, y);
+#define FB_COMBINE(KIND, PREF)                                                                                  \
+    k_combine<KIND><<<grid_for(ctx->nt, 64), 64, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col_orig, \
+                                                          ctx->corr.val, x, ctx->y_near, ctx->y_far, PREF, y)
+    if (kind == FMMBEM_STOKES_SL)
+        FB_COMBINE(FMMBEM_STOKES_SL, -1.0 / (8.0 * M_PI * ctx->prm.mu));
+    else if (kind == FMMBEM_LAPLACE_DL)
+        FB_COMBINE(FMMBEM_LAPLACE_DL, -1.0 / (4.0 * M_PI));
     else
-        k_combine<false><<<grid_for(ctx->nt, 64), 64, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col_orig,
-                                                                 ctx->corr.val, x, ctx->y_near, ctx->y_far, pref, y);
+        FB_COMBINE(FMMBEM_LAPLACE_SL, 1.0 / (4.0 * M_PI));
+#undef FB_COMBINE
     FB_HIP(hipGetLastError());
     stage_end(ctx, SO + 4, st, ev);
 }

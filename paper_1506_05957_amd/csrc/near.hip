@@ -10,8 +10,9 @@
 //       S_ii = int_i K, with the polar split about the centroid of Hess and
 //       Smith: radial integral exact, angular integral by 32-point
 //       Gauss-Legendre quadrature on each edge.
-// K is 1/r (Laplace) or the Stokeslet delta/r + r r^T / r^3 (Eq. 7), without
-// the 1/(4 pi) or -1/(8 pi mu) factor.  Every near-singular pair lies inside a
+// K is 1/r (Laplace), the Stokeslet delta/r + r r^T / r^3 (Eq. 7) or the
+// double-layer kernel n_j . (x - y) / |x - y|^3 (Eq. 11, zero on the target's
+// own flat panel), without the 1/(4 pi) or -1/(8 pi mu) factor.  Every near-singular pair lies inside a
 // P2P box pair (the acceptance test guarantees it), so candidates come from the
 // P2P lists.  Compiled with -ffp-contract=off: the near/far decision uses the
 // same rounded distance as the classification of Sec. 2.3 anywhere else.
@@ -99,15 +100,16 @@ __device__ void self_integral(const double *__restrict__ v, const double *x, con
     }
 }
 
-template <bool STOKES>
+template <int KIND>
 __global__ void k_corr_fill(int64_t nt, const int32_t *__restrict__ panel_leaf, const int32_t *__restrict__ p2p_ptr,
                             const int32_t *__restrict__ p2p_src, const int32_t *__restrict__ box_i,
                             const double *__restrict__ tc, const double *__restrict__ S,
                             const double *__restrict__ vtx, const double *__restrict__ sp,
                             const int32_t *__restrict__ rowptr, int32_t *__restrict__ col, double *__restrict__ val,
                             const RuleTables *__restrict__ Rg, const int32_t *__restrict__ perm,
-                            int32_t *__restrict__ col_orig)
+                            int32_t *__restrict__ col_orig, const double *__restrict__ nrm)
 {
+    constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nt)
         return;
@@ -125,7 +127,33 @@ __global__ void k_corr_fill(int64_t nt, const int32_t *__restrict__ panel_leaf, 
             col[o] = j;
             col_orig[o] = perm[j];
             const double *v = vtx + 9 * (int64_t)j;
-            if (!STOKES) {
+            if (KIND == FMMBEM_LAPLACE_DL) {
+                // n_j . (x - y) / |x - y|^3; zero on the target's own flat panel
+                double acc = 0.0;
+                if (!self) {
+                    const double nj[3] = {nrm[j], nrm[nt + j], nrm[2 * nt + j]};
+                    double a25 = 0.0, a4 = 0.0;
+                    for (int k = 0; k < NEAR_PTS; ++k) {
+                        const double *l = R.nb + 3 * k;
+                        double y0 = (l[0] * v[0] + l[1] * v[3]) + l[2] * v[6];
+                        double y1 = (l[0] * v[1] + l[1] * v[4]) + l[2] * v[7];
+                        double y2 = (l[0] * v[2] + l[1] * v[5]) + l[2] * v[8];
+                        double d[3] = {x[0] - y0, x[1] - y1, x[2] - y2};
+                        double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                        double r = sqrt(r2);
+                        a25 += R.nw[k] * S[j] * ((nj[0] * d[0] + nj[1] * d[1]) + nj[2] * d[2]) / (r2 * r);
+                    }
+                    for (int k = 0; k < 4; ++k) {
+                        int64_t s = 4 * (int64_t)j + k;
+                        double d[3] = {x[0] - sp[s], x[1] - sp[ns + s], x[2] - sp[2 * ns + s]};
+                        double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                        double r = sqrt(r2);
+                        a4 += sp[3 * ns + s] * ((nj[0] * d[0] + nj[1] * d[1]) + nj[2] * d[2]) / (r2 * r);
+                    }
+                    acc = a25 - a4;
+                }
+                val[o] = acc;
+            } else if (!STOKES) {
                 double acc;
                 if (self) {
                     self_integral(v, x, R, acc, nullptr, false);
@@ -222,12 +250,16 @@ void build_correction(fmmbem_ctx *ctx, hipStream_t st)
         C.col = ctx->arena.alloc<int32_t>(std::max<int64_t>(nnz, 1));
         C.col_orig = ctx->arena.alloc<int32_t>(std::max<int64_t>(nnz, 1));
         C.val = ctx->arena.alloc<double>(std::max<int64_t>(nnz, 1) * (stokes ? 9 : 1));
-        if (stokes)
-            k_corr_fill<true><<<grid_for(nt, 64), 64, 0, st>>>(nt, T.panel_leaf, T.p2p_ptr, T.p2p_src, T.box_i, G.tc,
-                                                               G.S, G.vtx, G.sp, C.ptr, C.col, C.val, dR, T.perm, C.col_orig);
+#define FB_CORR_FILL(KIND)                                                                                    \
+    k_corr_fill<KIND><<<grid_for(nt, 64), 64, 0, st>>>(nt, T.panel_leaf, T.p2p_ptr, T.p2p_src, T.box_i, G.tc, G.S, \
+                                                       G.vtx, G.sp, C.ptr, C.col, C.val, dR, T.perm, C.col_orig, G.nrm)
+        if (ctx->kernel == FMMBEM_STOKES_SL)
+            FB_CORR_FILL(FMMBEM_STOKES_SL);
+        else if (ctx->kernel == FMMBEM_LAPLACE_DL)
+            FB_CORR_FILL(FMMBEM_LAPLACE_DL);
         else
-            k_corr_fill<false><<<grid_for(nt, 64), 64, 0, st>>>(nt, T.panel_leaf, T.p2p_ptr, T.p2p_src, T.box_i, G.tc,
-                                                                G.S, G.vtx, G.sp, C.ptr, C.col, C.val, dR, T.perm, C.col_orig);
+            FB_CORR_FILL(FMMBEM_LAPLACE_SL);
+#undef FB_CORR_FILL
         FB_HIP(hipGetLastError());
         FB_HIP(hipStreamSynchronize(st));
         tmp.release();

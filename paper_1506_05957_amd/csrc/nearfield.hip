@@ -17,13 +17,16 @@ constexpr int NEAR_WAVES = 8;
 
 // Entries of one stored block per HIP block, in FP64: entry (j, i) is
 // sum_k w_jk G(t_i - y_jk) over the 4 Gauss points of source panel j, Laplace
-// G = 1/r, Stokes G_ab = delta_ab / r + d_a d_b / r^3 (d = t - y), without the
-// kernel prefactor (applied when the mat-vec is combined).
-template <bool STOKES>
+// G = 1/r, Stokes G_ab = delta_ab / r + d_a d_b / r^3 (d = t - y), double layer
+// G = n_j . d / r^3, without the kernel prefactor (applied when the mat-vec
+// is combined).
+template <int KIND>
 __global__ void k_near_build(const int4 *__restrict__ units, const int32_t *__restrict__ blk_unit,
                              const NearBlock *__restrict__ blk, int64_t nt, const double *__restrict__ tc,
-                             const double *__restrict__ sp, double *__restrict__ v64, float *__restrict__ v32)
+                             const double *__restrict__ sp, const double *__restrict__ nrm,
+                             double *__restrict__ v64, float *__restrict__ v32)
 {
+    constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     constexpr int PER = STOKES ? 9 : 1;
     const int64_t b = blockIdx.x;
     const NearBlock B = blk[b];
@@ -44,8 +47,11 @@ __global__ void k_near_build(const int4 *__restrict__ units, const int32_t *__re
                 const double d[3] = {t[0] - sp[s], t[1] - sp[ns + s], t[2] - sp[2 * ns + s]};
                 const double w = sp[3 * ns + s];
                 const double ri = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-                if constexpr (!STOKES) {
+                if constexpr (KIND == FMMBEM_LAPLACE_SL) {
                     v += w * ri;
+                } else if constexpr (KIND == FMMBEM_LAPLACE_DL) {
+                    const double nd = nrm[sj] * d[0] + nrm[nt + sj] * d[1] + nrm[2 * nt + sj] * d[2];
+                    v += w * nd * (ri * ri * ri);
                 } else {
                     const int a = ab / 3, c = ab % 3;
                     v += w * ((a == c ? ri : 0.0) + d[a] * d[c] * (ri * ri * ri));
@@ -186,12 +192,16 @@ void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st)
     if (!blks.empty()) {
         FB_HIP(hipMemcpyAsync(N.blk, blks.data(), sizeof(NearBlock) * blks.size(), hipMemcpyHostToDevice, st));
         FB_HIP(hipMemcpyAsync(blk_unit, bunit.data(), sizeof(int32_t) * bunit.size(), hipMemcpyHostToDevice, st));
+#define FB_NEAR_BUILD(KIND)                                                                                     \
+    k_near_build<KIND><<<(unsigned)N.nblk, 256, 0, st>>>(T.p2p_unit, blk_unit, N.blk, T.nt, ctx->geo.tc, ctx->geo.sp, \
+                                                         ctx->geo.nrm, N.v64, N.v32)
         if (stokes)
-            k_near_build<true><<<(unsigned)N.nblk, 256, 0, st>>>(T.p2p_unit, blk_unit, N.blk, T.nt, ctx->geo.tc,
-                                                                 ctx->geo.sp, N.v64, N.v32);
+            FB_NEAR_BUILD(FMMBEM_STOKES_SL);
+        else if (ctx->kernel == FMMBEM_LAPLACE_DL)
+            FB_NEAR_BUILD(FMMBEM_LAPLACE_DL);
         else
-            k_near_build<false><<<(unsigned)N.nblk, 256, 0, st>>>(T.p2p_unit, blk_unit, N.blk, T.nt, ctx->geo.tc,
-                                                                  ctx->geo.sp, N.v64, N.v32);
+            FB_NEAR_BUILD(FMMBEM_LAPLACE_SL);
+#undef FB_NEAR_BUILD
         FB_HIP(hipGetLastError());
     }
     FB_HIP(hipStreamSynchronize(st));  // host vectors go out of scope

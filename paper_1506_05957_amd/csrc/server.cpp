@@ -263,7 +263,8 @@ int fmmbem_submit(fmmbem_server_t *srv, const fmmbem_mesh *mesh, const double *b
         FB_REQUIRE(srv && mesh && bc_host && s && ticket, FMMBEM_EINVAL, "null argument");
         FB_REQUIRE(mesh->xyz && mesh->tri && mesh->n_triangles >= 1 && mesh->n_vertices >= 3, FMMBEM_EINVAL,
                    "empty mesh");
-        FB_REQUIRE(kernel == FMMBEM_LAPLACE_SL || kernel == FMMBEM_STOKES_SL, FMMBEM_EINVAL, "unknown kernel");
+        FB_REQUIRE(kernel == FMMBEM_LAPLACE_SL || kernel == FMMBEM_STOKES_SL || kernel == FMMBEM_LAPLACE_DL,
+                   FMMBEM_EINVAL, "unknown kernel");
         FB_REQUIRE(tol > 0.0, FMMBEM_EINVAL, "tol must be positive");
         auto r = std::make_unique<Request>();
         r->kernel = kernel;

@@ -37,6 +37,21 @@ namespace fmmbem {
 
 namespace {
 
+// outward unit normal of each sorted panel: (v1 - v0) x (v2 - v0), normalised
+__global__ void k_normals(int64_t nt, const double *__restrict__ vtx, double *__restrict__ nrm)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt)
+        return;
+    const double *v = vtx + 9 * i;
+    const double e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+    const double e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
+    const double a[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    for (int d = 0; d < 3; ++d)
+        nrm[d * nt + i] = a[d] / na;
+}
+
 __global__ void k_panel_geom(int64_t nt, const double *__restrict__ xyz, const int32_t *__restrict__ tri,
                              double *__restrict__ c, double *__restrict__ S, int *__restrict__ bad)
 {
@@ -526,6 +541,9 @@ void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream
         G.vtx = A.alloc<double>(9 * nt);
         G.sp = A.alloc<double>(4 * ns);
         k_gather_geom<<<grid_for(nt, 256), 256, 0, st>>>(nt, T.perm, d_xyz, d_tri, c0, S0, G.tc, G.S, G.vtx, G.sp);
+        FB_HIP(hipGetLastError());
+        G.nrm = A.alloc<double>(3 * nt);
+        k_normals<<<grid_for(nt, 256), 256, 0, st>>>(nt, G.vtx, G.nrm);
         FB_HIP(hipGetLastError());
 
         // ---- boxes level by level (octant search on the device, records on the host)

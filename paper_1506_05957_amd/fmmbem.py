@@ -20,7 +20,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
-LAPLACE, STOKES = 0, 1
+LAPLACE, STOKES, LAPLACE_DL = 0, 1, 2  # single layer, Stokes single layer, 1/2 I - K (exterior Neumann)
 FP64, FP32 = 0, 1
 FIXED, RELAX_SHIFT, RELAX_BF = 0, 1, 2
 P_MAX, P_MAX_FP32 = 20, 14
