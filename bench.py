@@ -10,10 +10,13 @@ FP32 P2P/expansions once eps_k >= 1e-5, FP64 Arnoldi), cycling over the five
 right-hand sides; inputs are resident in device memory before timing starts.
 The line also reports the fixed-p (p = 12, FP64) solve time, the FP64-only
 relaxed solve time, mat-vec rates, the per-stage split, the roofline of the
-dominant kernel and the oracle's CPU rate on a bounded sample.  Two more
-sections, outside the timed region: the 64-cell Stokes case (131072 panels,
-relaxed mixed vs fixed p = 16 FP64, each at its best N_CRIT) and a 512-request serving stream through
-the request loop (latency p50/p99 from arrival to done).
+dominant kernel and the oracle's CPU rate on a bounded sample.  Three more
+sections, outside the timed region: the second-kind Laplace solve (double
+layer, exterior Neumann, 32768 panels), the 64-cell Stokes case (131072
+panels, relaxed mixed vs fixed p = 16 FP64, each at its best N_CRIT) and a
+512-request serving stream through the request loop (latency p50/p99 from
+arrival to done).  The near field of the main workload is stored as a
+block-sparse matrix (--near fly evaluates it per mat-vec instead).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
 """
@@ -113,6 +116,43 @@ def stokes_cells(fb, syn, torch, dev, ncrit_relaxed=128, ncrit_fixed=256):
                      "converged": bool(rep["converged"]), "ncrit": ncrit, "build_s": t_build}
         fb.fmmbem_destroy(ctx)
     out["speedup_relaxed_vs_fixed"] = out["fixed_p16_fp64"]["solve_s"] / out["relaxed_mixed"]["solve_s"]
+    return out
+
+
+def laplace_second_kind(fb, syn, torch, dev, level=6, reps=5):
+    """Second-kind Laplace solve on the 32768-panel sphere (the double layer,
+    exterior Neumann problem): du/dn = -(l+1) Y_l^m for the exterior harmonic
+    u = Y_l^m / r^(l+1), l = 2; right side -V du/dn by one single-layer FMM
+    mat-vec (p = 12, FP64, outside the timing); (1/2 I - K) u = b solved to 1e-6,
+    relaxed mixed (p 12 -> 3) against fixed p = 12 FP64, stored near field."""
+    m = syn.sphere(level)
+    Y = syn.ylm_rhs(m, 2, 1)
+    sl = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE, fb.params(ncrit=64, p_max=12))
+    g = torch.tensor(3.0 * Y, device=dev)  # -du/dn
+    b = torch.empty_like(g)
+    fb.fmmbem_matvec(sl, 12, fb.FP64, g, b)
+    torch.cuda.synchronize()
+    fb.fmmbem_destroy(sl)
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE_DL, fb.params(ncrit=64, p_max=12, near_stored=1))
+    x = torch.empty_like(b)
+    out = {"workload": f"laplace_dl_2nd_kind_sphere{m.n_panels}_exterior_neumann_Y21_tol1e-6",
+           "panels": m.n_panels}
+    for name, sched in (("relaxed_mixed", fb.schedule(fb.LAPLACE_DL)),
+                        ("fixed_p12_fp64", fb.schedule(fb.LAPLACE_DL, rule=fb.FIXED, p_min=12, mixed=0))):
+        fb.fmmbem_solve_ctx(ctx, b, 1e-6, sched, x)  # warm-up
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = fb.fmmbem_solve_ctx(ctx, b, 1e-6, sched, x)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        err = float(torch.linalg.norm(x - torch.tensor(Y, device=dev)) / np.linalg.norm(Y))
+        out[name] = {"solve_ms_p50": 1e3 * pct(ts, 50), "iterations": rep["iterations"],
+                     "rel_res_true": rep["rel_res_true"], "closed_form_rel_err": err,
+                     "p_hist": [int(v) for v in rep["p_hist"]]}
+    out["speedup_relaxed_vs_fixed"] = out["fixed_p12_fp64"]["solve_ms_p50"] / out["relaxed_mixed"]["solve_ms_p50"]
+    fb.fmmbem_destroy(ctx)
     return out
 
 
@@ -316,8 +356,10 @@ def main():
                          f"mat-vec ({t_mv:.1f}s) times {n_mv} mat-vecs (fixed-p iterations + true residual)",
                "matvec_s": t_mv}
 
-    cells = serve = None
+    cells = serve = second = None
     if not args.no_extra:
+        print("bench: second-kind Laplace case", file=sys.stderr, flush=True)
+        second = laplace_second_kind(fb, syn, torch, dev)
         print("bench: 64-cell Stokes case", file=sys.stderr, flush=True)
         if args.cells_ncrit:
             cells = stokes_cells(fb, syn, torch, dev, args.cells_ncrit, args.cells_ncrit)
@@ -356,6 +398,7 @@ def main():
         "stage_ms": stage_split,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "laplace_2nd_kind": second,
         "stokes_64cells": cells,
         "serving": serve,
         "build_s": t_build,
