@@ -45,7 +45,7 @@ def pct(a, q):
 
 # source regions the HBM counter records were taken on: file, first marker, end marker
 COUNTED_SOURCES = {
-    "k_p2p<float, false>": [("fmm.hip", "// P2P (a10)", "// ----"), ("tree.hip", "// P2P work units", "}  // namespace")],
+    "k_p2p<float, false>": [("fmm.hip", "// P2P: one block per work unit", "// ----"), ("tree.hip", "// P2P work units", "}  // namespace")],
     "k_near_spmv<float, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
     "k_near_spmv<double, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
     "k_m2l_valu<double, 1, 8>": [("fmm.hip", "// The same pass 1 on the vector units", "// Pass 2:")],

@@ -172,8 +172,10 @@ const char *fmmbem_last_error(void);
 
 /* Per-stage device time, accumulated with HIP events recorded on the stream
  * each kernel is launched on, while timing is enabled.  Stages: 0 P2P (one
- * kernel), 1 M2L (two kernels), 2 P2M+M2M, 3 L2L+L2P, 4 charges + correction
- * + combine; entry [prec * 5 + stage] holds the launches made in precision
+ * kernel), 1 M2L (two kernels), 2 P2M+M2M, 3 L2L+L2P (L2P also combines far
+ * field, near field and corrections, after waiting for the near field), 4
+ * charges (+ the combine when no box pair is far); entry [prec * 5 + stage]
+ * holds the launches made in precision
  * prec (FMMBEM_FP64 = 0, FMMBEM_FP32 = 1), FMMBEM_N_STAGES entries in all.
  * t_ms[i] is the total time, launches[i] the number of timed launches and
  * flops[i] the algorithmic flops of those launches: P2P counts 12 (Laplace) or

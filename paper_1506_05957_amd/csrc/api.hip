@@ -185,8 +185,7 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         FB_HIP(hipStreamSynchronize(st));
     } catch (...) {
         (void)hipStreamSynchronize(st);
-        ctx->arena.release();
-        delete ctx;
+        fmmbem_destroy(ctx);  // arena, streams, events and graphs made so far
         throw;
     }
     *out = ctx;

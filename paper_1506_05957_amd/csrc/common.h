@@ -183,6 +183,8 @@ struct NearMatrix {
     double *v64 = nullptr;
     float *v32 = nullptr;
     double *xs = nullptr;           // [n] the mat-vec input in sorted panel order
+    int64_t folded = 0;             // corrections added into the stored blocks
+    Correction rest;                // corrections whose pair has no stored block
 };
 
 // GMRES workspace, one per context (krylov.hip)
@@ -190,13 +192,19 @@ struct KrylovWork {
     int m = 0;
     int64_t n = 0;
     int nb = 0;              // row blocks of the dot-product kernels
+    int rpt = 1;             // rows per thread in those blocks
     double *V = nullptr;     // [m+1][n]
     double *w = nullptr;     // [n]
     double *r = nullptr;     // [n]
-    double *part = nullptr;  // [m+2][nb]
-    double *h = nullptr;     // [2*(m+2)] device: h1 | h2 (second pass) ; h[.. + m+1] = |w|^2
+    double *part1 = nullptr; // [m+1][nb] per-block partials of the first Gram-Schmidt pass
+    double *part2 = nullptr; // [m+1][nb] the second pass
+    double *partn = nullptr; // [nb] |w|^2
+    // Hessenberg column in pinned, device-mapped host memory, written by the
+    // kernels directly: h1[0..k], |w|^2 at k + 1, h2 at m + 2 + j
+    double *hcol = nullptr;      // host view, [2*(m+2)]
+    double *hcol_dev = nullptr;  // the same memory, device view
+    hipEvent_t ev_h = nullptr;   // the column of the last step is complete
     double *y = nullptr;     // [m+1]
-    unsigned int *ticket = nullptr;  // [m+2] arrival counters of the fused reductions
     DevArena arena;
 };
 
@@ -258,8 +266,8 @@ struct GmresState {
     hipStream_t st;
     KrylovWork *kw = nullptr;
     std::vector<double> H, cs, sn, g, yv;
-    double *hbuf = nullptr;  // pinned host
-    hipEvent_t ev_h = nullptr;  // the Hessenberg column has reached hbuf
+    double *hbuf = nullptr;     // kw->hcol
+    hipEvent_t ev_h = nullptr;  // kw->ev_h
     int it = 0, restarts = 0, converged = 0, k = 0;
     int64_t matvecs = 0;
     double bnorm = 0, beta = 0, rel = 1, true_rel = 1, rho_prev = 1;
@@ -293,10 +301,9 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
 // launch the near field (charges + P2P) of a mat-vec on x at precision prec
 // ahead of time; the next run_matvec with the same x and prec uses it
 void prefetch_near(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
-// stored near field (nearfield.hip): assemble at build; copy the input in
-// sorted order (nearm.xs), then one product on stream st
+// stored near field (nearfield.hip): assemble at build; one product on
+// stream st of the input in sorted order (nearm.xs, written by the charges)
 void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st);
-void sort_near_input(fmmbem_ctx *ctx, const double *x, hipStream_t st);
 void launch_near_stored(fmmbem_ctx *ctx, int prec, hipStream_t st);
 int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
               fmmbem_report *rep, hipStream_t st);

@@ -115,7 +115,7 @@ template <typename R> __device__ inline cplx<R> load_full(const cplx<R> *__restr
 }
 
 // ---------------------------------------------------------------------------
-// charges (a4): packed sources of this mat-vec, position and charge together so
+// charges: packed sources of this mat-vec, position and charge together so
 // that P2P can stream them with one wave-uniform (scalar) load per source.
 // FP64: absolute position; FP32: position relative to the leaf centre.
 template <typename R, bool STOKES> struct Src;
@@ -128,16 +128,24 @@ template <> struct Src<float, true> { float x, y, z, f0, f1, f2, pad0, pad1; };
 // FMMBEM_LAPLACE_DL (dipoles w x n_j of the source panel, n outward).
 template <int KIND> constexpr bool vec_src() { return KIND != FMMBEM_LAPLACE_SL; }
 
+// With xs (the stored near field), the first thread of every panel also
+// copies the panel's input value(s) to xs in sorted order.
 template <typename R, int KIND>
 __global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const double *__restrict__ sp,
                           const float *__restrict__ sp32, const double *__restrict__ nrm,
-                          const double *__restrict__ x, Src<R, vec_src<KIND>()> *__restrict__ src)
+                          const double *__restrict__ x, Src<R, vec_src<KIND>()> *__restrict__ src,
+                          double *__restrict__ xs)
 {
+    constexpr int NQ = KIND == FMMBEM_STOKES_SL ? 3 : 1;
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ns = 4 * nt;
     if (s >= ns)
         return;
     const int64_t o = perm[s >> 2];
+    if (xs && (s & 3) == 0)
+#pragma unroll
+        for (int a = 0; a < NQ; ++a)
+            xs[NQ * (s >> 2) + a] = x[NQ * o + a];
     const double w = sp[3 * ns + s];
     Src<R, vec_src<KIND>()> v;
     if constexpr (sizeof(R) == 8) {
@@ -168,16 +176,27 @@ __global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const do
 }
 
 // ---------------------------------------------------------------------------
-// P2M (a5): one block per leaf.  Thread = (order m, source slice): it runs the
-// recurrence of column m (n = m..p) for every source of its slice and
-// accumulates q conj(R_n^m((y - c) / s)); slices are summed in a fixed order.
-// PM is a compile-time bound on p so that the accumulators stay in registers.
+// P2M: one block per leaf.  Thread = (order m, source slice): it accumulates
+// q conj(R_n^m((y - c) / s)) over the sources of its slice for n = m..p, and
+// the slices are summed in a fixed order.  PM is a compile-time bound on p so
+// that the accumulators stay in registers.
+//
+// The harmonics of one source come from one branch-free sweep n = 1..PM whose
+// step coefficients depend on (n, m) only and are set up once per thread:
+//   C_n = al_n (x + i y) C_{n-1} + be_n z C_{n-1} - ga_n r^2 C_{n-2},  C_0 = 1,
+// with al_n = -1/(2n) for n <= m (the diagonal R_n^n), and for n > m
+// be_n = (2n - 1)/((n - m)(n + m)), ga_n = 1/((n - m)(n + m)) (ga = 0 at
+// n = m + 1, where R_{m-1}^m = 0), so that C_n = R_n^n below the column and
+// R_n^m on it.  Entries below the column are accumulated too and never written.
+// Channels are taken CG at a time (Stokes: 4 in FP32, 2 in FP64), so that
+// every harmonic serves CG channels.
 template <typename R, int NCH, int PM>
 __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__restrict__ leaves,
                                              const int32_t *__restrict__ box_i, const double *__restrict__ box_r,
                                              double side, const Src<R, NCH == 4> *__restrict__ src,
                                              cplx<R> *__restrict__ M)
 {
+    constexpr int CG = NCH == 1 ? 1 : (sizeof(R) == 4 ? 4 : 2);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<R> *red = reinterpret_cast<cplx<R> *>(smem_raw);  // [nsl][nc]
     const int b = leaves[blockIdx.x];
@@ -189,11 +208,21 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
     const bool active = sl < nsl;
     const int nc = ncoef(p);
     const R is = (R)(1.0 / s);
-    for (int ch = 0; ch < NCH; ++ch) {
-        R are[PM + 1], aim[PM + 1];
+    R al[PM + 1], be[PM + 1], ga[PM + 1];
 #pragma unroll
-        for (int n = 0; n <= PM; ++n)
-            are[n] = aim[n] = 0;
+    for (int n = 1; n <= PM; ++n) {
+        const R f = (n > m && n <= p) ? inv_int<R>((n - m) * (n + m)) : R(0);
+        al[n] = n <= m ? -inv_int<R>(2 * n) : R(0);
+        be[n] = R(2 * n - 1) * f;
+        ga[n] = n >= m + 2 ? f : R(0);
+    }
+    for (int c0 = 0; c0 < NCH; c0 += CG) {
+        R are[CG][PM + 1], aim[CG][PM + 1];
+#pragma unroll
+        for (int g = 0; g < CG; ++g)
+#pragma unroll
+            for (int n = 0; n <= PM; ++n)
+                are[g][n] = aim[g][n] = 0;
         if (active) {
             for (int64_t si = 4 * (int64_t)pb + sl; si < 4 * (int64_t)pe; si += nsl) {
                 const Src<R, NCH == 4> sv = src[si];
@@ -207,65 +236,63 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
                     y = sv.y;
                     z = sv.z;
                 }
-                R qq;
+                R qq[CG];
                 if constexpr (NCH == 1) {
-                    qq = sv.q;
+                    qq[0] = sv.q;
                 } else {
-                    qq = ch == 0 ? sv.f0 : ch == 1 ? sv.f1 : ch == 2 ? sv.f2 : (sv.f0 * x + sv.f1 * y) + sv.f2 * z;
+                    const R q4 = (sv.f0 * x + sv.f1 * y) + sv.f2 * z;
+                    const R all[4] = {sv.f0, sv.f1, sv.f2, q4};
+#pragma unroll
+                    for (int g = 0; g < CG; ++g)
+                        qq[g] = all[(c0 + g) & 3];
                 }
                 x *= is;
                 y *= is;
                 z *= is;
                 const R r2 = x * x + y * y + z * z;
-                R dre = 1, dim = 0;
-                for (int k = 1; k <= m; ++k) {
-                    R f = -inv_int<R>(2 * k);
-                    R a = f * (x * dre - y * dim), bb = f * (x * dim + y * dre);
-                    dre = a;
-                    dim = bb;
-                }
-                R cr = 0, ci = 0, pr = 0, pi = 0;
+                R cr = 1, ci = 0, pr = 0, pi = 0;
 #pragma unroll
-                for (int n = 0; n <= PM; ++n) {
-                    if (n <= p) {
-                        if (n == m) {
-                            cr = dre;
-                            ci = dim;
-                        } else if (n > m) {
-                            R f = inv_int<R>((n - m) * (n + m));
-                            R a = R(2 * n - 1) * z;
-                            R nr = (a * cr - r2 * pr) * f, ni = (a * ci - r2 * pi) * f;
-                            pr = cr;
-                            pi = ci;
-                            cr = nr;
-                            ci = ni;
-                        }
-                        if (n >= m) {
-                            are[n] += qq * cr;
-                            aim[n] -= qq * ci;
-                        }
+                for (int g = 0; g < CG; ++g)
+                    are[g][0] += qq[g];
+#pragma unroll
+                for (int n = 1; n <= PM; ++n) {
+                    const R A = al[n] * x + be[n] * z, B = al[n] * y, G = ga[n] * r2;
+                    const R nr = (A * cr - B * ci) - G * pr, ni = (A * ci + B * cr) - G * pi;
+                    pr = cr;
+                    pi = ci;
+                    cr = nr;
+                    ci = ni;
+#pragma unroll
+                    for (int g = 0; g < CG; ++g) {
+                        are[g][n] += qq[g] * cr;
+                        aim[g][n] -= qq[g] * ci;
                     }
                 }
             }
+        }
 #pragma unroll
-            for (int n = 0; n <= PM; ++n)
-                if (n <= p && n >= m)
-                    red[sl * nc + cidx(n, m)] = cplx<R>{are[n], aim[n]};
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < nc; t += blockDim.x) {
-            R sr = 0, si2 = 0;
-            for (int k = 0; k < nsl; ++k) {
-                sr += red[k * nc + t].re;
-                si2 += red[k * nc + t].im;
+        for (int g = 0; g < CG; ++g) {
+            if (active) {
+#pragma unroll
+                for (int n = 0; n <= PM; ++n)
+                    if (n <= p && n >= m)
+                        red[sl * nc + cidx(n, m)] = cplx<R>{are[g][n], aim[g][n]};
             }
-            M[((int64_t)b * NCH + ch) * ncs + t] = cplx<R>{sr, si2};
+            __syncthreads();
+            for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+                R sr = 0, si2 = 0;
+                for (int k = 0; k < nsl; ++k) {
+                    sr += red[k * nc + t].re;
+                    si2 += red[k * nc + t].im;
+                }
+                M[((int64_t)b * NCH + c0 + g) * ncs + t] = cplx<R>{sr, si2};
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
-// P2M of dipole sources (the double layer, f3): a moment d = w x n at y has
+// P2M of dipole sources (the double layer): a moment d = w x n at y has
 // the multipole sum conj(d . grad R_n^m(y - c)), and with the gradient
 // identities of the factorial-normalised harmonics
 //   d . grad R_n^m = (dx - i dy)/2 R_{n-1}^{m+1} - (dx + i dy)/2 R_{n-1}^{m-1}
@@ -405,7 +432,7 @@ __global__ __launch_bounds__(256) void k_p2m_dipole(int p, int ncs, const int32_
 }
 
 // ---------------------------------------------------------------------------
-// M2M (a6) and L2L (a8) as products with the octant operators: the child C
+// M2M and L2L as products with the octant operators: the child C
 // sits at delta = (c_C - c_P) / s_P, one of the 8 offsets (+-1/2, +-1/2, +-1/2),
 // and in the scaled expansions
 //   M2M: M_n^m(P) += sum_{j <= n} 2^-j sum_mm conj(R_{n-j}^{m-mm}(delta)) M_j^mm(C)
@@ -532,7 +559,7 @@ __global__ void k_m2m_sum(int p, int ncs, int npar, const int32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// M2L (a7), in two passes.  Pass 1, one block per chunk of pairs sharing a
+// M2L, in two passes.  Pass 1, one block per chunk of pairs sharing a
 // translation (D, eT, eS), computes per pair the scaled translation
 //   L_k^l = (-1)^k 2^(-eT (k+1)) sum_{n,m} 2^(-eS n) M_n^m I_{n+k}^{m+l}(D 2^-e)
 // (sigma the larger half-size) and writes it to Y[pair]; pass 2 sums Y over
@@ -830,14 +857,51 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_
 }
 
 // ---------------------------------------------------------------------------
-// L2P (a9): one block per leaf, one thread per target.
-template <typename R, bool STOKES>
+// The combine of a mat-vec for sorted target i: y[perm i] = pref (near +
+// far + sum_e S_ie x_e) over the correction entries e of row i, plus x / 2
+// for the second-kind operator; yf holds the far field of the target.
+struct CombineArgs {
+    const int32_t *perm, *cptr, *ccol;
+    const double *cval, *x, *ynear;
+    double pref;
+    double *y;
+};
+
+template <int KIND>
+__device__ inline void combine_target(const CombineArgs &A, int64_t i, const double *yf)
+{
+    const int64_t o = A.perm[i];
+    if constexpr (KIND != FMMBEM_STOKES_SL) {
+        double acc = A.ynear[i] + yf[0];
+        for (int e = A.cptr[i]; e < A.cptr[i + 1]; ++e)
+            acc += A.cval[e] * A.x[A.ccol[e]];
+        A.y[o] = KIND == FMMBEM_LAPLACE_DL ? 0.5 * A.x[o] + A.pref * acc : A.pref * acc;
+    } else {
+        double a0 = A.ynear[3 * i] + yf[0], a1 = A.ynear[3 * i + 1] + yf[1], a2 = A.ynear[3 * i + 2] + yf[2];
+        for (int e = A.cptr[i]; e < A.cptr[i + 1]; ++e) {
+            const int64_t jo = A.ccol[e];
+            const double *v = A.cval + 9 * (int64_t)e;
+            const double t0 = A.x[3 * jo], t1 = A.x[3 * jo + 1], t2 = A.x[3 * jo + 2];
+            a0 += (v[0] * t0 + v[1] * t1) + v[2] * t2;
+            a1 += (v[3] * t0 + v[4] * t1) + v[5] * t2;
+            a2 += (v[6] * t0 + v[7] * t1) + v[8] * t2;
+        }
+        A.y[3 * o] = A.pref * a0;
+        A.y[3 * o + 1] = A.pref * a1;
+        A.y[3 * o + 2] = A.pref * a2;
+    }
+}
+
+// L2P: one block per leaf, one thread per target, which also combines the
+// target's far field with its near field (joined before the launch).
+template <typename R, int KIND>
 __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__restrict__ leaves,
                                             const int32_t *__restrict__ box_i, const double *__restrict__ box_r,
                                             double side, int64_t nt, const double *__restrict__ tc,
                                             const float *__restrict__ tc32, const cplx<R> *__restrict__ L,
-                                            double *__restrict__ yfar)
+                                            CombineArgs ca)
 {
+    constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     constexpr int NCH = STOKES ? 4 : 1;
     constexpr int NV = STOKES ? 3 : 1;        // potentials evaluated
     constexpr int NG = STOKES ? 12 : 0;       // gradients evaluated (channel x direction)
@@ -929,23 +993,26 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
             }
         }
         if constexpr (!STOKES) {
-            yfar[i] = (double)pot[0] / s;
+            const double yf = (double)pot[0] / s;
+            combine_target<KIND>(ca, i, &yf);
         } else {
             const double is = 1.0 / s, is2 = is * is;
             const double xr[3] = {(double)x * s, (double)y * s, (double)z * s};  // x - c
+            double yf[3];
             for (int dir = 0; dir < 3; ++dir) {
                 double u = (double)pot[dir] * is;
                 for (int a = 0; a < 3; ++a)
                     u -= xr[a] * (double)grd[3 * a + dir] * is2;
                 u += (double)grd[9 + dir] * is2;
-                yfar[3 * (int64_t)i + dir] = u;
+                yf[dir] = u;
             }
+            combine_target<KIND>(ca, i, yf);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// P2P (a10): one block per work unit (at most 64 targets of one leaf).  The
+// P2P: one block per work unit (at most 64 targets of one leaf).  The
 // NW waves of the block take the unit's source chunks round robin.  With n
 // targets a wave runs P = floor(64 / n) phases: lane (ph, t) sums over the
 // sources ph, ph + P, ... of the chunk, so that a small leaf still fills the
@@ -1122,38 +1189,14 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, 
 }
 
 // ---------------------------------------------------------------------------
-// a11 + a12: y[perm i] = pref * (far + near + sum_j S_ij x_j), plus x / 2 for
-// the second-kind operator (pref = -1/(4 pi) there)
+// combine without a far field (no accepted box pair): y_far is zero
 template <int KIND>
-__global__ void k_combine(int64_t nt, const int32_t *__restrict__ perm, const int32_t *__restrict__ cptr,
-                          const int32_t *__restrict__ ccol, const double *__restrict__ cval,
-                          const double *__restrict__ x, const double *__restrict__ ynear,
-                          const double *__restrict__ yfar, double pref, double *__restrict__ y)
+__global__ void k_combine(int64_t nt, CombineArgs ca, const double *__restrict__ yfar)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nt)
-        return;
-    const int64_t o = perm[i];
-    if constexpr (KIND != FMMBEM_STOKES_SL) {
-        double acc = ynear[i] + yfar[i];
-        for (int e = cptr[i]; e < cptr[i + 1]; ++e)
-            acc += cval[e] * x[ccol[e]];
-        y[o] = KIND == FMMBEM_LAPLACE_DL ? 0.5 * x[o] + pref * acc : pref * acc;
-    } else {
-        double a0 = ynear[3 * i] + yfar[3 * i], a1 = ynear[3 * i + 1] + yfar[3 * i + 1],
-               a2 = ynear[3 * i + 2] + yfar[3 * i + 2];
-        for (int e = cptr[i]; e < cptr[i + 1]; ++e) {
-            const int64_t jo = ccol[e];
-            const double *v = cval + 9 * (int64_t)e;
-            const double t0 = x[3 * jo], t1 = x[3 * jo + 1], t2 = x[3 * jo + 2];
-            a0 += (v[0] * t0 + v[1] * t1) + v[2] * t2;
-            a1 += (v[3] * t0 + v[4] * t1) + v[5] * t2;
-            a2 += (v[6] * t0 + v[7] * t1) + v[8] * t2;
-        }
-        y[3 * o] = pref * a0;
-        y[3 * o + 1] = pref * a1;
-        y[3 * o + 2] = pref * a2;
-    }
+    constexpr int NQ = KIND == FMMBEM_STOKES_SL ? 3 : 1;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nt)
+        combine_target<KIND>(ca, i, yfar + NQ * i);
 }
 
 // charges of this mat-vec on st, then P2P on the side stream
@@ -1172,10 +1215,9 @@ void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
         FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
 
     stage_begin(ctx, SO + 4, st, &ev);
-    k_charges<R, KIND><<<grid_for(ns, 256), 256, 0, st>>>(nt, T.perm, G.sp, G.sp32, G.nrm, x, src);
+    k_charges<R, KIND><<<grid_for(ns, 256), 256, 0, st>>>(nt, T.perm, G.sp, G.sp32, G.nrm, x, src,
+                                                          ctx->nearm.v64 ? ctx->nearm.xs : nullptr);
     FB_HIP(hipGetLastError());
-    if (ctx->nearm.v64)
-        sort_near_input(ctx, x, st);
     stage_end(ctx, SO + 4, st, ev);
 
     FB_HIP(hipEventRecord(ctx->ev_fork, st));
@@ -1200,9 +1242,12 @@ void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
     ctx->near_pending = true;
 }
 
-// far field of order p on st from the charges of launch_near, then st joins the side stream
+// The far field of order p on st, P2M through L2P, from the charges that the
+// near-field launch wrote before it; st joins the side stream before L2P,
+// which combines far and near field into y.  Without a far field: y_far = 0,
+// join and combine.
 template <typename R, int KIND>
-void launch_fmm(fmmbem_ctx *ctx, int p, hipStream_t st)
+void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
 {
     constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     constexpr int NCH = STOKES ? 4 : 1;
@@ -1314,16 +1359,39 @@ void launch_fmm(fmmbem_ctx *ctx, int p, hipStream_t st)
                                                                      P.level_list, T.box_i, T.box_r, L, L);
             FB_HIP(hipGetLastError());
         }
-        k_l2p<R, STOKES><<<T.nleaf, 64, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L,
-                                                 ctx->y_far);
+        FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // L2P combines with the near field
+        k_l2p<R, KIND><<<T.nleaf, 64, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L, ca);
         FB_HIP(hipGetLastError());
         stage_end(ctx, SO + 3, st, ev);
     } else {
+        hipEvent_t ev4;
+        stage_begin(ctx, SO + 4, st, &ev4);
         FB_HIP(hipMemsetAsync(ctx->y_far, 0, sizeof(double) * ctx->n, st));
+        FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+        k_combine<KIND><<<grid_for(nt, 64), 64, 0, st>>>(nt, ca, ctx->y_far);
+        FB_HIP(hipGetLastError());
+        stage_end(ctx, SO + 4, st, ev4);
     }
+}
 
-    FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
-    ctx->near_pending = false;
+void far_dispatch(fmmbem_ctx *ctx, int p, int prec, const CombineArgs &ca, hipStream_t st)
+{
+    const int kind = ctx->kernel;
+    if (prec == FMMBEM_FP64) {
+        if (kind == FMMBEM_STOKES_SL)
+            far_chain<double, FMMBEM_STOKES_SL>(ctx, p, ca, st);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            far_chain<double, FMMBEM_LAPLACE_DL>(ctx, p, ca, st);
+        else
+            far_chain<double, FMMBEM_LAPLACE_SL>(ctx, p, ca, st);
+    } else {
+        if (kind == FMMBEM_STOKES_SL)
+            far_chain<float, FMMBEM_STOKES_SL>(ctx, p, ca, st);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            far_chain<float, FMMBEM_LAPLACE_DL>(ctx, p, ca, st);
+        else
+            far_chain<float, FMMBEM_LAPLACE_SL>(ctx, p, ca, st);
+    }
 }
 
 void near_dispatch(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
@@ -1365,36 +1433,14 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
     ctx->spec_prec = -1;
     if (!have_near)
         near_dispatch(ctx, prec, x, st);
-    if (prec == FMMBEM_FP64) {
-        if (kind == FMMBEM_STOKES_SL)
-            launch_fmm<double, FMMBEM_STOKES_SL>(ctx, p, st);
-        else if (kind == FMMBEM_LAPLACE_DL)
-            launch_fmm<double, FMMBEM_LAPLACE_DL>(ctx, p, st);
-        else
-            launch_fmm<double, FMMBEM_LAPLACE_SL>(ctx, p, st);
-    } else {
-        if (kind == FMMBEM_STOKES_SL)
-            launch_fmm<float, FMMBEM_STOKES_SL>(ctx, p, st);
-        else if (kind == FMMBEM_LAPLACE_DL)
-            launch_fmm<float, FMMBEM_LAPLACE_DL>(ctx, p, st);
-        else
-            launch_fmm<float, FMMBEM_LAPLACE_SL>(ctx, p, st);
-    }
-    hipEvent_t ev;
-    const int SO = prec == FMMBEM_FP64 ? 0 : 5;
-    stage_begin(ctx, SO + 4, st, &ev);
-#define FB_COMBINE(KIND, PREF)                                                                                  \
-    k_combine<KIND><<<grid_for(ctx->nt, 64), 64, 0, st>>>(ctx->nt, ctx->tree.perm, ctx->corr.ptr, ctx->corr.col_orig, \
-                                                          ctx->corr.val, x, ctx->y_near, ctx->y_far, PREF, y)
-    if (kind == FMMBEM_STOKES_SL)
-        FB_COMBINE(FMMBEM_STOKES_SL, -1.0 / (8.0 * M_PI * ctx->prm.mu));
-    else if (kind == FMMBEM_LAPLACE_DL)
-        FB_COMBINE(FMMBEM_LAPLACE_DL, -1.0 / (4.0 * M_PI));
-    else
-        FB_COMBINE(FMMBEM_LAPLACE_SL, 1.0 / (4.0 * M_PI));
-#undef FB_COMBINE
-    FB_HIP(hipGetLastError());
-    stage_end(ctx, SO + 4, st, ev);
+    // stored near field: its blocks already hold the corrections of their pairs
+    const Correction &C = ctx->prm.near_stored ? ctx->nearm.rest : ctx->corr;
+    const double pref = kind == FMMBEM_STOKES_SL   ? -1.0 / (8.0 * M_PI * ctx->prm.mu)
+                        : kind == FMMBEM_LAPLACE_DL ? -1.0 / (4.0 * M_PI)
+                                                    : 1.0 / (4.0 * M_PI);
+    const CombineArgs ca{ctx->tree.perm, C.ptr, C.col_orig, C.val, x, ctx->y_near, pref, y};
+    far_dispatch(ctx, p, prec, ca, st);  // ends with the join and the combine
+    ctx->near_pending = false;
 }
 
 }  // namespace fmmbem

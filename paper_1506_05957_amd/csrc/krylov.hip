@@ -20,144 +20,212 @@ namespace fmmbem {
 namespace {
 
 constexpr int DOT_BLOCK = 256;
-constexpr int DOT_PER_THREAD = 2;
+constexpr int DOT_NWV = DOT_BLOCK / 64;
+constexpr int DOT_MAX_BLOCKS = 256;  // row blocks; rows per thread grow beyond that
+constexpr int AXPY_UNROLL = 8;
 
-// Classical Gram-Schmidt dots: block (b, g) takes the rows of block b and the
-// vectors j = g CGS_JG .. + CGS_JG - 1 and writes part[j][b] = V_j . w' over its
-// rows, where w' = w - sum_{j < nv} hprev[j] V_j when hprev is given (the
-// first pass's update, recomputed per block and not stored) and w' = w
-// otherwise.  The last block to arrive (atomic ticket) sums part[j][0..nb) in
-// block order into out[j] for every j and re-arms the ticket.
-constexpr int CGS_JG = 8;
-__global__ __launch_bounds__(DOT_BLOCK) void k_cgs_dots(int64_t n, const double *__restrict__ V, int64_t ldv, int nv,
-                                                         const double *__restrict__ hprev, const double *__restrict__ w,
-                                                         double *__restrict__ part, int nb, double *__restrict__ out,
-                                                         unsigned int *__restrict__ ticket)
+// The reductions of the Arnoldi step carry no atomics or fences: each kernel
+// writes one partial per row block, and the next kernel of the step (ordered
+// after it on the stream) sums those partials again in every block, in one
+// fixed order, so that all blocks see bit-identical coefficients and a solve
+// is reproducible.  Row block b holds rows b R + k DOT_BLOCK + t, k < rpt,
+// R = rpt DOT_BLOCK.
+
+// out[j] = sum_b part[j nb + b] for j < nv, into LDS: the waves take the
+// vectors four at a time, lanes stride over b, then a shuffle tree.
+__device__ void block_sums(const double *__restrict__ part, int nb, int nv, double *__restrict__ out)
 {
-    constexpr int NWV = DOT_BLOCK / 64;
-    __shared__ double sh[CGS_JG][NWV];
-    __shared__ bool last;
-    const int b = blockIdx.x, j0 = blockIdx.y * CGS_JG;
-    const int nj = min(CGS_JG, nv - j0);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t base = (int64_t)b * DOT_BLOCK * DOT_PER_THREAD;
-    double wl[DOT_PER_THREAD];
+    for (int jb = 0; jb < nv; jb += 4 * DOT_NWV) {
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = lane; k < nb; k += 64) {
+            double v[4];
 #pragma unroll
-    for (int k = 0; k < DOT_PER_THREAD; ++k) {
-        const int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
-        double x = 0.0;
-        if (i < n) {
-            x = w[i];
-            if (hprev)
-                for (int j = 0; j < nv; ++j)
-                    x -= hprev[j] * V[(int64_t)j * ldv + i];
-        }
-        wl[k] = x;
-    }
-    for (int jj = 0; jj < nj; ++jj) {
-        const double *v = V + (int64_t)(j0 + jj) * ldv;
-        double s = 0.0;
+            for (int r = 0; r < 4; ++r) {
+                const int j = jb + r * DOT_NWV + wv;
+                v[r] = j < nv ? part[(int64_t)j * nb + k] : 0.0;
+            }
 #pragma unroll
-        for (int k = 0; k < DOT_PER_THREAD; ++k) {
-            const int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
-            if (i < n)
-                s += v[i] * wl[k];
+            for (int r = 0; r < 4; ++r)
+                t[r] += v[r];
         }
+#pragma unroll
         for (int off = 32; off > 0; off >>= 1)
-            s += __shfl_down(s, off, 64);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                t[r] += __shfl_down(t[r], off, 64);
         if (lane == 0)
-            sh[jj][wv] = s;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jb + r * DOT_NWV + wv;
+                if (j < nv)
+                    out[j] = t[r];
+            }
     }
-    __syncthreads();
-    if ((int)threadIdx.x < nj) {
-        double t = 0.0;
-        for (int k = 0; k < NWV; ++k)
-            t += sh[threadIdx.x][k];
-        part[(int64_t)(j0 + threadIdx.x) * nb + b] = t;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0)
-        last = atomicAdd(ticket, 1u) == (unsigned)(nb * gridDim.y - 1);
-    __syncthreads();
-    if (!last)
-        return;
-    __threadfence();
-    for (int j = threadIdx.x; j < nv; j += DOT_BLOCK) {
-        double t = 0.0;
-        for (int k = 0; k < nb; ++k)
-            t += __builtin_nontemporal_load(&part[(int64_t)j * nb + k]);
-        out[j] = t;
-    }
-    if (threadIdx.x == 0)
-        *ticket = 0u;
 }
 
-// w -= sum_{j<nv} (h1[j] + h2[j]) V_j (both Gram-Schmidt passes), and |w|^2
-// into *nrm2 (same last-block scheme)
-__global__ __launch_bounds__(DOT_BLOCK) void k_update_norm(int64_t n, const double *__restrict__ V, int64_t ldv,
-                                                            int nv, const double *__restrict__ h1,
-                                                            const double *__restrict__ h2, double *__restrict__ w,
-                                                            double *__restrict__ part, int nb,
-                                                            double *__restrict__ nrm2, unsigned int *__restrict__ ticket)
+// Sum over the block of one value per thread (shuffle tree per wave, then
+// the waves in order); the result is valid in thread 0.
+__device__ double block_total(double s, double *__restrict__ sh)
 {
-    __shared__ double sh[DOT_BLOCK / 64];
-    __shared__ bool last;
-    const int b = blockIdx.x;
-    double s = 0.0;
-    const int64_t base = (int64_t)b * DOT_BLOCK * DOT_PER_THREAD;
-    for (int k = 0; k < DOT_PER_THREAD; ++k) {
-        int64_t i = base + (int64_t)k * DOT_BLOCK + threadIdx.x;
-        if (i < n) {
-            double x = w[i];
-            for (int j = 0; j < nv; ++j)
-                x -= (h1[j] + h2[j]) * V[(int64_t)j * ldv + i];
-            w[i] = x;
-            s += x * x;
-        }
-    }
     for (int off = 32; off > 0; off >>= 1)
         s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0)
         sh[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < DOT_BLOCK / 64; ++k)
-            t += sh[k];
-        part[b] = t;
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == (unsigned)(nb - 1);
-    }
-    __syncthreads();
-    if (!last)
-        return;
-    __threadfence();
     double t = 0.0;
-    for (int k = threadIdx.x; k < nb; k += DOT_BLOCK)
-        t += __builtin_nontemporal_load(&part[k]);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < DOT_NWV; ++k)
+            t += sh[k];
+    return t;
+}
+
+// x - sum_{j < nv} c[j] V_j[i] in the order j = 0, 1, ...; the loads of
+// AXPY_UNROLL vectors are issued together so that their latencies overlap.
+// With c2, the coefficient is c[j] + c2[j].
+__device__ inline double sub_combination(double x, const double *__restrict__ V, int64_t ldv, int nv, int64_t i,
+                                         const double *__restrict__ c, const double *__restrict__ c2)
+{
+    int j = 0;
+    for (; j + AXPY_UNROLL <= nv; j += AXPY_UNROLL) {
+        double v[AXPY_UNROLL];
+#pragma unroll
+        for (int u = 0; u < AXPY_UNROLL; ++u)
+            v[u] = V[(int64_t)(j + u) * ldv + i];
+#pragma unroll
+        for (int u = 0; u < AXPY_UNROLL; ++u)
+            x -= (c2 ? c[j + u] + c2[j + u] : c[j + u]) * v[u];
+    }
+    for (; j < nv; ++j)
+        x -= (c2 ? c[j] + c2[j] : c[j]) * V[(int64_t)j * ldv + i];
+    return x;
+}
+
+// Classical Gram-Schmidt dots: block (b, g) takes row block b and the vectors
+// j = g CGS_JG .. + CGS_JG - 1 and writes part[j][b] = V_j . w' over its rows,
+// where w' = w - sum_{j < nv} h1[j] V_j when the first pass's partials hpart
+// are given (h1 summed from them, the update recomputed per block and not
+// stored) and w' = w otherwise.  Dynamic LDS: nv doubles.
+constexpr int CGS_JG = 8;
+__global__ __launch_bounds__(DOT_BLOCK) void k_cgs_dots(int64_t n, int rpt, const double *__restrict__ V, int64_t ldv,
+                                                         int nv, const double *__restrict__ hpart,
+                                                         const double *__restrict__ w, double *__restrict__ part,
+                                                         int nb)
+{
+    extern __shared__ double hs[];  // [nv] first-pass coefficients
+    __shared__ double sh[CGS_JG][DOT_NWV];
+    const int b = blockIdx.x, j0 = blockIdx.y * CGS_JG;
+    const int nj = min(CGS_JG, nv - j0);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (hpart) {
+        block_sums(hpart, nb, nv, hs);
+        __syncthreads();
+    }
+    double s[CGS_JG];
+#pragma unroll
+    for (int jj = 0; jj < CGS_JG; ++jj)
+        s[jj] = 0.0;
+    const int64_t base = (int64_t)b * rpt * DOT_BLOCK + threadIdx.x;
+    for (int k = 0; k < rpt; ++k) {
+        const int64_t i = base + (int64_t)k * DOT_BLOCK;
+        if (i >= n)
+            break;
+        double x = w[i];
+        if (hpart)
+            x = sub_combination(x, V, ldv, nv, i, hs, nullptr);
+        double v[CGS_JG];
+#pragma unroll
+        for (int jj = 0; jj < CGS_JG; ++jj)
+            v[jj] = jj < nj ? V[(int64_t)(j0 + jj) * ldv + i] : 0.0;
+#pragma unroll
+        for (int jj = 0; jj < CGS_JG; ++jj)
+            s[jj] += v[jj] * x;
+    }
+#pragma unroll
     for (int off = 32; off > 0; off >>= 1)
-        t += __shfl_down(t, off, 64);
-    if ((threadIdx.x & 63) == 0)
-        sh[threadIdx.x >> 6] = t;
+#pragma unroll
+        for (int jj = 0; jj < CGS_JG; ++jj)
+            s[jj] += __shfl_down(s[jj], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int jj = 0; jj < CGS_JG; ++jj)
+            sh[jj][wv] = s[jj];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = 0.0;
-        for (int k = 0; k < DOT_BLOCK / 64; ++k)
-            r += sh[k];
-        *nrm2 = r;
-        *ticket = 0u;
+    if ((int)threadIdx.x < nj) {
+        double t = 0.0;
+        for (int k = 0; k < DOT_NWV; ++k)
+            t += sh[threadIdx.x][k];
+        part[(int64_t)(j0 + threadIdx.x) * nb + b] = t;
     }
 }
 
-// v = w / sqrt(nrm2[0])
-__global__ void k_normalize(int64_t n, const double *__restrict__ w, const double *__restrict__ nrm2,
-                            double *__restrict__ v)
+// h1, h2 summed from the two passes' partials; w -= sum_{j<nv} (h1[j] + h2[j])
+// V_j, and the partial of |w|^2 of this row block into partn[b].  Block 0
+// also writes h1 to hout[0..nv) and h2 to hout[off2..off2 + nv) for the host.
+// Dynamic LDS: 2 nv doubles.
+__global__ __launch_bounds__(DOT_BLOCK) void k_update_norm(int64_t n, int rpt, const double *__restrict__ V,
+                                                            int64_t ldv, int nv, const double *__restrict__ part1,
+                                                            const double *__restrict__ part2, int nb,
+                                                            double *__restrict__ w, double *__restrict__ partn,
+                                                            double *__restrict__ hout, int off2)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    v[i] = w[i] / sqrt(nrm2[0]);
+    extern __shared__ double hs[];  // [2][nv]
+    __shared__ double sh[DOT_NWV];
+    const int b = blockIdx.x;
+    block_sums(part1, nb, nv, hs);
+    block_sums(part2, nb, nv, hs + nv);
+    __syncthreads();
+    if (b == 0)
+        for (int j = threadIdx.x; j < nv; j += DOT_BLOCK) {
+            hout[j] = hs[j];
+            hout[off2 + j] = hs[nv + j];
+        }
+    double s = 0.0;
+    const int64_t base = (int64_t)b * rpt * DOT_BLOCK + threadIdx.x;
+    for (int k = 0; k < rpt; ++k) {
+        const int64_t i = base + (int64_t)k * DOT_BLOCK;
+        if (i >= n)
+            break;
+        const double x = sub_combination(w[i], V, ldv, nv, i, hs, hs + nv);
+        w[i] = x;
+        s += x * x;
+    }
+    const double t = block_total(s, sh);
+    if (threadIdx.x == 0)
+        partn[b] = t;
+}
+
+// v = w / sqrt(nrm2) with nrm2 summed from the partials partn[0..nb); block 0
+// also writes nrm2 to *nrm2_out when given.
+__global__ __launch_bounds__(DOT_BLOCK) void k_normalize(int64_t n, int rpt, const double *__restrict__ w,
+                                                          const double *__restrict__ partn, int nb,
+                                                          double *__restrict__ v, double *__restrict__ nrm2_out)
+{
+    __shared__ double tot;
+    block_sums(partn, nb, 1, &tot);
+    __syncthreads();
+    const double nrm2 = tot;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nrm2_out)
+        *nrm2_out = nrm2;
+    const double inv = 1.0 / sqrt(nrm2);
+    const int64_t base = (int64_t)blockIdx.x * rpt * DOT_BLOCK + threadIdx.x;
+    for (int k = 0; k < rpt; ++k) {
+        const int64_t i = base + (int64_t)k * DOT_BLOCK;
+        if (i >= n)
+            break;
+        v[i] = w[i] * inv;
+    }
+}
+
+// out[j] = sum_b part[j nb + b], j < nv (one block)
+__global__ __launch_bounds__(DOT_BLOCK) void k_sum_parts(const double *__restrict__ part, int nb, int nv,
+                                                          double *__restrict__ out)
+{
+    extern __shared__ double hs[];
+    block_sums(part, nb, nv, hs);
+    __syncthreads();
+    for (int j = threadIdx.x; j < nv; j += DOT_BLOCK)
+        out[j] = hs[j];
 }
 
 // x += sum_{j<nv} y[j] V_j
@@ -168,7 +236,17 @@ __global__ void k_xupdate(int64_t n, const double *__restrict__ V, int64_t ldv, 
     if (i >= n)
         return;
     double s = x[i];
-    for (int j = 0; j < nv; ++j)
+    int j = 0;
+    for (; j + AXPY_UNROLL <= nv; j += AXPY_UNROLL) {
+        double v[AXPY_UNROLL];
+#pragma unroll
+        for (int u = 0; u < AXPY_UNROLL; ++u)
+            v[u] = V[(int64_t)(j + u) * ldv + i];
+#pragma unroll
+        for (int u = 0; u < AXPY_UNROLL; ++u)
+            s += y[j + u] * v[u];
+    }
+    for (; j < nv; ++j)
         s += y[j] * V[(int64_t)j * ldv + i];
     x[i] = s;
 }
@@ -180,44 +258,68 @@ __global__ void k_sub(int64_t n, const double *__restrict__ b, const double *__r
         r[i] = b[i] - a[i];
 }
 
+void release_work(KrylovWork *kw)
+{
+    kw->arena.release();
+    if (kw->hcol)
+        (void)hipHostFree(kw->hcol);
+    if (kw->ev_h)
+        (void)hipEventDestroy(kw->ev_h);
+    delete kw;
+}
+
 KrylovWork *get_work(fmmbem_ctx *ctx, int m)
 {
     KrylovWork *kw = ctx->kw;
     if (kw && kw->m >= m)
         return kw;
     if (kw) {
-        kw->arena.release();
-        delete kw;
+        FB_HIP(hipDeviceSynchronize());  // nothing may still use the old workspace
+        release_work(kw);
         ctx->kw = nullptr;
     }
     kw = new KrylovWork();
     try {
         kw->m = m;
         kw->n = ctx->n;
-        kw->nb = (int)((ctx->n + DOT_BLOCK * DOT_PER_THREAD - 1) / (DOT_BLOCK * DOT_PER_THREAD));
+        kw->rpt = (int)std::max<int64_t>(1, (ctx->n + (int64_t)DOT_BLOCK * DOT_MAX_BLOCKS - 1) /
+                                               ((int64_t)DOT_BLOCK * DOT_MAX_BLOCKS));
+        kw->nb = (int)((ctx->n + (int64_t)DOT_BLOCK * kw->rpt - 1) / ((int64_t)DOT_BLOCK * kw->rpt));
         kw->V = kw->arena.alloc<double>((size_t)(m + 1) * ctx->n);
         kw->w = kw->arena.alloc<double>(ctx->n);
         kw->r = kw->arena.alloc<double>(ctx->n);
-        kw->part = kw->arena.alloc<double>((size_t)(m + 2) * kw->nb);
-        kw->h = kw->arena.alloc<double>(2 * (size_t)(m + 2));
+        kw->part1 = kw->arena.alloc<double>((size_t)(m + 1) * kw->nb);
+        kw->part2 = kw->arena.alloc<double>((size_t)(m + 1) * kw->nb);
+        kw->partn = kw->arena.alloc<double>(kw->nb);
         kw->y = kw->arena.alloc<double>(m + 1);
-        kw->ticket = kw->arena.alloc<unsigned int>(m + 2);
-        FB_HIP(hipMemset(kw->ticket, 0, sizeof(unsigned int) * (m + 2)));
+        FB_HIP(hipHostMalloc((void **)&kw->hcol, sizeof(double) * 2 * (m + 2), hipHostMallocMapped));
+        std::fill(kw->hcol, kw->hcol + 2 * (m + 2), 0.0);
+        FB_HIP(hipHostGetDevicePointer((void **)&kw->hcol_dev, kw->hcol, 0));
+        FB_HIP(hipEventCreateWithFlags(&kw->ev_h, hipEventDisableTiming));
     } catch (...) {
-        kw->arena.release();
-        delete kw;
+        release_work(kw);
         throw;
     }
     ctx->kw = kw;
     return kw;
 }
 
-// out[0..nv) = V_j . w  (device); with hprev, w -= sum_j hprev[j] V_j first
-void multidot(KrylovWork *kw, const double *V, int nv, const double *w, double *out, hipStream_t st,
-              const double *hprev = nullptr)
+// part[j][b] = V_j . w over row block b, j < nv; with hpart (the first
+// pass's partials), w' = w - sum_j h1[j] V_j in place of w
+void cgs_dots(KrylovWork *kw, const double *V, int nv, const double *w, double *part, hipStream_t st,
+              const double *hpart = nullptr)
 {
     dim3 grid(kw->nb, (nv + CGS_JG - 1) / CGS_JG);
-    k_cgs_dots<<<grid, DOT_BLOCK, 0, st>>>(kw->n, V, kw->n, nv, hprev, w, kw->part, kw->nb, out, kw->ticket);
+    const size_t shm = hpart ? sizeof(double) * nv : 0;
+    k_cgs_dots<<<grid, DOT_BLOCK, shm, st>>>(kw->n, kw->rpt, V, kw->n, nv, hpart, w, part, kw->nb);
+    FB_HIP(hipGetLastError());
+}
+
+// |r|^2 into the host column's entry 0 (read after the stream is synchronised)
+void norm2(KrylovWork *kw, const double *r, hipStream_t st)
+{
+    cgs_dots(kw, r, 1, r, kw->part1, st);
+    k_sum_parts<<<1, DOT_BLOCK, sizeof(double), st>>>(kw->part1, kw->nb, 1, kw->hcol_dev);
     FB_HIP(hipGetLastError());
 }
 
@@ -243,8 +345,7 @@ Sched choose(const fmmbem_schedule *s, double rho, double eta)
 void free_krylov(fmmbem_ctx *ctx)
 {
     if (ctx->kw) {
-        ctx->kw->arena.release();
-        delete ctx->kw;
+        release_work(ctx->kw);
         ctx->kw = nullptr;
     }
 }
@@ -260,17 +361,11 @@ GmresState::GmresState(fmmbem_ctx *c, const double *b_, double tol_, const fmmbe
     sn.assign(m, 0.0);
     g.assign(m + 1, 0.0);
     yv.assign(m, 0.0);
-    FB_HIP(hipHostMalloc((void **)&hbuf, sizeof(double) * 2 * (m + 2), hipHostMallocDefault));
-    FB_HIP(hipEventCreateWithFlags(&ev_h, hipEventDisableTiming));
+    hbuf = kw->hcol;
+    ev_h = kw->ev_h;
 }
 
-GmresState::~GmresState()
-{
-    if (ev_h)
-        (void)hipEventDestroy(ev_h);
-    if (hbuf)
-        (void)hipHostFree(hbuf);
-}
+GmresState::~GmresState() = default;
 
 void GmresState::record(int p, int prec, double r)
 {
@@ -285,8 +380,8 @@ void GmresState::begin_cycle()
 {
     // v0 = r / beta
     const int64_t n = ctx->n;
-    multidot(kw, kw->r, 1, kw->r, kw->h, st);
-    k_normalize<<<grid_for(n, 256), 256, 0, st>>>(n, kw->r, kw->h, kw->V);
+    cgs_dots(kw, kw->r, 1, kw->r, kw->part1, st);
+    k_normalize<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->rpt, kw->r, kw->part1, kw->nb, kw->V, nullptr);
     FB_HIP(hipGetLastError());
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -299,8 +394,7 @@ void GmresState::start()
     const int64_t n = ctx->n;
     FB_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
     FB_HIP(hipMemcpyAsync(kw->r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    multidot(kw, kw->r, 1, kw->r, kw->h, st);
-    FB_HIP(hipMemcpyAsync(hbuf, kw->h, sizeof(double), hipMemcpyDeviceToHost, st));
+    norm2(kw, kw->r, st);
     FB_HIP(hipStreamSynchronize(st));
     bnorm = std::sqrt(hbuf[0]);
     beta = bnorm;
@@ -326,15 +420,14 @@ void GmresState::enqueue_step()
     double *vk = kw->V + (int64_t)k * n, *vn = kw->V + (int64_t)(k + 1) * n;
     run_matvec(ctx, cur.p, cur.prec, vk, kw->w, st);
     ++matvecs;
-    multidot(kw, kw->V, k + 1, kw->w, kw->h, st);
-    multidot(kw, kw->V, k + 1, kw->w, kw->h + (m + 2), st, kw->h);
-    k_update_norm<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->V, n, k + 1, kw->h, kw->h + (m + 2), kw->w, kw->part,
-                                                kw->nb, kw->h + (k + 1), kw->ticket + (m + 1));
+    cgs_dots(kw, kw->V, k + 1, kw->w, kw->part1, st);
+    cgs_dots(kw, kw->V, k + 1, kw->w, kw->part2, st, kw->part1);
+    // h1[0..k], |w|^2 at k + 1 and h2[0..k] at m + 2 go straight to the host column
+    k_update_norm<<<kw->nb, DOT_BLOCK, 2 * sizeof(double) * (k + 1), st>>>(
+        n, kw->rpt, kw->V, n, k + 1, kw->part1, kw->part2, kw->nb, kw->w, kw->partn, kw->hcol_dev, m + 2);
     FB_HIP(hipGetLastError());
-    k_normalize<<<grid_for(n, 256), 256, 0, st>>>(n, kw->w, kw->h + (k + 1), vn);
+    k_normalize<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->rpt, kw->w, kw->partn, kw->nb, vn, kw->hcol_dev + (k + 1));
     FB_HIP(hipGetLastError());
-    // h1[0..k], |w|^2 at k + 1, and h2[0..k] at m + 2: one copy
-    FB_HIP(hipMemcpyAsync(hbuf, kw->h, sizeof(double) * (m + 2 + k + 1), hipMemcpyDeviceToHost, st));
     FB_HIP(hipEventRecord(ev_h, st));
     // While the host waits for the column, start the near field of the next
     // mat-vec (its input is v_{k+1}).  Its precision follows the schedule at
@@ -370,8 +463,7 @@ void GmresState::end_cycle()
     ++matvecs;
     k_sub<<<grid_for(n, 256), 256, 0, st>>>(n, b, kw->w, kw->r);
     FB_HIP(hipGetLastError());
-    multidot(kw, kw->r, 1, kw->r, kw->h, st);
-    FB_HIP(hipMemcpyAsync(hbuf, kw->h, sizeof(double), hipMemcpyDeviceToHost, st));
+    norm2(kw, kw->r, st);
     FB_HIP(hipStreamSynchronize(st));
     beta = std::sqrt(hbuf[0]);
     true_rel = beta / bnorm;

@@ -1,9 +1,11 @@
 // The regular near field stored as a block-sparse matrix (Sec. 2.3, 2.5): the
 // 4-point rule between every target panel and the panels of the leaves in its
 // P2P list, assembled once and multiplied by every mat-vec, as the paper holds
-// its near field.  The near-singular and self corrections stay as they are:
-// the stored block leaves each target's own panel at zero, exactly as the
-// on-the-fly P2P skips it.
+// its near field.  The near-singular and self corrections (25-point rule minus
+// 4-point rule, and the analytic self integral on a block that leaves the
+// target's own panel at zero) are then added into the entries of their pairs,
+// so that a stored entry is the accurate integral and the mat-vec no longer
+// visits them; the few pairs without a stored block keep a separate list.
 #include <algorithm>
 #include <vector>
 
@@ -63,18 +65,23 @@ __global__ void k_near_build(const int4 *__restrict__ units, const int32_t *__re
     }
 }
 
-// xs = x in sorted panel order
-template <int NQ>
-__global__ void k_sort_input(int64_t nt, const int32_t *__restrict__ perm, const double *__restrict__ x,
-                             double *__restrict__ xs)
+// v64[dst[f] + ab step[f]] += val[PER src[f] + ab] for every folded
+// correction f and component ab; each destination is one pair's entry, so no
+// two threads meet.  The FP32 copy is rounded again from the sum.
+template <int PER>
+__global__ void k_fold_corrections(int64_t nfold, const int64_t *__restrict__ dst, const int32_t *__restrict__ step,
+                                   const int64_t *__restrict__ srcidx, const double *__restrict__ val,
+                                   double *__restrict__ v64, float *__restrict__ v32)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nt)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nfold * PER)
         return;
-    const int64_t o = perm[i];
-#pragma unroll
-    for (int a = 0; a < NQ; ++a)
-        xs[NQ * i + a] = x[NQ * o + a];
+    const int64_t f = t / PER;
+    const int ab = (int)(t % PER);
+    const int64_t d = dst[f] + (int64_t)ab * step[f];
+    const double v = v64[d] + val[PER * srcidx[f] + ab];
+    v64[d] = v;
+    v32[d] = (float)v;
 }
 
 // y_near = stored near field times x: one HIP block per P2P unit, lane =
@@ -136,6 +143,118 @@ __global__ __launch_bounds__(64 * NEAR_WAVES) void k_near_spmv(int nunit, int pe
                 s += red[k][a][lane];
             ynear[(int64_t)NQ * (tb + lane) + a] = s;
         }
+    }
+}
+
+// Adds every correction whose pair (target i, source panel j) lies in a
+// stored block into that entry and collects the others, in target order, into
+// the rest list that the combine step still applies.
+void fold_corrections(fmmbem_ctx *ctx, const std::vector<int4> &units, const std::vector<int32_t> &bptr,
+                      const std::vector<NearBlock> &blks, hipStream_t st)
+{
+    Tree &T = ctx->tree;
+    NearMatrix &N = ctx->nearm;
+    const Correction &C = ctx->corr;
+    const int per = ctx->kernel == FMMBEM_STOKES_SL ? 9 : 1;
+    const int64_t nt = T.nt;
+    std::vector<int32_t> cptr(nt + 1), ccol(std::max<int64_t>(C.nnz, 1)), corig(std::max<int64_t>(C.nnz, 1));
+    std::vector<double> cval(std::max<int64_t>(C.nnz, 1) * per);
+    FB_HIP(hipMemcpyAsync(cptr.data(), C.ptr, sizeof(int32_t) * (nt + 1), hipMemcpyDeviceToHost, st));
+    if (C.nnz > 0) {
+        FB_HIP(hipMemcpyAsync(ccol.data(), C.col, sizeof(int32_t) * C.nnz, hipMemcpyDeviceToHost, st));
+        FB_HIP(hipMemcpyAsync(corig.data(), C.col_orig, sizeof(int32_t) * C.nnz, hipMemcpyDeviceToHost, st));
+        FB_HIP(hipMemcpyAsync(cval.data(), C.val, sizeof(double) * C.nnz * per, hipMemcpyDeviceToHost, st));
+    }
+    FB_HIP(hipStreamSynchronize(st));
+    // unit of every sorted target; per unit, its blocks ordered by first panel
+    std::vector<int32_t> unit_of(nt, -1);
+    for (int g = 0; g < (int)units.size() && g < T.n_unit; ++g)
+        for (int i = units[g].x; i < units[g].y; ++i)
+            unit_of[i] = g;
+    std::vector<int32_t> order(blks.size());
+    for (int g = 0; g + 1 < (int)bptr.size(); ++g) {
+        for (int b = bptr[g]; b < bptr[g + 1]; ++b)
+            order[b] = b;
+        std::sort(order.begin() + bptr[g], order.begin() + bptr[g + 1],
+                  [&](int a, int b) { return blks[a].j0 < blks[b].j0; });
+    }
+    std::vector<int64_t> dst, srcidx;
+    std::vector<int32_t> step;
+    std::vector<int32_t> rptr(nt + 1, 0), rcol, rorig;
+    std::vector<double> rval;
+    for (int64_t i = 0; i < nt; ++i) {
+        const int g = unit_of[i];
+        for (int e = cptr[i]; e < cptr[i + 1]; ++e) {
+            const int j = ccol[e];
+            int hit = -1;
+            if (g >= 0) {
+                // last block (by first panel) starting at or before j
+                int lo = bptr[g], hi = bptr[g + 1];
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) / 2;
+                    if (blks[order[mid]].j0 <= j)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                if (lo < bptr[g + 1]) {
+                    const NearBlock &B = blks[order[lo]];
+                    if (B.j0 <= j && j < B.j0 + B.ns)
+                        hit = order[lo];
+                }
+            }
+            if (hit >= 0) {
+                const NearBlock &B = blks[hit];
+                const int n = units[g].y - units[g].x;
+                dst.push_back(B.off + (int64_t)(j - B.j0) * per * n + (i - units[g].x));
+                step.push_back(n);
+                srcidx.push_back(e);
+            } else {
+                rcol.push_back(j);
+                rorig.push_back(corig[e]);
+                for (int a = 0; a < per; ++a)
+                    rval.push_back(cval[(int64_t)per * e + a]);
+            }
+        }
+        rptr[i + 1] = (int32_t)rcol.size();
+    }
+    N.folded = (int64_t)dst.size();
+    DevArena &A = ctx->arena;
+    Correction &Rr = N.rest;
+    Rr.nnz = (int64_t)rcol.size();
+    Rr.ptr = A.alloc<int32_t>(nt + 1);
+    Rr.col = A.alloc<int32_t>(std::max<size_t>(rcol.size(), 1));
+    Rr.col_orig = A.alloc<int32_t>(std::max<size_t>(rorig.size(), 1));
+    Rr.val = A.alloc<double>(std::max<size_t>(rval.size(), 1));
+    FB_HIP(hipMemcpyAsync(Rr.ptr, rptr.data(), sizeof(int32_t) * (nt + 1), hipMemcpyHostToDevice, st));
+    if (!rcol.empty()) {
+        FB_HIP(hipMemcpyAsync(Rr.col, rcol.data(), sizeof(int32_t) * rcol.size(), hipMemcpyHostToDevice, st));
+        FB_HIP(hipMemcpyAsync(Rr.col_orig, rorig.data(), sizeof(int32_t) * rorig.size(), hipMemcpyHostToDevice, st));
+        FB_HIP(hipMemcpyAsync(Rr.val, rval.data(), sizeof(double) * rval.size(), hipMemcpyHostToDevice, st));
+    }
+    if (!dst.empty()) {
+        DevArena tmp;
+        try {
+            int64_t *d_dst = tmp.alloc<int64_t>(dst.size());
+            int32_t *d_step = tmp.alloc<int32_t>(step.size());
+            int64_t *d_src = tmp.alloc<int64_t>(srcidx.size());
+            FB_HIP(hipMemcpyAsync(d_dst, dst.data(), sizeof(int64_t) * dst.size(), hipMemcpyHostToDevice, st));
+            FB_HIP(hipMemcpyAsync(d_step, step.data(), sizeof(int32_t) * step.size(), hipMemcpyHostToDevice, st));
+            FB_HIP(hipMemcpyAsync(d_src, srcidx.data(), sizeof(int64_t) * srcidx.size(), hipMemcpyHostToDevice, st));
+            const int64_t work = (int64_t)dst.size() * per;
+            if (per == 9)
+                k_fold_corrections<9><<<grid_for(work, 256), 256, 0, st>>>((int64_t)dst.size(), d_dst, d_step, d_src,
+                                                                          C.val, N.v64, N.v32);
+            else
+                k_fold_corrections<1><<<grid_for(work, 256), 256, 0, st>>>((int64_t)dst.size(), d_dst, d_step, d_src,
+                                                                          C.val, N.v64, N.v32);
+            FB_HIP(hipGetLastError());
+            FB_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+            tmp.release();
+            throw;
+        }
+        tmp.release();
     }
 }
 
@@ -204,17 +323,8 @@ void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st)
 #undef FB_NEAR_BUILD
         FB_HIP(hipGetLastError());
     }
+    fold_corrections(ctx, units, bptr, blks, st);
     FB_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
-}
-
-void sort_near_input(fmmbem_ctx *ctx, const double *x, hipStream_t st)
-{
-    Tree &T = ctx->tree;
-    if (ctx->kernel == FMMBEM_STOKES_SL)
-        k_sort_input<3><<<grid_for(T.nt, 256), 256, 0, st>>>(T.nt, T.perm, x, ctx->nearm.xs);
-    else
-        k_sort_input<1><<<grid_for(T.nt, 256), 256, 0, st>>>(T.nt, T.perm, x, ctx->nearm.xs);
-    FB_HIP(hipGetLastError());
 }
 
 void launch_near_stored(fmmbem_ctx *ctx, int prec, hipStream_t st)

@@ -1,4 +1,4 @@
-"""Red-blood-cell studies of Sec. 3.3 through the same GPU path (f4).
+"""Red-blood-cell studies of Sec. 3.3 through the same GPU path.
 
   python -m paper_1506_05957_amd.studies [--out FILE]
 

@@ -134,3 +134,4 @@ def test_stored_near_field_matches_on_the_fly(orc, kernel, name):
         assert e <= bar
     fb.fmmbem_destroy(a)
     fb.fmmbem_destroy(b)
+

@@ -1,4 +1,4 @@
-"""Laplace double layer, second kind (f3): the GPU operator 1/2 I - K against
+"""Laplace double layer, second kind: the GPU operator 1/2 I - K against
 the oracle's dense operator, the error of the expansions against p, and the
 exterior Neumann solve against the oracle and the closed form on the sphere."""
 import numpy as np
