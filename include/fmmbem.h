@@ -99,7 +99,14 @@ typedef struct {
      * (Laplace), 108 B (Stokes); see fmmbem_stats.near_entries.
      * 0 (default): evaluated on the fly by every mat-vec. */
     int32_t near_stored;
-    int32_t reserved;  /* must be 0 */
+    /* 1: the FP64 M2L operator of every distinct translation (Sec. 2.5), the
+     * real (2 ncoef(p_max))^2 matrix that pass 1 applies, is generated once at
+     * build and stored; FP64 mat-vecs stream it through the matrix cores
+     * instead of generating it from the translation's harmonics on every
+     * call.  Memory: about 8 (2 ncoef(p_max))^2 bytes per translation (a
+     * sphere of 32768 panels at p_max = 12: 4601 translations, 1.3 GB); see
+     * fmmbem_stats.m2l_op_bytes.  0 (default): generated on the fly. */
+    int32_t m2l_stored;
 } fmmbem_params;
 
 typedef struct {
@@ -133,6 +140,8 @@ typedef struct {
     int64_t nnz_correction;      /* near-singular + self entries (blocks for Stokes) */
     int64_t device_bytes;        /* device memory held by the context */
     int64_t near_entries;        /* panel pairs of the stored near field (0 unless near_stored) */
+    int64_t n_translations;      /* distinct M2L translations (offset and box sizes) */
+    int64_t m2l_op_bytes;        /* stored FP64 M2L operators (0 unless m2l_stored) */
 } fmmbem_stats;
 
 /* Defaults described above. */

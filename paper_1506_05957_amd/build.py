@@ -24,7 +24,9 @@ SOURCES = [
     ("tree.hip", ["-ffp-contract=off"]),
     ("near.hip", ["-ffp-contract=off"]),
     ("translations.hip", []),
-    ("fmm.hip", []),
+    # MFMA accumulators in VGPRs: without it the compiler copies them
+    # through AGPRs around every product of the M2L loops
+    ("fmm.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
     ("nearfield.hip", []),
     ("krylov.hip", []),
     ("api.hip", []),

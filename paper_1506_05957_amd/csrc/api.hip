@@ -101,7 +101,7 @@ void fmmbem_params_default(fmmbem_params *prm)
     prm->p_max = 16;
     prm->mu = 1.0;
     prm->near_stored = 0;
-    prm->reserved = 0;
+    prm->m2l_stored = 0;
 }
 
 void fmmbem_schedule_default(fmmbem_schedule *s, int kernel)
@@ -140,7 +140,7 @@ static void validate_params(const fmmbem_params *p)
     FB_REQUIRE(p->p_max >= 1 && p->p_max <= FMMBEM_P_MAX, FMMBEM_EINVAL, "p_max must be in [1, 20]");
     FB_REQUIRE(p->mu > 0.0 && std::isfinite(p->mu), FMMBEM_EINVAL, "mu must be positive");
     FB_REQUIRE(p->near_stored == 0 || p->near_stored == 1, FMMBEM_EINVAL, "near_stored must be 0 or 1");
-    FB_REQUIRE(p->reserved == 0, FMMBEM_EINVAL, "reserved must be 0");
+    FB_REQUIRE(p->m2l_stored == 0 || p->m2l_stored == 1, FMMBEM_EINVAL, "m2l_stored must be 0 or 1");
 }
 
 int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *params, void *hip_stream,
@@ -175,6 +175,8 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         build_translations(ctx, st);
         if (prm.near_stored)
             build_near_matrix(ctx, st);
+        if (prm.m2l_stored)
+            build_m2l_operators(ctx, st);
         const int ncs = ncoef(prm.p_max);
         ctx->charges = ctx->arena.alloc<double>((size_t)(kernel == FMMBEM_LAPLACE_SL ? 4 : 8) * ctx->nsrc);
         ctx->Y = ctx->arena.alloc<double>(2 * (size_t)std::max<int64_t>(ctx->tree.n_m2l, 1) * ctx->nch * ncs);
@@ -287,6 +289,8 @@ int fmmbem_get_stats(const fmmbem_ctx_t *ctx, fmmbem_stats *o)
     o->nnz_correction = ctx->corr.nnz;
     o->device_bytes = ctx->arena.bytes + (ctx->kw ? ctx->kw->arena.bytes : 0);
     o->near_entries = ctx->nearm.entries;
+    o->n_translations = ctx->m2l.n_trans;
+    o->m2l_op_bytes = ctx->m2l.ops_bytes;
     return FMMBEM_OK;
     API_END
 }

@@ -164,6 +164,12 @@ struct M2LPlan {
     // the first and L2L out of levels above the second carry nothing
     int lmin_src = 0, lmin_tgt = 0;
     void *Z = nullptr;                  // [nbox][nch][ncoef(p_max)] complex FP64: per-child M2M terms
+    // stored FP64 pass-1 operators (m2l_stored): per translation, row tiles
+    // rt < ops_nrt of 16 rows, column steps kt < ops_k4 of 4 inputs, 64
+    // values per (rt, kt) in the matrix-core lane order
+    double *ops64 = nullptr;
+    int ops_nrt = 0, ops_k4 = 0;
+    int64_t ops_bytes = 0;
 };
 
 // The regular near field stored as a block-sparse matrix (nearfield.hip): per
@@ -304,6 +310,8 @@ void prefetch_near(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
 // stored near field (nearfield.hip): assemble at build; one product on
 // stream st of the input in sorted order (nearm.xs, written by the charges)
 void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st);
+// stored FP64 M2L operators (fmm.hip), after build_translations
+void build_m2l_operators(fmmbem_ctx *ctx, hipStream_t st);
 void launch_near_stored(fmmbem_ctx *ctx, int prec, hipStream_t st);
 int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
               fmmbem_report *rep, hipStream_t st);

@@ -176,6 +176,22 @@ __global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const do
 }
 
 // ---------------------------------------------------------------------------
+// Sources of a leaf are staged through LDS in tiles of P2M_TILE: one coalesced
+// copy per tile, so that the per-source loop reads them from LDS instead of
+// waiting on a global load each time.
+constexpr int P2M_TILE = 256;
+
+template <typename S>
+__device__ inline void stage_sources(const S *__restrict__ src, int64_t first, int count, S *__restrict__ tile)
+{
+    static_assert(sizeof(S) % 16 == 0, "sources are whole 16-byte words");
+    constexpr int W = sizeof(S) / 16;
+    const int4 *g = reinterpret_cast<const int4 *>(src + first);
+    int4 *t = reinterpret_cast<int4 *>(tile);
+    for (int k = threadIdx.x; k < count * W; k += blockDim.x)
+        t[k] = g[k];
+}
+
 // P2M: one block per leaf.  Thread = (order m, source slice): it accumulates
 // q conj(R_n^m((y - c) / s)) over the sources of its slice for n = m..p, and
 // the slices are summed in a fixed order.  PM is a compile-time bound on p so
@@ -197,8 +213,10 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
                                              cplx<R> *__restrict__ M)
 {
     constexpr int CG = NCH == 1 ? 1 : (sizeof(R) == 4 ? 4 : 2);
+    using S = Src<R, NCH == 4>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *red = reinterpret_cast<cplx<R> *>(smem_raw);  // [nsl][nc]
+    S *tile = reinterpret_cast<S *>(smem_raw);                                   // [P2M_TILE]
+    cplx<R> *red = reinterpret_cast<cplx<R> *>(smem_raw + sizeof(S) * P2M_TILE);  // [nsl][nc]
     const int b = leaves[blockIdx.x];
     const int lv = box_i[6 * b], pb = box_i[6 * b + 1], pe = box_i[6 * b + 2];
     const double s = ldexp(side, -(lv + 1));
@@ -223,9 +241,15 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
 #pragma unroll
             for (int n = 0; n <= PM; ++n)
                 are[g][n] = aim[g][n] = 0;
-        if (active) {
-            for (int64_t si = 4 * (int64_t)pb + sl; si < 4 * (int64_t)pe; si += nsl) {
-                const Src<R, NCH == 4> sv = src[si];
+        for (int64_t t0 = 4 * (int64_t)pb; t0 < 4 * (int64_t)pe; t0 += P2M_TILE) {
+            const int cnt = (int)std::min<int64_t>(P2M_TILE, 4 * (int64_t)pe - t0);
+            __syncthreads();  // the previous tile has been read
+            stage_sources(src, t0, cnt, tile);
+            __syncthreads();
+            if (!active)
+                continue;
+            for (int si = sl; si < cnt; si += nsl) {
+                const S sv = tile[si];
                 R x, y, z;  // relative to the leaf centre
                 if constexpr (sizeof(R) == 8) {
                     x = sv.x - c[0];
@@ -306,8 +330,10 @@ __global__ __launch_bounds__(256) void k_p2m_dipole(int p, int ncs, const int32_
                                                     double side, const Src<R, true> *__restrict__ src,
                                                     cplx<R> *__restrict__ M)
 {
+    using S = Src<R, true>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cplx<R> *red = reinterpret_cast<cplx<R> *>(smem_raw);  // [nsl][nc]
+    S *tile = reinterpret_cast<S *>(smem_raw);                                   // [P2M_TILE]
+    cplx<R> *red = reinterpret_cast<cplx<R> *>(smem_raw + sizeof(S) * P2M_TILE);  // [nsl][nc]
     const int b = leaves[blockIdx.x];
     const int lv = box_i[6 * b], pb = box_i[6 * b + 1], pe = box_i[6 * b + 2];
     const double s = ldexp(side, -(lv + 1));
@@ -323,9 +349,15 @@ __global__ __launch_bounds__(256) void k_p2m_dipole(int p, int ncs, const int32_
 #pragma unroll
     for (int n = 0; n <= PM; ++n)
         are[n] = aim[n] = 0;
-    if (active) {
-        for (int64_t si = 4 * (int64_t)pb + sl; si < 4 * (int64_t)pe; si += nsl) {
-            const Src<R, true> sv = src[si];
+    for (int64_t t0 = 4 * (int64_t)pb; t0 < 4 * (int64_t)pe; t0 += P2M_TILE) {
+        const int cnt = (int)std::min<int64_t>(P2M_TILE, 4 * (int64_t)pe - t0);
+        __syncthreads();  // the previous tile has been read
+        stage_sources(src, t0, cnt, tile);
+        __syncthreads();
+        if (!active)
+            continue;
+        for (int si = sl; si < cnt; si += nsl) {
+            const S sv = tile[si];
             R x, y, z;  // relative to the leaf centre, then scaled
             if constexpr (sizeof(R) == 8) {
                 x = sv.x - c[0];
@@ -415,6 +447,8 @@ __global__ __launch_bounds__(256) void k_p2m_dipole(int p, int ncs, const int32_
                 }
             }
         }
+    }
+    if (active) {
 #pragma unroll
         for (int n = 0; n <= PM; ++n)
             if (n <= p && n >= m)
@@ -702,6 +736,194 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(int p, int ncs, int q_tab, con
 }
 
 // LDS of k_m2l_mfma: the key's table and the (n, m) index
+// Stored pass-1 operators (FP64).  k_m2l_opgen writes, for translation u at
+// p_max, the element of A that lane (i + 16 k) of the matrix-core step (rt, kt)
+// takes, A[16 rt + i][4 kt + k], exactly as k_m2l_mfma generates it, to
+// ops[((u nrt + rt) k4 + kt) 64 + lane]; entries beyond 2 ncoef(p_max) are 0.
+// Grid (translation, row tile); the waves take the column steps in turn.
+__global__ __launch_bounds__(256) void k_m2l_opgen(int pmax, int q_tab, int nrt, int k4,
+                                                   const uint64_t *__restrict__ trans_key,
+                                                   const cplx<double> *__restrict__ table, double *__restrict__ ops)
+{
+    const int u = blockIdx.x, rt = blockIdx.y;
+    const uint64_t key = trans_key[u];
+    const int eT = (int)((key >> 48) & 63), eS = (int)((key >> 54) & 63);
+    const cplx<double> *It = table + (int64_t)u * (q_tab + 1) * (q_tab + 1);
+    const int Dp = 2 * ncoef(pmax);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int pin = lk & 1;
+    const int r = rt * 16 + li;
+    const bool rv = r < Dp;
+    int k = 0, l = 0;
+    if (rv)
+        idx_to_nm(r >> 1, k, l);
+    const int po = r & 1;
+    const double sall = (po == 0 && pin == 1) ? -1.0 : 1.0;
+    const bool take_im = (po ^ pin) != 0;
+    const double f = rv ? sall * ldexp((k & 1) ? -1.0 : 1.0, -eT * (k + 1)) : 0.0;
+    double *dst = ops + ((int64_t)u * nrt + rt) * k4 * 64 + lane;
+    for (int kt = w; kt < k4; kt += blockDim.x >> 6) {
+        const int qi = 4 * kt + lk;
+        double a = 0.0;
+        if (rv && qi < Dp) {
+            int n, m;
+            idx_to_nm(qi >> 1, n, m);
+            const cplx<double> *row = It + (n + k) * (n + k + 1);  // I_{n+k}^{0}
+            const cplx<double> P = row[l + m];
+            double pc = take_im ? P.im : P.re;
+            if (m > 0) {
+                const cplx<double> Q = row[l - m];
+                const double qc = take_im ? Q.im : Q.re;
+                pc += (((m & 1) != 0) != (pin != 0)) ? -qc : qc;
+            }
+            a = ldexp(f * pc, -eS * n);
+        }
+        dst[(int64_t)kt * 64] = a;
+    }
+}
+
+// Pass 1 in FP64 from the stored operators: the A element of every
+// matrix-core step is loaded (one coalesced 512-byte read per wave and step)
+// instead of generated.  The chunk's input columns are staged in LDS, NT
+// column tiles per pass (stride 16 NT + 1 against bank conflicts; columns
+// past the chunk are zero, so every product runs unconditionally and the
+// accumulators stay in place), and each wave runs RB row tiles at once so
+// that their products overlap.  Order
+// p < p_max uses the leading rows and inputs of the stored operator; the rest
+// of a boundary tile meets zero inputs and unstored outputs.
+constexpr int M2LS_RB = 3;
+template <int NCH, int NT>
+__global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, int k4_s,
+                                                    const int32_t *__restrict__ chunk_begin,
+                                                    const int32_t *__restrict__ chunk_trans,
+                                                    const int32_t *__restrict__ pair_sorted,
+                                                    const int32_t *__restrict__ pairs, const double *__restrict__ ops,
+                                                    const cplx<double> *__restrict__ M, cplx<double> *__restrict__ Y)
+{
+    typedef Acc4<double>::type acc_t;
+    constexpr int RB = M2LS_RB, ldb = 16 * NT + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *Bs = reinterpret_cast<double *>(smem_raw);  // [Kp][ldb]
+    int *colbase = reinterpret_cast<int *>(Bs + ldb * (size_t)((2 * ncoef(p) + 3) & ~3));  // [16 NT]
+    const int nc = ncoef(p), Dp = 2 * nc, Kp = (Dp + 3) & ~3, nrt = (Dp + 15) / 16;
+    const int c = blockIdx.x;
+    const int u = chunk_trans[c], pb = chunk_begin[c], pe = chunk_begin[c + 1];
+    const int ncol = (pe - pb) * NCH, nct = (ncol + 15) / 16;
+    constexpr int nwave = 4;  // launched with 256 threads
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const double *Au = ops + (int64_t)u * nrt_s * k4_s * 64 + lane;
+    for (int g0 = 0; g0 < nct; g0 += NT) {
+        const int gt = min(NT, nct - g0);
+        const int c0 = 16 * g0, cn = min(16 * gt, ncol - c0);
+        __syncthreads();  // the previous pass has read Bs
+        if ((int)threadIdx.x < 16 * NT) {
+            const int j = threadIdx.x;
+            int cb = -1;
+            if (j < cn) {
+                const int col = c0 + j, pl = col / NCH, ch = col - pl * NCH;
+                cb = (pairs[2 * pair_sorted[pb + pl] + 1] * NCH + ch) * ncs;  // in complex units
+            }
+            colbase[j] = cb;
+        }
+        __syncthreads();
+        // wave w stages columns w CPW .. + CPW - 1 (Dp contiguous reals each),
+        // all of its loads issued before the LDS writes; reads past the chunk
+        // or past Dp go to a valid address and are replaced by zero
+        {
+            constexpr int CPW = 16 * NT / 4;
+            int cbs[CPW];
+#pragma unroll
+            for (int c2 = 0; c2 < CPW; ++c2)
+                cbs[c2] = colbase[w * CPW + c2];
+            for (int k = lane; k < Kp; k += 64) {
+                const int kc = min(k, Dp - 1);
+                double v[CPW];
+#pragma unroll
+                for (int c2 = 0; c2 < CPW; ++c2)
+                    v[c2] = reinterpret_cast<const double *>(M + max(cbs[c2], 0))[kc];
+#pragma unroll
+                for (int c2 = 0; c2 < CPW; ++c2)
+                    Bs[k * ldb + w * CPW + c2] = (cbs[c2] >= 0 && k < Dp) ? v[c2] : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int rb = w; rb < nrt; rb += nwave * RB) {
+            acc_t acc[RB][NT];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+                    acc[i][ct] = acc_t{0, 0, 0, 0};
+            // row tiles past nrt repeat the last one and are not stored; rows
+            // and inputs past Dp meet zero inputs or are not stored, so the
+            // loads need no guard (a guarded load would wait on each read).
+            // The operator values of the next PF steps are kept in flight.
+            constexpr int PF = 8;
+            const int nsteps = Kp >> 2;
+            const double *At[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                At[i] = Au + (int64_t)min(rb + i * nwave, nrt - 1) * k4_s * 64;
+            double ring[PF][RB];
+#pragma unroll
+            for (int j = 0; j < PF; ++j)
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    ring[j][i] = At[i][(int64_t)min(j, nsteps - 1) * 64];
+            for (int s0 = 0; s0 < nsteps; s0 += PF) {
+#pragma unroll
+                for (int j = 0; j < PF; ++j) {
+                    const int st = s0 + j;
+                    if (st < nsteps) {
+                        const double *brow = Bs + (4 * st + lk) * ldb + li;
+                        double bv[NT];
+#pragma unroll
+                        for (int ct = 0; ct < NT; ++ct)
+                            bv[ct] = brow[16 * ct];
+#pragma unroll
+                        for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+                            for (int i = 0; i < RB; ++i)
+                                acc[i][ct] = mfma_16x16x4(ring[j][i], bv[ct], acc[i][ct]);
+                        const int sn = min(st + PF, nsteps - 1);
+#pragma unroll
+                        for (int i = 0; i < RB; ++i)
+                            ring[j][i] = At[i][(int64_t)sn * 64];
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int rt = rb + i * nwave;
+                if (rt >= nrt)
+                    continue;
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct) {
+                    const int col = c0 + ct * 16 + li;
+                    if (ct >= gt || col >= ncol)
+                        continue;
+                    const int pl = col / NCH, ch = col - pl * NCH;
+                    double *dst = reinterpret_cast<double *>(Y + ((int64_t)pair_sorted[pb + pl] * NCH + ch) * nc);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = rt * 16 + 4 * v + lk;  // FP64 output layout
+                        if (row < Dp)
+                            dst[row] = acc[i][ct][v];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// LDS of k_m2l_stored with NT column tiles per pass
+inline size_t m2l_stored_shm(int p, int nt)
+{
+    const size_t Kp = (2 * ncoef(p) + 3) & ~3;
+    return sizeof(double) * Kp * (16 * nt + 1) + sizeof(int) * 16 * nt;
+}
+
 template <typename R> size_t m2l_mfma_shm(int p)
 {
     const int q = 2 * p;
@@ -1267,7 +1489,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
         stage_begin(ctx, SO + 2, st, &ev);
         {
             const int nsl = 256 / (p + 1);
-            const size_t shm = sizeof(cplx<R>) * (size_t)nsl * ncoef(p);
+            const size_t shm = sizeof(cplx<R>) * (size_t)nsl * ncoef(p) + sizeof(Src<R, VS>) * P2M_TILE;
             if constexpr (KIND == FMMBEM_LAPLACE_DL) {
                 if (p <= 4)
                     k_p2m_dipole<R, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
@@ -1332,6 +1554,16 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
             if constexpr (sizeof(R) == 4) {
                 k_m2l_mfma<R, NCH><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), st>>>(
                     p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
+            } else if (P.ops64) {
+                // two column tiles per pass while they fit in 64 KB of LDS (p <= 13)
+                if (m2l_stored_shm(p, 2) <= 65536)
+                    k_m2l_stored<NCH, 2><<<P.n_chunks, 256, m2l_stored_shm(p, 2), st>>>(
+                        p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin, P.chunk_trans, P.pair_sorted, T.m2l_pairs,
+                        P.ops64, M, Y);
+                else
+                    k_m2l_stored<NCH, 1><<<P.n_chunks, 256, m2l_stored_shm(p, 1), st>>>(
+                        p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin, P.chunk_trans, P.pair_sorted, T.m2l_pairs,
+                        P.ops64, M, Y);
             } else {
                 constexpr int PB = NCH == 1 ? 8 : 2;
                 const size_t shm = sizeof(cplx<R>) * (size_t)(2 * p + 1) * (2 * p + 1);
@@ -1441,6 +1673,22 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
     const CombineArgs ca{ctx->tree.perm, C.ptr, C.col_orig, C.val, x, ctx->y_near, pref, y};
     far_dispatch(ctx, p, prec, ca, st);  // ends with the join and the combine
     ctx->near_pending = false;
+}
+
+void build_m2l_operators(fmmbem_ctx *ctx, hipStream_t st)
+{
+    M2LPlan &P = ctx->m2l;
+    if (P.n_trans == 0)
+        return;
+    const int Dp = 2 * ncoef(ctx->prm.p_max);
+    P.ops_nrt = (Dp + 15) / 16;
+    P.ops_k4 = (Dp + 3) / 4;
+    const int64_t per = (int64_t)P.ops_nrt * P.ops_k4 * 64;
+    P.ops64 = ctx->arena.alloc<double>((size_t)per * P.n_trans);
+    P.ops_bytes = (int64_t)sizeof(double) * per * P.n_trans;
+    k_m2l_opgen<<<dim3(P.n_trans, P.ops_nrt), 256, 0, st>>>(ctx->prm.p_max, P.q, P.ops_nrt, P.ops_k4, P.trans_key,
+                                                           P.table64, P.ops64);
+    FB_HIP(hipGetLastError());
 }
 
 }  // namespace fmmbem

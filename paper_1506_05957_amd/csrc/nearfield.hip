@@ -17,6 +17,17 @@ namespace {
 
 constexpr int NEAR_WAVES = 8;
 
+// Layout of one stored block (n targets, ns sources padded to ns4 groups of
+// four): value (target i, source j, component ab) sits at
+//   off + ((j / 4) PER + ab) n 4 + 4 i + j % 4,
+// so that the four sources of a group are adjacent for every target and a
+// lane reads them with one 16-byte (FP32) or 32-byte (FP64) load; padding
+// sources hold zeros.
+__host__ __device__ inline int64_t near_index(int64_t off, int n, int per, int j, int ab, int i)
+{
+    return off + (((int64_t)(j >> 2) * per + ab) * n + i) * 4 + (j & 3);
+}
+
 // Entries of one stored block per HIP block, in FP64: entry (j, i) is
 // sum_k w_jk G(t_i - y_jk) over the 4 Gauss points of source panel j, Laplace
 // G = 1/r, Stokes G_ab = delta_ab / r + d_a d_b / r^3 (d = t - y), double layer
@@ -35,14 +46,16 @@ __global__ void k_near_build(const int4 *__restrict__ units, const int32_t *__re
     const int4 u = units[blk_unit[b]];
     const int tb = u.x, n = u.y - u.x;
     const int64_t ns = 4 * nt;
-    const int64_t cnt = (int64_t)n * B.ns * PER;
+    const int ns4 = (B.ns + 3) / 4;
+    const int64_t cnt = (int64_t)n * ns4 * 4 * PER;  // in storage order
     for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
-        const int i = (int)(e % n);
-        const int64_t r = e / n;
-        const int ab = (int)(r % PER), j = (int)(r / PER);
+        const int jl = (int)(e & 3);
+        const int i = (int)((e >> 2) % n);
+        const int64_t r = (e >> 2) / n;
+        const int ab = (int)(r % PER), j = 4 * (int)(r / PER) + jl;
         const int ti = tb + i, sj = B.j0 + j;
         double v = 0.0;
-        if (ti != sj) {
+        if (j < B.ns && ti != sj) {
             const double t[3] = {tc[ti], tc[nt + ti], tc[2 * nt + ti]};
             for (int k = 0; k < 4; ++k) {
                 const int64_t s = 4 * (int64_t)sj + k;
@@ -65,7 +78,7 @@ __global__ void k_near_build(const int4 *__restrict__ units, const int32_t *__re
     }
 }
 
-// v64[dst[f] + ab step[f]] += val[PER src[f] + ab] for every folded
+// v64[dst[f] + 4 ab step[f]] += val[PER src[f] + ab] for every folded
 // correction f and component ab; each destination is one pair's entry, so no
 // two threads meet.  The FP32 copy is rounded again from the sum.
 template <int PER>
@@ -78,7 +91,7 @@ __global__ void k_fold_corrections(int64_t nfold, const int64_t *__restrict__ ds
         return;
     const int64_t f = t / PER;
     const int ab = (int)(t % PER);
-    const int64_t d = dst[f] + (int64_t)ab * step[f];
+    const int64_t d = dst[f] + (int64_t)ab * 4 * step[f];
     const double v = v64[d] + val[PER * srcidx[f] + ab];
     v64[d] = v;
     v32[d] = (float)v;
@@ -89,6 +102,10 @@ __global__ void k_fold_corrections(int64_t nfold, const int64_t *__restrict__ ds
 // wave-uniform and come through the scalar cache; matrix reads are coalesced
 // over the targets, unrolled so that many are in flight.  Partial sums of the
 // waves are added in wave order, in FP64.
+template <typename R> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
 template <typename R, bool STOKES>
 __global__ __launch_bounds__(64 * NEAR_WAVES) void k_near_spmv(int nunit, int per_xcd, const int4 *__restrict__ units,
                                                                const int32_t *__restrict__ blk_ptr,
@@ -110,23 +127,36 @@ __global__ __launch_bounds__(64 * NEAR_WAVES) void k_near_spmv(int nunit, int pe
 #pragma unroll
     for (int a = 0; a < NQ; ++a)
         acc[a] = 0;
+    using V4 = typename Vec4<R>::type;
     if (active) {
         for (int b = blk_ptr[g] + w; b < blk_ptr[g + 1]; b += NEAR_WAVES) {
             const NearBlock B = blk[b];
-            const R *v = vals + B.off + lane;
+            const int ns4 = (B.ns + 3) / 4;
+            const V4 *v = reinterpret_cast<const V4 *>(vals + B.off) + lane;
             const double *xj = xs + (int64_t)NQ * B.j0;
             if constexpr (!STOKES) {
-#pragma unroll 16
-                for (int j = 0; j < B.ns; ++j)
-                    acc[0] += v[(int64_t)j * n] * (R)xj[j];
-            } else {
 #pragma unroll 4
-                for (int j = 0; j < B.ns; ++j) {
-                    const R x0 = (R)xj[3 * j], x1 = (R)xj[3 * j + 1], x2 = (R)xj[3 * j + 2];
-                    const R *vj = v + (int64_t)j * 9 * n;
-                    acc[0] += vj[0] * x0 + vj[n] * x1 + vj[2 * n] * x2;
-                    acc[1] += vj[3 * n] * x0 + vj[4 * n] * x1 + vj[5 * n] * x2;
-                    acc[2] += vj[6 * n] * x0 + vj[7 * n] * x1 + vj[8 * n] * x2;
+                for (int q = 0; q < ns4; ++q) {
+                    const V4 a = v[(int64_t)q * n];
+                    const double *xq = xj + 4 * q;
+                    acc[0] += ((a.x * (R)xq[0] + a.y * (R)xq[1]) + a.z * (R)xq[2]) + a.w * (R)xq[3];
+                }
+            } else {
+                for (int q = 0; q < ns4; ++q) {
+                    const V4 *vq = v + (int64_t)q * 9 * n;
+                    const double *xq = xj + 12 * q;
+                    R xv[12];
+#pragma unroll
+                    for (int k = 0; k < 12; ++k)
+                        xv[k] = (R)xq[k];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const V4 c0 = vq[(3 * a) * n], c1 = vq[(3 * a + 1) * n], c2 = vq[(3 * a + 2) * n];
+                        acc[a] += ((c0.x * xv[0] + c1.x * xv[1]) + c2.x * xv[2]) +
+                                  ((c0.y * xv[3] + c1.y * xv[4]) + c2.y * xv[5]) +
+                                  ((c0.z * xv[6] + c1.z * xv[7]) + c2.z * xv[8]) +
+                                  ((c0.w * xv[9] + c1.w * xv[10]) + c2.w * xv[11]);
+                    }
                 }
             }
         }
@@ -206,7 +236,7 @@ void fold_corrections(fmmbem_ctx *ctx, const std::vector<int4> &units, const std
             if (hit >= 0) {
                 const NearBlock &B = blks[hit];
                 const int n = units[g].y - units[g].x;
-                dst.push_back(B.off + (int64_t)(j - B.j0) * per * n + (i - units[g].x));
+                dst.push_back(near_index(B.off, n, per, j - B.j0, 0, (int)(i - units[g].x)));
                 step.push_back(n);
                 srcidx.push_back(e);
             } else {
@@ -260,6 +290,9 @@ void fold_corrections(fmmbem_ctx *ctx, const std::vector<int4> &units, const std
 
 }  // namespace
 
+// input values per panel (3 for Stokes)
+inline int per_q(const fmmbem_ctx *ctx) { return ctx->kernel == FMMBEM_STOKES_SL ? 3 : 1; }
+
 void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st)
 {
     Tree &T = ctx->tree;
@@ -292,7 +325,7 @@ void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st)
             const int ns = hb[6 * s + 2] - hb[6 * s + 1];
             blks.push_back(NearBlock{hb[6 * s + 1], ns, off});
             bunit.push_back(g);
-            off += (int64_t)n * ns * per;
+            off += (int64_t)n * ((ns + 3) / 4) * 4 * per;  // padded to groups of four sources
             entries += (int64_t)n * ns;
         }
         bptr.push_back((int32_t)blks.size());
@@ -306,7 +339,9 @@ void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st)
     int32_t *blk_unit = A.alloc<int32_t>(std::max<size_t>(bunit.size(), 1));
     N.v64 = A.alloc<double>(std::max<int64_t>(off, 1));
     N.v32 = A.alloc<float>(std::max<int64_t>(off, 1));
-    N.xs = A.alloc<double>(ctx->n);
+    // the last group of a block may read up to three panels past the end
+    N.xs = A.alloc<double>(ctx->n + 3 * per_q(ctx));
+    FB_HIP(hipMemsetAsync(N.xs, 0, sizeof(double) * (ctx->n + 3 * per_q(ctx)), st));
     FB_HIP(hipMemcpyAsync(N.blk_ptr, bptr.data(), sizeof(int32_t) * bptr.size(), hipMemcpyHostToDevice, st));
     if (!blks.empty()) {
         FB_HIP(hipMemcpyAsync(N.blk, blks.data(), sizeof(NearBlock) * blks.size(), hipMemcpyHostToDevice, st));

@@ -60,7 +60,13 @@ int64_t estimate_bytes(int64_t nt, int kernel, const fmmbem_params &prm, const f
     int64_t work = 4 * nt * nch * 8 + 2 * n * 8;
     int64_t kry = ((int64_t)s.restart + 4) * n * 8;
     int64_t io = 2 * n * 8;
-    return geo + corr + exp + ops + lists + work + kry + io + (16 << 20);
+    // stored near field: about ncrit / 2 panels in each of ~20 neighbouring
+    // leaves per target, FP64 + FP32 values (x 9 for Stokes)
+    int64_t near = prm.near_stored ? nt * 10 * prm.ncrit * 12 * (kernel == FMMBEM_STOKES_SL ? 9 : 1) : 0;
+    // stored M2L operators: at most 316 offsets per level pair class
+    const int64_t ntrans = std::min<int64_t>(nbox * 27, 20000);
+    int64_t m2l = prm.m2l_stored ? ntrans * ((dop + 15) / 16) * 16 * ((dop + 3) / 4) * 4 * 8 : 0;
+    return geo + corr + exp + ops + lists + work + kry + io + near + m2l + (16 << 20);
 }
 
 }  // namespace

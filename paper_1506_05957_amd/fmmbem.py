@@ -38,7 +38,7 @@ class fmmbem_mesh(ctypes.Structure):
 
 class fmmbem_params(ctypes.Structure):
     _fields_ = [("theta", c_d), ("ncrit", c_i32), ("p_max", c_i32), ("mu", c_d), ("near_stored", c_i32),
-                ("reserved", c_i32)]
+                ("m2l_stored", c_i32)]
 
 
 class fmmbem_schedule(ctypes.Structure):
@@ -56,7 +56,8 @@ class fmmbem_stats(ctypes.Structure):
     _fields_ = [("n_panels", c_i64), ("n_unknowns", c_i64), ("n_sources", c_i64), ("n_boxes", c_i32),
                 ("n_leaves", c_i32), ("n_levels", c_i32), ("max_leaf", c_i32), ("n_m2l", c_i64),
                 ("n_p2p", c_i64), ("p2p_interactions", c_i64), ("nnz_correction", c_i64),
-                ("device_bytes", c_i64), ("near_entries", c_i64)]
+                ("device_bytes", c_i64), ("near_entries", c_i64), ("n_translations", c_i64),
+                ("m2l_op_bytes", c_i64)]
 
 
 class fmmbem_server_params(ctypes.Structure):
@@ -139,8 +140,8 @@ def make_mesh(xyz, tri):
     return m, (xyz, tri)
 
 
-def params(theta=0.5, ncrit=64, p_max=16, mu=1.0, near_stored=0) -> fmmbem_params:
-    return fmmbem_params(theta, ncrit, p_max, mu, near_stored, 0)
+def params(theta=0.5, ncrit=64, p_max=16, mu=1.0, near_stored=0, m2l_stored=0) -> fmmbem_params:
+    return fmmbem_params(theta, ncrit, p_max, mu, near_stored, m2l_stored)
 
 
 def schedule(kernel=LAPLACE, **kw) -> fmmbem_schedule:
