@@ -192,6 +192,12 @@ const char *fmmbem_last_error(void);
  * channel; the other stages count 0.  Any output pointer may be NULL. */
 #define FMMBEM_N_STAGES 10
 int fmmbem_set_timing(fmmbem_ctx_t *ctx, int enabled);
+/* Times only the stages whose bit is set in mask (bit prec * 5 + stage, the
+ * entry layout of fmmbem_get_timing); every timed stage records two events on
+ * its stream per mat-vec, so a narrow mask keeps the host work of a timed
+ * solve close to that of an untimed one.  0 turns timing off; bits at or past
+ * FMMBEM_N_STAGES give FMMBEM_EINVAL. */
+int fmmbem_set_timing_stages(fmmbem_ctx_t *ctx, uint32_t mask);
 int fmmbem_get_timing(fmmbem_ctx_t *ctx, double *t_ms, int64_t *launches, double *flops, int reset);
 
 /* Introspection for tests: sizes, then copies of the tree and lists in the

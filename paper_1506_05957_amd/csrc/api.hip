@@ -15,7 +15,7 @@ void set_last_error(const std::string &m) { g_last_error = m; }
 void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev)
 {
     *ev = nullptr;
-    if (!ctx->timing.enabled)
+    if (!((ctx->timing.mask >> stage) & 1u))
         return;
     Timing &T = ctx->timing;
     if (T.pool.empty()) {
@@ -26,7 +26,6 @@ void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev)
     *ev = T.pool.back();
     T.pool.pop_back();
     FB_HIP(hipEventRecord(*ev, st));
-    (void)stage;
 }
 
 static void resolve_pending(Timing &T)
@@ -45,7 +44,7 @@ static void resolve_pending(Timing &T)
 
 void stage_end(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t ev, double flops)
 {
-    if (!ctx->timing.enabled || !ev)
+    if (!ev)  // stage not timed
         return;
     Timing &T = ctx->timing;
     if (T.pool.empty()) {
@@ -321,7 +320,17 @@ int fmmbem_set_timing(fmmbem_ctx_t *ctx, int enabled)
 {
     API_BEGIN
     FB_REQUIRE(ctx, FMMBEM_EINVAL, "null argument");
-    ctx->timing.enabled = enabled != 0;
+    ctx->timing.mask = enabled ? (1u << FMMBEM_N_STAGES) - 1u : 0u;
+    return FMMBEM_OK;
+    API_END
+}
+
+int fmmbem_set_timing_stages(fmmbem_ctx_t *ctx, uint32_t mask)
+{
+    API_BEGIN
+    FB_REQUIRE(ctx, FMMBEM_EINVAL, "null argument");
+    FB_REQUIRE(mask < (1u << FMMBEM_N_STAGES), FMMBEM_EINVAL, "stage mask has bits past FMMBEM_N_STAGES");
+    ctx->timing.mask = mask;
     return FMMBEM_OK;
     API_END
 }

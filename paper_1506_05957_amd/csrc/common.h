@@ -119,7 +119,7 @@ struct Correction {
 };
 
 struct Timing {
-    bool enabled = false;
+    uint32_t mask = 0;  // bit s: stage s is timed
     double t_ms[FMMBEM_N_STAGES] = {0};
     int64_t launches[FMMBEM_N_STAGES] = {0};
     double flops[FMMBEM_N_STAGES] = {0};

@@ -87,6 +87,7 @@ _sig("fmmbem_get_stats", ctypes.c_int, [c_vp, P(fmmbem_stats)])
 _sig("fmmbem_destroy", None, [c_vp])
 _sig("fmmbem_last_error", ctypes.c_char_p, [])
 _sig("fmmbem_set_timing", ctypes.c_int, [c_vp, ctypes.c_int])
+_sig("fmmbem_set_timing_stages", ctypes.c_int, [c_vp, ctypes.c_uint32])
 _sig("fmmbem_get_timing", ctypes.c_int, [c_vp, P(c_d), P(c_i64), P(c_d), ctypes.c_int])
 _sig("fmmbem_tree_sizes", ctypes.c_int, [c_vp, P(c_i64)])
 _sig("fmmbem_tree_get", ctypes.c_int, [c_vp, P(c_i32), P(ctypes.c_uint64), P(c_i32), P(c_d), P(c_i32),
@@ -239,6 +240,12 @@ def fmmbem_destroy(ctx: Context):
 
 def fmmbem_set_timing(ctx: Context, enabled: bool):
     _check(_lib.fmmbem_set_timing(ctx.handle, int(bool(enabled))))
+
+
+def fmmbem_set_timing_stages(ctx: Context, stages):
+    """Time only the named stages (names of STAGES) or a bit mask."""
+    mask = stages if isinstance(stages, int) else sum(1 << STAGES.index(s) for s in stages)
+    _check(_lib.fmmbem_set_timing_stages(ctx.handle, mask))
 
 
 def fmmbem_get_timing(ctx: Context, reset: bool = False):

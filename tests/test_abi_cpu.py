@@ -81,6 +81,7 @@ def test_null_arguments(fb):
     assert fb._lib.fmmbem_build(None, 0, None, None, None) == fb.EINVAL
     assert fb._lib.fmmbem_matvec(None, 5, 0, None, None, None) == fb.EINVAL
     assert fb._lib.fmmbem_get_stats(None, None) == fb.EINVAL
+    assert fb._lib.fmmbem_set_timing_stages(None, 1) == fb.EINVAL
     fb._lib.fmmbem_destroy(None)
 
 
