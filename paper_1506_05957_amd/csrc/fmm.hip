@@ -521,14 +521,37 @@ __global__ __launch_bounds__(256) void k_octant_apply(int p, int ncs, int D, con
 #pragma unroll
     for (int q = 0; q < NCOL; ++q)
         acc[q] = 0;
-    if (active) {
-        // the first k of this wave's residue class at or above k0
-        for (int k = k0 + ((w - k0) % NW + NW) % NW; k < k1; k += NW) {
-            const R a = A[(int64_t)k * D];
-            const R *x = xs + k * NCOL;
+    // wave w takes the inputs k = w + NW t, t < nit, the same for all its
+    // lanes; entries outside the lane's triangle [k0, k1) are zeroed after an
+    // unguarded read (rows past Dp read row 0 and are not stored), so the
+    // operator reads of the next PF steps stay in flight
+    {
+        constexpr int PF = 8;
+        const int nit = w < Dp ? (Dp - w + NW - 1) / NW : 0;
+        if (nit > 0) {
+            R ring[PF];
 #pragma unroll
-            for (int q = 0; q < NCOL; ++q)
-                acc[q] += a * x[q];
+            for (int j = 0; j < PF; ++j)
+                ring[j] = A[(int64_t)(w + NW * min(j, nit - 1)) * D];
+            auto step = [&](int t, R &slot) {
+                const int k = w + NW * t;
+                const R a = (k >= k0 && k < k1) ? slot : R(0);
+                const R *x = xs + k * NCOL;
+#pragma unroll
+                for (int q = 0; q < NCOL; ++q)
+                    acc[q] += a * x[q];
+                slot = A[(int64_t)(w + NW * min(t + PF, nit - 1)) * D];
+            };
+            const int nfull = nit - nit % PF;
+            for (int t0 = 0; t0 < nfull; t0 += PF) {
+#pragma unroll
+                for (int j = 0; j < PF; ++j)
+                    step(t0 + j, ring[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < PF; ++j)
+                if (nfull + j < nit)
+                    step(nfull + j, ring[j]);
         }
     }
     __syncthreads();  // xs is dead from here on
@@ -794,6 +817,7 @@ __global__ __launch_bounds__(256) void k_m2l_opgen(int pmax, int q_tab, int nrt,
 constexpr int M2LS_RB = 3;
 template <int NCH, int NT>
 __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, int k4_s,
+                                                    const int32_t *__restrict__ chunk_list,
                                                     const int32_t *__restrict__ chunk_begin,
                                                     const int32_t *__restrict__ chunk_trans,
                                                     const int32_t *__restrict__ pair_sorted,
@@ -806,7 +830,7 @@ __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, i
     double *Bs = reinterpret_cast<double *>(smem_raw);  // [Kp][ldb]
     int *colbase = reinterpret_cast<int *>(Bs + ldb * (size_t)((2 * ncoef(p) + 3) & ~3));  // [16 NT]
     const int nc = ncoef(p), Dp = 2 * nc, Kp = (Dp + 3) & ~3, nrt = (Dp + 15) / 16;
-    const int c = blockIdx.x;
+    const int c = chunk_list[blockIdx.x];
     const int u = chunk_trans[c], pb = chunk_begin[c], pe = chunk_begin[c + 1];
     const int ncol = (pe - pb) * NCH, nct = (ncol + 15) / 16;
     constexpr int nwave = 4;  // launched with 256 threads
@@ -871,28 +895,34 @@ __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, i
 #pragma unroll
                 for (int i = 0; i < RB; ++i)
                     ring[j][i] = At[i][(int64_t)min(j, nsteps - 1) * 64];
-            for (int s0 = 0; s0 < nsteps; s0 += PF) {
+            // full groups of PF steps carry no branch, so that the wait for a
+            // ring slot covers only its own read; the remainder follows
+            auto step = [&](int st, double *slot) {
+                const double *brow = Bs + (4 * st + lk) * ldb + li;
+                double bv[NT];
 #pragma unroll
-                for (int j = 0; j < PF; ++j) {
-                    const int st = s0 + j;
-                    if (st < nsteps) {
-                        const double *brow = Bs + (4 * st + lk) * ldb + li;
-                        double bv[NT];
+                for (int ct = 0; ct < NT; ++ct)
+                    bv[ct] = brow[16 * ct];
 #pragma unroll
-                        for (int ct = 0; ct < NT; ++ct)
-                            bv[ct] = brow[16 * ct];
+                for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
-                        for (int ct = 0; ct < NT; ++ct)
+                    for (int i = 0; i < RB; ++i)
+                        acc[i][ct] = mfma_16x16x4(slot[i], bv[ct], acc[i][ct]);
+                const int sn = min(st + PF, nsteps - 1);
 #pragma unroll
-                            for (int i = 0; i < RB; ++i)
-                                acc[i][ct] = mfma_16x16x4(ring[j][i], bv[ct], acc[i][ct]);
-                        const int sn = min(st + PF, nsteps - 1);
+                for (int i = 0; i < RB; ++i)
+                    slot[i] = At[i][(int64_t)sn * 64];
+            };
+            const int nfull = nsteps - nsteps % PF;
+            for (int s0 = 0; s0 < nfull; s0 += PF) {
 #pragma unroll
-                        for (int i = 0; i < RB; ++i)
-                            ring[j][i] = At[i][(int64_t)sn * 64];
-                    }
-                }
+                for (int j = 0; j < PF; ++j)
+                    step(s0 + j, ring[j]);
             }
+#pragma unroll
+            for (int j = 0; j < PF; ++j)
+                if (nfull + j < nsteps)
+                    step(nfull + j, ring[j]);
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 const int rt = rb + i * nwave;
@@ -1048,7 +1078,23 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_
         const int nsl_here = max(1, (int)blockDim.x / span);
         const int ch = t / nc, idx = t - ch * nc;
         R sr = 0, si = 0;
-        if (sl < nsl_here) {
+        if (sl < nsl_here && !FIXC) {
+            // U reads issued together (clamped to the last pair, the extra
+            // ones dropped), then added in pair order
+            constexpr int U = 8;
+            for (int e = e0 + sl; e < e1; e += U * nsl_here) {
+                cplx<R> v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    v[u] = Y[(int64_t)min(e + u * nsl_here, e1 - 1) * no + t];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (e + u * nsl_here < e1) {
+                        sr += v[u].re;
+                        si += v[u].im;
+                    }
+            }
+        } else if (sl < nsl_here) {
             for (int e = e0 + sl; e < e1; e += nsl_here) {
                 const cplx<R> v = Y[(int64_t)e * no + t];
                 sr += v.re;
@@ -1555,15 +1601,22 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
                 k_m2l_mfma<R, NCH><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), st>>>(
                     p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
             } else if (P.ops64) {
-                // two column tiles per pass while they fit in 64 KB of LDS (p <= 13)
-                if (m2l_stored_shm(p, 2) <= 65536)
-                    k_m2l_stored<NCH, 2><<<P.n_chunks, 256, m2l_stored_shm(p, 2), st>>>(
-                        p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin, P.chunk_trans, P.pair_sorted, T.m2l_pairs,
-                        P.ops64, M, Y);
-                else
-                    k_m2l_stored<NCH, 1><<<P.n_chunks, 256, m2l_stored_shm(p, 1), st>>>(
-                        p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin, P.chunk_trans, P.pair_sorted, T.m2l_pairs,
-                        P.ops64, M, Y);
+                // narrow chunks with one column tile per pass; wide ones with
+                // two while they fit in 64 KB of LDS (p <= 13), else one
+                if (P.n_narrow > 0)
+                    k_m2l_stored<NCH, 1><<<P.n_narrow, 256, m2l_stored_shm(p, 1), st>>>(
+                        p, ncs, P.ops_nrt, P.ops_k4, P.chunks_narrow, P.chunk_begin, P.chunk_trans, P.pair_sorted,
+                        T.m2l_pairs, P.ops64, M, Y);
+                if (P.n_wide > 0) {
+                    if (m2l_stored_shm(p, 2) <= 65536)
+                        k_m2l_stored<NCH, 2><<<P.n_wide, 256, m2l_stored_shm(p, 2), st>>>(
+                            p, ncs, P.ops_nrt, P.ops_k4, P.chunks_wide, P.chunk_begin, P.chunk_trans,
+                            P.pair_sorted, T.m2l_pairs, P.ops64, M, Y);
+                    else
+                        k_m2l_stored<NCH, 1><<<P.n_wide, 256, m2l_stored_shm(p, 1), st>>>(
+                            p, ncs, P.ops_nrt, P.ops_k4, P.chunks_wide, P.chunk_begin, P.chunk_trans,
+                            P.pair_sorted, T.m2l_pairs, P.ops64, M, Y);
+                }
             } else {
                 constexpr int PB = NCH == 1 ? 8 : 2;
                 const size_t shm = sizeof(cplx<R>) * (size_t)(2 * p + 1) * (2 * p + 1);
@@ -1689,6 +1742,22 @@ void build_m2l_operators(fmmbem_ctx *ctx, hipStream_t st)
     k_m2l_opgen<<<dim3(P.n_trans, P.ops_nrt), 256, 0, st>>>(ctx->prm.p_max, P.q, P.ops_nrt, P.ops_k4, P.trans_key,
                                                            P.table64, P.ops64);
     FB_HIP(hipGetLastError());
+    // chunks by width
+    std::vector<int32_t> cb(P.n_chunks + 1), narrow, wide;
+    FB_HIP(hipMemcpyAsync(cb.data(), P.chunk_begin, sizeof(int32_t) * (P.n_chunks + 1), hipMemcpyDeviceToHost, st));
+    FB_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < P.n_chunks; ++c)
+        ((cb[c + 1] - cb[c]) * ctx->nch <= 16 ? narrow : wide).push_back(c);
+    P.n_narrow = (int)narrow.size();
+    P.n_wide = (int)wide.size();
+    P.chunks_narrow = ctx->arena.alloc<int32_t>(std::max<size_t>(narrow.size(), 1));
+    P.chunks_wide = ctx->arena.alloc<int32_t>(std::max<size_t>(wide.size(), 1));
+    if (!narrow.empty())
+        FB_HIP(hipMemcpyAsync(P.chunks_narrow, narrow.data(), sizeof(int32_t) * narrow.size(), hipMemcpyHostToDevice,
+                              st));
+    if (!wide.empty())
+        FB_HIP(hipMemcpyAsync(P.chunks_wide, wide.data(), sizeof(int32_t) * wide.size(), hipMemcpyHostToDevice, st));
+    FB_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
 }
 
 }  // namespace fmmbem
