@@ -43,6 +43,11 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
+def ms_pct(a, q):
+    """q-th percentile of times a in ms, or None when nothing was timed."""
+    return 1e3 * pct(a, q) if len(a) else None
+
+
 # source regions the HBM counter records were taken on: file, first marker, end marker
 COUNTED_SOURCES = {
     "k_p2p<float, false>": [("fmm.hip", "// P2P: one block per work unit", "// ----"), ("tree.hip", "// P2P work units", "}  // namespace")],
@@ -50,6 +55,7 @@ COUNTED_SOURCES = {
     "k_near_spmv<double, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
     "k_m2l_valu<double, 1, 8>": [("fmm.hip", "// The same pass 1 on the vector units", "// Pass 2:")],
     "k_m2l_stored<1, 2>": [("fmm.hip", "// Pass 1 in FP64 from the stored operators", "// LDS of k_m2l_stored")],
+    "k_m2l_reduce<double, 1, false>": [("fmm.hip", "// Pass 2: L(T) = sum of Y", "\n}\n")],
 }
 
 
@@ -88,6 +94,7 @@ def kernel_traffic(kernel: str):
                 return None
             return float(rec["traffic_bytes_per_launch"])
     return None
+
 
 
 def stokes_cells(fb, syn, torch, dev, ncrit_relaxed=128, ncrit_fixed=256):
@@ -209,6 +216,9 @@ def main():
     ap.add_argument("--m2l", choices=("stored", "fly"), default="stored",
                     help="FP64 M2L operators of the Laplace workloads: stored at build or generated per mat-vec")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="warm-up and timed region only: no comparison solves, mat-vec rates, CPU baseline or "
+                         "extra cases (for profiling the timed kernels alone)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 64-cell Stokes comparison and the serving stream")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
@@ -306,8 +316,13 @@ def main():
         return ts, its
 
     k_cmp = max(5, min(args.steps, 10))
-    t_fixed, it_fixed = time_solves(fixed, k_cmp)
-    t_rel64, it_rel64 = time_solves(relaxed64, k_cmp)
+    if args.timed_only:
+        args.no_cpu = args.no_extra = True
+        t_fixed = t_rel64 = []
+        it_fixed = it_rel64 = [0]
+    else:
+        t_fixed, it_fixed = time_solves(fixed, k_cmp)
+        t_rel64, it_rel64 = time_solves(relaxed64, k_cmp)
 
     # ---- mat-vec rates
     def matvec_rate(p, prec, reps=50):
@@ -320,8 +335,11 @@ def main():
         torch.cuda.synchronize()
         return reps / (time.perf_counter() - t)
 
-    mv = {"p12_fp64": matvec_rate(12, fb.FP64), "p12_fp32": matvec_rate(12, fb.FP32),
-          "p6_fp32": matvec_rate(6, fb.FP32), "p3_fp32": matvec_rate(3, fb.FP32)}
+    if args.timed_only:
+        mv = {}
+    else:
+        mv = {"p12_fp64": matvec_rate(12, fb.FP64), "p12_fp32": matvec_rate(12, fb.FP32),
+              "p6_fp32": matvec_rate(6, fb.FP32), "p3_fp32": matvec_rate(3, fb.FP32)}
 
     # ---- roofline of the dominant kernel stage, timed live in the timed region
     t_ms, launches, flops = stage[dom]
@@ -338,15 +356,15 @@ def main():
                     "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": kernel_traffic(kname), "avg_launch_us": avg_s * 1e6,
                     "launches": launches, "bytes_per_launch": nbytes}
     elif dom == "m2l_fp64" and stats["m2l_op_bytes"] > 0:
-        # stored operators: each translation's operator streams from HBM once
-        # (order 12 = p_max: all of it), plus the multipoles read and the
-        # per-pair results written and summed
+        # M2L pass 1 from stored operators: each translation's operator streams
+        # from HBM once (order 12 = p_max: all of it), plus the multipoles read
+        # and the per-pair results written
         nc = 91
-        nbytes = (stats["m2l_op_bytes"] + stats["n_boxes"] * 2 * nc * 8 + 2 * stats["n_m2l"] * 2 * nc * 8)
-        kname = "k_m2l_stored<1, 2> + k_m2l_reduce<double, 1, false>"
+        nbytes = stats["m2l_op_bytes"] + stats["n_boxes"] * 2 * nc * 8 + stats["n_m2l"] * 2 * nc * 8
+        kname = "k_m2l_stored<1, 2>"
         achieved = nbytes / avg_s
         roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
-                    "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": kernel_traffic("k_m2l_stored<1, 2>"),
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": kernel_traffic(kname),
                     "avg_launch_us": avg_s * 1e6, "launches": launches, "bytes_per_launch": nbytes,
                     "flops_per_launch": flops / max(launches, 1),
                     "fp64_tflops": flops / max(launches, 1) / avg_s / 1e12}
@@ -354,10 +372,9 @@ def main():
         achieved = flops / max(launches, 1) / avg_s
         peak = PEAK_FP32_VALU if dom.endswith("fp32") else PEAK_FP64_VALU
         kname = {"p2p_fp32": "k_p2p<float, false>", "p2p_fp64": "k_p2p<double, false>",
-                 "m2l_fp32": "k_m2l_mfma<float, 1> + k_m2l_reduce<float, 1, false>",
-                 "m2l_fp64": "k_m2l_valu<double, 1, 8> + k_m2l_reduce<double, 1, false>"}[dom]
+                 "m2l_fp32": "k_m2l_mfma<float, 1>", "m2l_fp64": "k_m2l_valu<double, 1, 8>"}[dom]
         roofline = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": kernel_traffic(kname.split(" + ")[0]),
+                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": kernel_traffic(kname),
                     "avg_launch_us": avg_s * 1e6, "launches": launches,
                     "flops_per_launch": flops / max(launches, 1)}
 
@@ -413,14 +430,14 @@ def main():
                    "rhs": [f"Y_{l}^{m}" for l, m in orders], "ncrit": args.ncrit, "theta": 0.5, "restart": 50,
                    "near_field": args.near, "m2l_fp64": args.m2l},
         "solve_ms": {"relaxed_mixed_p50": 1e3 * pct(times, 50), "relaxed_mixed_p99": 1e3 * pct(times, 99),
-                     "relaxed_fp64_p50": 1e3 * pct(t_rel64, 50), "relaxed_fp64_p99": 1e3 * pct(t_rel64, 99),
-                     "fixed_p12_fp64_p50": 1e3 * pct(t_fixed, 50), "fixed_p12_fp64_p99": 1e3 * pct(t_fixed, 99)},
-        "speedup_relaxed_vs_fixed": pct(t_fixed, 50) / pct(times, 50),
+                     "relaxed_fp64_p50": ms_pct(t_rel64, 50), "relaxed_fp64_p99": ms_pct(t_rel64, 99),
+                     "fixed_p12_fp64_p50": ms_pct(t_fixed, 50), "fixed_p12_fp64_p99": ms_pct(t_fixed, 99)},
+        "speedup_relaxed_vs_fixed": None if args.timed_only else pct(t_fixed, 50) / pct(times, 50),
         "iterations": {"relaxed_mixed": float(np.mean(iters)), "relaxed_fp64": float(np.mean(it_rel64)),
                        "fixed": float(np.mean(it_fixed))},
         "matvec_per_s": {"in_relaxed_solves": matvecs / t_total, **mv},
         "p2p_interactions_per_matvec": stats["p2p_interactions"],
-        "p2p_interactions_per_s_fp32": stats["p2p_interactions"] * mv["p3_fp32"],
+        "p2p_interactions_per_s_fp32": stats["p2p_interactions"] * mv["p3_fp32"] if mv else None,
         "p_history_last": last_p, "prec_history_last": last_prec,
         "stage_ms": stage_split,
         "stage_ms_warmup_all_stages": {k: {"ms": round(v[0], 3), "launches": v[1]}

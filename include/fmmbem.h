@@ -181,15 +181,20 @@ const char *fmmbem_last_error(void);
 
 /* Per-stage device time, accumulated with HIP events recorded on the stream
  * each kernel is launched on, while timing is enabled.  Stages: 0 P2P (one
- * kernel), 1 M2L (two kernels), 2 P2M+M2M, 3 L2L+L2P (L2P also combines far
- * field, near field and corrections, after waiting for the near field), 4
+ * kernel), 1 M2L pass 1 (the per-pair translations, one kernel), 2 P2M+M2M,
+ * 3 the downward pass: the per-target sum of the M2L terms, L2L and L2P (L2P
+ * also combines far field, near field and corrections, after waiting for the
+ * near field), 4
  * charges (+ the combine when no box pair is far); entry [prec * 5 + stage]
  * holds the launches made in precision
  * prec (FMMBEM_FP64 = 0, FMMBEM_FP32 = 1), FMMBEM_N_STAGES entries in all.
  * t_ms[i] is the total time, launches[i] the number of timed launches and
- * flops[i] the algorithmic flops of those launches: P2P counts 12 (Laplace) or
- * 30 (Stokes) per source-target pair, M2L 4 (p+1)^3 (p+2) per box pair and
- * channel; the other stages count 0.  Any output pointer may be NULL. */
+ * flops[i] the algorithmic flops of those launches: P2P evaluated on the fly
+ * counts 12 (Laplace single layer), 18 (double layer) or 30 (Stokes) per
+ * source-target pair, the stored near field 2 per stored value (9 values per
+ * panel pair for Stokes), M2L 8 ncoef(p)^2 per box pair and channel (the real
+ * (2 ncoef(p))^2 operator times a coefficient vector); the other stages
+ * count 0.  Any output pointer may be NULL. */
 #define FMMBEM_N_STAGES 10
 int fmmbem_set_timing(fmmbem_ctx_t *ctx, int enabled);
 /* Times only the stages whose bit is set in mask (bit prec * 5 + stage, the

@@ -170,10 +170,6 @@ struct M2LPlan {
     double *ops64 = nullptr;
     int ops_nrt = 0, ops_k4 = 0;
     int64_t ops_bytes = 0;
-    // chunks of at most 16 columns (pairs x channels) and the wider ones,
-    // launched with one and with two column tiles per pass
-    int32_t *chunks_narrow = nullptr, *chunks_wide = nullptr;
-    int n_narrow = 0, n_wide = 0;
 };
 
 // The regular near field stored as a block-sparse matrix (nearfield.hip): per

@@ -817,7 +817,6 @@ __global__ __launch_bounds__(256) void k_m2l_opgen(int pmax, int q_tab, int nrt,
 constexpr int M2LS_RB = 3;
 template <int NCH, int NT>
 __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, int k4_s,
-                                                    const int32_t *__restrict__ chunk_list,
                                                     const int32_t *__restrict__ chunk_begin,
                                                     const int32_t *__restrict__ chunk_trans,
                                                     const int32_t *__restrict__ pair_sorted,
@@ -830,7 +829,7 @@ __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, i
     double *Bs = reinterpret_cast<double *>(smem_raw);  // [Kp][ldb]
     int *colbase = reinterpret_cast<int *>(Bs + ldb * (size_t)((2 * ncoef(p) + 3) & ~3));  // [16 NT]
     const int nc = ncoef(p), Dp = 2 * nc, Kp = (Dp + 3) & ~3, nrt = (Dp + 15) / 16;
-    const int c = chunk_list[blockIdx.x];
+    const int c = blockIdx.x;
     const int u = chunk_trans[c], pb = chunk_begin[c], pe = chunk_begin[c + 1];
     const int ncol = (pe - pb) * NCH, nct = (ncol + 15) / 16;
     constexpr int nwave = 4;  // launched with 256 threads
@@ -1601,22 +1600,15 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
                 k_m2l_mfma<R, NCH><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), st>>>(
                     p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
             } else if (P.ops64) {
-                // narrow chunks with one column tile per pass; wide ones with
-                // two while they fit in 64 KB of LDS (p <= 13), else one
-                if (P.n_narrow > 0)
-                    k_m2l_stored<NCH, 1><<<P.n_narrow, 256, m2l_stored_shm(p, 1), st>>>(
-                        p, ncs, P.ops_nrt, P.ops_k4, P.chunks_narrow, P.chunk_begin, P.chunk_trans, P.pair_sorted,
-                        T.m2l_pairs, P.ops64, M, Y);
-                if (P.n_wide > 0) {
-                    if (m2l_stored_shm(p, 2) <= 65536)
-                        k_m2l_stored<NCH, 2><<<P.n_wide, 256, m2l_stored_shm(p, 2), st>>>(
-                            p, ncs, P.ops_nrt, P.ops_k4, P.chunks_wide, P.chunk_begin, P.chunk_trans,
-                            P.pair_sorted, T.m2l_pairs, P.ops64, M, Y);
-                    else
-                        k_m2l_stored<NCH, 1><<<P.n_wide, 256, m2l_stored_shm(p, 1), st>>>(
-                            p, ncs, P.ops_nrt, P.ops_k4, P.chunks_wide, P.chunk_begin, P.chunk_trans,
-                            P.pair_sorted, T.m2l_pairs, P.ops64, M, Y);
-                }
+                // two column tiles per pass while they fit in 64 KB of LDS (p <= 13)
+                if (m2l_stored_shm(p, 2) <= 65536)
+                    k_m2l_stored<NCH, 2><<<P.n_chunks, 256, m2l_stored_shm(p, 2), st>>>(
+                        p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin, P.chunk_trans, P.pair_sorted, T.m2l_pairs,
+                        P.ops64, M, Y);
+                else
+                    k_m2l_stored<NCH, 1><<<P.n_chunks, 256, m2l_stored_shm(p, 1), st>>>(
+                        p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin, P.chunk_trans, P.pair_sorted, T.m2l_pairs,
+                        P.ops64, M, Y);
             } else {
                 constexpr int PB = NCH == 1 ? 8 : 2;
                 const size_t shm = sizeof(cplx<R>) * (size_t)(2 * p + 1) * (2 * p + 1);
@@ -1624,16 +1616,20 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
                     p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
             }
             FB_HIP(hipGetLastError());
+        }
+        // real form: a (2 nc) x (2 nc) operator times each pair's coefficients, per channel
+        stage_end(ctx, SO + 1, st, ev, 8.0 * ncoef(p) * ncoef(p) * NCH * (double)T.n_m2l);
+
+        // the downward pass: the per-target sum of the M2L terms, then L2L and L2P
+        stage_begin(ctx, SO + 3, st, &ev);
+        {
+            cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
             if constexpr (NCH == 4)
                 k_m2l_reduce<R, NCH, true><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             else
                 k_m2l_reduce<R, NCH, false><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             FB_HIP(hipGetLastError());
         }
-        // real form: a (2 nc) x (2 nc) operator times each pair's coefficients, per channel
-        stage_end(ctx, SO + 1, st, ev, 8.0 * ncoef(p) * ncoef(p) * NCH * (double)T.n_m2l);
-
-        stage_begin(ctx, SO + 3, st, &ev);
         // parents of level l - 1 into children of level l; levels above the
         // coarsest M2L target hold no local expansion
         for (int l = std::max(1, P.lmin_tgt + 1); l < T.nlevels; ++l) {
@@ -1742,22 +1738,6 @@ void build_m2l_operators(fmmbem_ctx *ctx, hipStream_t st)
     k_m2l_opgen<<<dim3(P.n_trans, P.ops_nrt), 256, 0, st>>>(ctx->prm.p_max, P.q, P.ops_nrt, P.ops_k4, P.trans_key,
                                                            P.table64, P.ops64);
     FB_HIP(hipGetLastError());
-    // chunks by width
-    std::vector<int32_t> cb(P.n_chunks + 1), narrow, wide;
-    FB_HIP(hipMemcpyAsync(cb.data(), P.chunk_begin, sizeof(int32_t) * (P.n_chunks + 1), hipMemcpyDeviceToHost, st));
-    FB_HIP(hipStreamSynchronize(st));
-    for (int c = 0; c < P.n_chunks; ++c)
-        ((cb[c + 1] - cb[c]) * ctx->nch <= 16 ? narrow : wide).push_back(c);
-    P.n_narrow = (int)narrow.size();
-    P.n_wide = (int)wide.size();
-    P.chunks_narrow = ctx->arena.alloc<int32_t>(std::max<size_t>(narrow.size(), 1));
-    P.chunks_wide = ctx->arena.alloc<int32_t>(std::max<size_t>(wide.size(), 1));
-    if (!narrow.empty())
-        FB_HIP(hipMemcpyAsync(P.chunks_narrow, narrow.data(), sizeof(int32_t) * narrow.size(), hipMemcpyHostToDevice,
-                              st));
-    if (!wide.empty())
-        FB_HIP(hipMemcpyAsync(P.chunks_wide, wide.data(), sizeof(int32_t) * wide.size(), hipMemcpyHostToDevice, st));
-    FB_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
 }
 
 }  // namespace fmmbem
