@@ -494,19 +494,39 @@ __global__ __launch_bounds__(256) void k_octant_apply(int p, int ncs, int D, con
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R *xs = reinterpret_cast<R *>(smem_raw);    // [Dp][NCOL], then
     R *part = reinterpret_cast<R *>(smem_raw);  // [NW - 1][NCOL][64]
+    __shared__ int64_t colofs[NCOL];  // first real of each column's input, -1 past the tile
     const int4 tl = tiles[tile0 + blockIdx.x];
     const int o = tl.x, e0 = tl.y, cnt = tl.z;
     const int Dp = 2 * ncoef(p);
-    for (int t = threadIdx.x; t < NCOL * Dp; t += blockDim.x) {
-        const int col = t / Dp, k = t - col * Dp;
-        const int b = col / NCH, ch = col - b * NCH;
-        R v = 0;
+    if ((int)threadIdx.x < NCOL) {
+        const int col = threadIdx.x, b = col / NCH, ch = col - b * NCH;
+        int64_t ofs = -1;
         if (b < cnt) {
             const int box = list[e0 + b];
             const int from = L2L ? box_i[6 * box + 3] : box;
-            v = reinterpret_cast<const R *>(X + ((int64_t)from * NCH + ch) * ncs)[k];
+            ofs = 2 * (((int64_t)from * NCH + ch) * ncs);
         }
-        xs[k * NCOL + col] = v;
+        colofs[col] = ofs;
+    }
+    __syncthreads();
+    // wave w stages columns 4 w .. 4 w + 3, the loads of a row issued together
+    // (columns past the tile read offset 0 and store zero)
+    {
+        const int w0 = threadIdx.x >> 6, lane0 = threadIdx.x & 63;
+        const R *Xr = reinterpret_cast<const R *>(X);
+        int64_t ofs[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            ofs[c] = colofs[4 * w0 + c];
+        for (int k = lane0; k < Dp; k += 64) {
+            R v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                v[c] = Xr[(ofs[c] < 0 ? 0 : ofs[c]) + k];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                xs[k * NCOL + 4 * w0 + c] = ofs[c] < 0 ? R(0) : v[c];
+        }
     }
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
