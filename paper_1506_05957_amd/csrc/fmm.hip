@@ -625,13 +625,19 @@ __global__ void k_m2m_sum(int p, int ncs, int npar, const int32_t *__restrict__ 
     const int i = (int)(t / (NCH * nc)), rem = (int)(t - (int64_t)i * NCH * nc);
     const int ch = rem / nc, c = rem - ch * nc;
     const int P = parents[i];
-    const int c0 = box_i[6 * P + 4], c1 = c0 + box_i[6 * P + 5];
+    const int c0 = box_i[6 * P + 4], nch = box_i[6 * P + 5];  // 1..8 children
+    // the (at most 8) children's terms read together, added in child order
+    cplx<R> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        v[u] = Z[((int64_t)(c0 + min(u, nch - 1)) * NCH + ch) * ncs + c];
     R sr = 0, si = 0;
-    for (int C = c0; C < c1; ++C) {
-        const cplx<R> v = Z[((int64_t)C * NCH + ch) * ncs + c];
-        sr += v.re;
-        si += v.im;
-    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (u < nch) {
+            sr += v[u].re;
+            si += v[u].im;
+        }
     M[((int64_t)P * NCH + ch) * ncs + c] = cplx<R>{sr, si};
 }
 
