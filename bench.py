@@ -54,7 +54,8 @@ COUNTED_SOURCES = {
     "k_near_spmv<float, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
     "k_near_spmv<double, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
     "k_m2l_valu<double, 1, 8>": [("fmm.hip", "// The same pass 1 on the vector units", "// Pass 2:")],
-    "k_m2l_stored<1, 2>": [("fmm.hip", "// Pass 1 in FP64 from the stored operators", "// LDS of k_m2l_stored")],
+    "k_m2l_stored<1>": [("fmm.hip", "// Pass 1 in FP64 from the stored operators",
+                         "template <typename R> size_t m2l_mfma_shm")],
     "k_m2l_reduce<double, 1, false>": [("fmm.hip", "// Pass 2: L(T) = sum of Y", "\n}\n")],
 }
 
@@ -361,7 +362,7 @@ def main():
         # and the per-pair results written
         nc = 91
         nbytes = stats["m2l_op_bytes"] + stats["n_boxes"] * 2 * nc * 8 + stats["n_m2l"] * 2 * nc * 8
-        kname = "k_m2l_stored<1, 2>"
+        kname = "k_m2l_stored<1>"
         achieved = nbytes / avg_s
         roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9,
                     "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": kernel_traffic(kname),

@@ -831,17 +831,21 @@ __global__ __launch_bounds__(256) void k_m2l_opgen(int pmax, int q_tab, int nrt,
     }
 }
 
-// Pass 1 in FP64 from the stored operators: the A element of every
-// matrix-core step is loaded (one coalesced 512-byte read per wave and step)
-// instead of generated.  The chunk's input columns are staged in LDS, NT
-// column tiles per pass (stride 16 NT + 1 against bank conflicts; columns
-// past the chunk are zero, so every product runs unconditionally and the
-// accumulators stay in place), and each wave runs RB row tiles at once so
-// that their products overlap.  Order
-// p < p_max uses the leading rows and inputs of the stored operator; the rest
-// of a boundary tile meets zero inputs and unstored outputs.
-constexpr int M2LS_RB = 3;
-template <int NCH, int NT>
+// Pass 1 in FP64 from the stored operators.  Block = chunk (at most 64
+// columns: pairs x channels, one key); wave w runs row tiles w, w + 4, w + 8
+// of the operator (three products in flight) with an eight-step ring of
+// operator reads (one coalesced 512-byte read per wave and step, never
+// guarded: a guarded read would wait on itself), so each operator value is
+// read once per chunk.  The chunk's inputs are staged in LDS one window of
+// 16 steps (64 inputs) at a time for all four column tiles ([64][65]
+// doubles, zero past the chunk and past 2 ncoef(p)); the window barriers
+// leave the ring's reads in flight.  Column tiles past the chunk are skipped
+// (a branch uniform over the block).  Row tiles past nrt repeat the last one
+// and are not stored; steps past the order's own read a stored value and meet
+// zero inputs.
+constexpr int M2LS_RB = 3;   // row tiles per wave
+constexpr int M2LS_WS = 16;  // steps per staged window
+template <int NCH>
 __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, int k4_s,
                                                     const int32_t *__restrict__ chunk_begin,
                                                     const int32_t *__restrict__ chunk_trans,
@@ -850,133 +854,105 @@ __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, i
                                                     const cplx<double> *__restrict__ M, cplx<double> *__restrict__ Y)
 {
     typedef Acc4<double>::type acc_t;
-    constexpr int RB = M2LS_RB, ldb = 16 * NT + 1;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *Bs = reinterpret_cast<double *>(smem_raw);  // [Kp][ldb]
-    int *colbase = reinterpret_cast<int *>(Bs + ldb * (size_t)((2 * ncoef(p) + 3) & ~3));  // [16 NT]
-    const int nc = ncoef(p), Dp = 2 * nc, Kp = (Dp + 3) & ~3, nrt = (Dp + 15) / 16;
-    const int c = blockIdx.x;
-    const int u = chunk_trans[c], pb = chunk_begin[c], pe = chunk_begin[c + 1];
-    const int ncol = (pe - pb) * NCH, nct = (ncol + 15) / 16;
+    constexpr int RB = M2LS_RB, NT = 4, WS = M2LS_WS, PF = 8, ldb = 16 * NT + 1;
     constexpr int nwave = 4;  // launched with 256 threads
+    static_assert(WS % PF == 0 && 4 * WS == 64, "a window is 64 inputs, whole ring groups");
+    __shared__ double Bs[4 * WS * ldb];
+    __shared__ int colbase[16 * NT];
+    const int nc = ncoef(p), Dp = 2 * nc, nsteps = (Dp + 3) / 4, nrt = (Dp + 15) / 16;
+    const int c = blockIdx.x;
+    const int u = chunk_trans[c], pb = chunk_begin[c];
+    const int ncol = (chunk_begin[c + 1] - pb) * NCH, nct = (ncol + 15) / 16;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
+    if ((int)threadIdx.x < 16 * NT) {
+        const int j = threadIdx.x;
+        int cb = -1;
+        if (j < ncol) {
+            const int pl = j / NCH, ch = j - pl * NCH;
+            cb = 2 * (pairs[2 * pair_sorted[pb + pl] + 1] * NCH + ch) * ncs;  // first real
+        }
+        colbase[j] = cb;
+    }
+    __syncthreads();
+    int cbs[16];  // this wave's staging columns 16 w .. 16 w + 15
+#pragma unroll
+    for (int c2 = 0; c2 < 16; ++c2)
+        cbs[c2] = colbase[16 * w + c2];
+    const double *Mr = reinterpret_cast<const double *>(M);
     const double *Au = ops + (int64_t)u * nrt_s * k4_s * 64 + lane;
-    for (int g0 = 0; g0 < nct; g0 += NT) {
-        const int gt = min(NT, nct - g0);
-        const int c0 = 16 * g0, cn = min(16 * gt, ncol - c0);
-        __syncthreads();  // the previous pass has read Bs
-        if ((int)threadIdx.x < 16 * NT) {
-            const int j = threadIdx.x;
-            int cb = -1;
-            if (j < cn) {
-                const int col = c0 + j, pl = col / NCH, ch = col - pl * NCH;
-                cb = (pairs[2 * pair_sorted[pb + pl] + 1] * NCH + ch) * ncs;  // in complex units
-            }
-            colbase[j] = cb;
-        }
-        __syncthreads();
-        // wave w stages columns w CPW .. + CPW - 1 (Dp contiguous reals each),
-        // all of its loads issued before the LDS writes; reads past the chunk
-        // or past Dp go to a valid address and are replaced by zero
-        {
-            constexpr int CPW = 16 * NT / 4;
-            int cbs[CPW];
+    for (int rb0 = 0; rb0 < nrt; rb0 += nwave * RB) {  // the same trip count for every wave
+        const double *At[RB];
 #pragma unroll
-            for (int c2 = 0; c2 < CPW; ++c2)
-                cbs[c2] = colbase[w * CPW + c2];
-            for (int k = lane; k < Kp; k += 64) {
-                const int kc = min(k, Dp - 1);
-                double v[CPW];
+        for (int i = 0; i < RB; ++i)
+            At[i] = Au + (int64_t)min(rb0 + w + nwave * i, nrt - 1) * k4_s * 64;
+        acc_t acc[RB][NT];
 #pragma unroll
-                for (int c2 = 0; c2 < CPW; ++c2)
-                    v[c2] = reinterpret_cast<const double *>(M + max(cbs[c2], 0))[kc];
+        for (int i = 0; i < RB; ++i)
 #pragma unroll
-                for (int c2 = 0; c2 < CPW; ++c2)
-                    Bs[k * ldb + w * CPW + c2] = (cbs[c2] >= 0 && k < Dp) ? v[c2] : 0.0;
-            }
-        }
-        __syncthreads();
-        for (int rb = w; rb < nrt; rb += nwave * RB) {
-            acc_t acc[RB][NT];
+            for (int ct = 0; ct < NT; ++ct)
+                acc[i][ct] = acc_t{0, 0, 0, 0};
+        double ring[PF][RB];
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
 #pragma unroll
             for (int i = 0; i < RB; ++i)
+                ring[j][i] = At[i][(int64_t)min(j, nsteps - 1) * 64];
+        for (int w0 = 0; w0 < nsteps; w0 += WS) {
+            __syncthreads();  // the previous window has been read
+            {
+                const int k = 4 * w0 + lane, kc = min(k, Dp - 1);
+                double v[16];
 #pragma unroll
-                for (int ct = 0; ct < NT; ++ct)
-                    acc[i][ct] = acc_t{0, 0, 0, 0};
-            // row tiles past nrt repeat the last one and are not stored; rows
-            // and inputs past Dp meet zero inputs or are not stored, so the
-            // loads need no guard (a guarded load would wait on each read).
-            // The operator values of the next PF steps are kept in flight.
-            constexpr int PF = 8;
-            const int nsteps = Kp >> 2;
-            const double *At[RB];
+                for (int c2 = 0; c2 < 16; ++c2)
+                    v[c2] = Mr[max(cbs[c2], 0) + kc];
 #pragma unroll
-            for (int i = 0; i < RB; ++i)
-                At[i] = Au + (int64_t)min(rb + i * nwave, nrt - 1) * k4_s * 64;
-            double ring[PF][RB];
+                for (int c2 = 0; c2 < 16; ++c2)
+                    Bs[lane * ldb + 16 * w + c2] = (cbs[c2] >= 0 && k < Dp) ? v[c2] : 0.0;
+            }
+            __syncthreads();
+            for (int j0 = 0; j0 < WS; j0 += PF) {
 #pragma unroll
-            for (int j = 0; j < PF; ++j)
+                for (int j = 0; j < PF; ++j) {
+                    const int st = w0 + j0 + j;
+                    const double *brow = Bs + (4 * (j0 + j) + lk) * ldb + li;
 #pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    ring[j][i] = At[i][(int64_t)min(j, nsteps - 1) * 64];
-            // full groups of PF steps carry no branch, so that the wait for a
-            // ring slot covers only its own read; the remainder follows
-            auto step = [&](int st, double *slot) {
-                const double *brow = Bs + (4 * st + lk) * ldb + li;
-                double bv[NT];
+                    for (int ct = 0; ct < NT; ++ct) {
+                        if (ct < nct) {
+                            const double bv = brow[16 * ct];
 #pragma unroll
-                for (int ct = 0; ct < NT; ++ct)
-                    bv[ct] = brow[16 * ct];
-#pragma unroll
-                for (int ct = 0; ct < NT; ++ct)
+                            for (int i = 0; i < RB; ++i)
+                                acc[i][ct] = mfma_16x16x4(ring[j][i], bv, acc[i][ct]);
+                        }
+                    }
+                    const int sn = min(st + PF, nsteps - 1);
 #pragma unroll
                     for (int i = 0; i < RB; ++i)
-                        acc[i][ct] = mfma_16x16x4(slot[i], bv[ct], acc[i][ct]);
-                const int sn = min(st + PF, nsteps - 1);
-#pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    slot[i] = At[i][(int64_t)sn * 64];
-            };
-            const int nfull = nsteps - nsteps % PF;
-            for (int s0 = 0; s0 < nfull; s0 += PF) {
-#pragma unroll
-                for (int j = 0; j < PF; ++j)
-                    step(s0 + j, ring[j]);
+                        ring[j][i] = At[i][(int64_t)sn * 64];
+                }
             }
+        }
 #pragma unroll
-            for (int j = 0; j < PF; ++j)
-                if (nfull + j < nsteps)
-                    step(nfull + j, ring[j]);
+        for (int i = 0; i < RB; ++i) {
+            const int rt = rb0 + w + nwave * i;
+            if (rt >= nrt)
+                continue;
 #pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                const int rt = rb + i * nwave;
-                if (rt >= nrt)
+            for (int ct = 0; ct < NT; ++ct) {
+                const int col = ct * 16 + li;
+                if (ct >= nct || col >= ncol)
                     continue;
+                const int pl = col / NCH, ch = col - pl * NCH;
+                double *dst = reinterpret_cast<double *>(Y + ((int64_t)pair_sorted[pb + pl] * NCH + ch) * nc);
 #pragma unroll
-                for (int ct = 0; ct < NT; ++ct) {
-                    const int col = c0 + ct * 16 + li;
-                    if (ct >= gt || col >= ncol)
-                        continue;
-                    const int pl = col / NCH, ch = col - pl * NCH;
-                    double *dst = reinterpret_cast<double *>(Y + ((int64_t)pair_sorted[pb + pl] * NCH + ch) * nc);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = rt * 16 + 4 * v + lk;  // FP64 output layout
-                        if (row < Dp)
-                            dst[row] = acc[i][ct][v];
-                    }
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rt * 16 + 4 * v + lk;  // FP64 output layout
+                    if (row < Dp)
+                        dst[row] = acc[i][ct][v];
                 }
             }
         }
     }
-}
-
-// LDS of k_m2l_stored with NT column tiles per pass
-inline size_t m2l_stored_shm(int p, int nt)
-{
-    const size_t Kp = (2 * ncoef(p) + 3) & ~3;
-    return sizeof(double) * Kp * (16 * nt + 1) + sizeof(int) * 16 * nt;
 }
 
 template <typename R> size_t m2l_mfma_shm(int p)
@@ -1626,15 +1602,9 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
                 k_m2l_mfma<R, NCH><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), st>>>(
                     p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
             } else if (P.ops64) {
-                // two column tiles per pass while they fit in 64 KB of LDS (p <= 13)
-                if (m2l_stored_shm(p, 2) <= 65536)
-                    k_m2l_stored<NCH, 2><<<P.n_chunks, 256, m2l_stored_shm(p, 2), st>>>(
-                        p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin, P.chunk_trans, P.pair_sorted, T.m2l_pairs,
-                        P.ops64, M, Y);
-                else
-                    k_m2l_stored<NCH, 1><<<P.n_chunks, 256, m2l_stored_shm(p, 1), st>>>(
-                        p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin, P.chunk_trans, P.pair_sorted, T.m2l_pairs,
-                        P.ops64, M, Y);
+                k_m2l_stored<NCH><<<P.n_chunks, 256, 0, st>>>(p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin,
+                                                               P.chunk_trans, P.pair_sorted, T.m2l_pairs, P.ops64,
+                                                               M, Y);
             } else {
                 constexpr int PB = NCH == 1 ? 8 : 2;
                 const size_t shm = sizeof(cplx<R>) * (size_t)(2 * p + 1) * (2 * p + 1);
