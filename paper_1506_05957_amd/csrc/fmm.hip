@@ -833,7 +833,7 @@ __global__ __launch_bounds__(256) void k_m2l_opgen(int pmax, int q_tab, int nrt,
 
 // Pass 1 in FP64 from the stored operators.  Block = chunk (at most 64
 // columns: pairs x channels, one key); wave w runs row tiles w, w + 4, w + 8
-// of the operator (three products in flight) with an eight-step ring of
+// of the operator (three products in flight) with a four-step ring of
 // operator reads (one coalesced 512-byte read per wave and step, never
 // guarded: a guarded read would wait on itself), so each operator value is
 // read once per chunk.  The chunk's inputs are staged in LDS one window of
@@ -846,7 +846,7 @@ __global__ __launch_bounds__(256) void k_m2l_opgen(int pmax, int q_tab, int nrt,
 constexpr int M2LS_RB = 3;   // row tiles per wave
 constexpr int M2LS_WS = 16;  // steps per staged window
 template <int NCH>
-__global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, int k4_s,
+__global__ __launch_bounds__(256, 3) void k_m2l_stored(int p, int ncs, int nrt_s, int k4_s,
                                                     const int32_t *__restrict__ chunk_begin,
                                                     const int32_t *__restrict__ chunk_trans,
                                                     const int32_t *__restrict__ pair_sorted,
@@ -854,7 +854,7 @@ __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, i
                                                     const cplx<double> *__restrict__ M, cplx<double> *__restrict__ Y)
 {
     typedef Acc4<double>::type acc_t;
-    constexpr int RB = M2LS_RB, NT = 4, WS = M2LS_WS, PF = 8, ldb = 16 * NT + 1;
+    constexpr int RB = M2LS_RB, NT = 4, WS = M2LS_WS, PF = 4, ldb = 16 * NT + 1;
     constexpr int nwave = 4;  // launched with 256 threads
     static_assert(WS % PF == 0 && 4 * WS == 64, "a window is 64 inputs, whole ring groups");
     __shared__ double Bs[4 * WS * ldb];
@@ -875,10 +875,6 @@ __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, i
         colbase[j] = cb;
     }
     __syncthreads();
-    int cbs[16];  // this wave's staging columns 16 w .. 16 w + 15
-#pragma unroll
-    for (int c2 = 0; c2 < 16; ++c2)
-        cbs[c2] = colbase[16 * w + c2];
     const double *Mr = reinterpret_cast<const double *>(M);
     const double *Au = ops + (int64_t)u * nrt_s * k4_s * 64 + lane;
     for (int rb0 = 0; rb0 < nrt; rb0 += nwave * RB) {  // the same trip count for every wave
@@ -900,15 +896,21 @@ __global__ __launch_bounds__(256) void k_m2l_stored(int p, int ncs, int nrt_s, i
                 ring[j][i] = At[i][(int64_t)min(j, nsteps - 1) * 64];
         for (int w0 = 0; w0 < nsteps; w0 += WS) {
             __syncthreads();  // the previous window has been read
-            {
-                const int k = 4 * w0 + lane, kc = min(k, Dp - 1);
-                double v[16];
+            // wave w stages columns 16 w .. 16 w + 15, eight reads at a time
+            const int k = 4 * w0 + lane, kc = min(k, Dp - 1);
 #pragma unroll
-                for (int c2 = 0; c2 < 16; ++c2)
-                    v[c2] = Mr[max(cbs[c2], 0) + kc];
+            for (int h = 0; h < 2; ++h) {
+                int cb[8];
+                double v[8];
 #pragma unroll
-                for (int c2 = 0; c2 < 16; ++c2)
-                    Bs[lane * ldb + 16 * w + c2] = (cbs[c2] >= 0 && k < Dp) ? v[c2] : 0.0;
+                for (int c2 = 0; c2 < 8; ++c2)
+                    cb[c2] = colbase[16 * w + 8 * h + c2];
+#pragma unroll
+                for (int c2 = 0; c2 < 8; ++c2)
+                    v[c2] = Mr[max(cb[c2], 0) + kc];
+#pragma unroll
+                for (int c2 = 0; c2 < 8; ++c2)
+                    Bs[lane * ldb + 16 * w + 8 * h + c2] = (cb[c2] >= 0 && k < Dp) ? v[c2] : 0.0;
             }
             __syncthreads();
             for (int j0 = 0; j0 < WS; j0 += PF) {
