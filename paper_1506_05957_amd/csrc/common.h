@@ -245,10 +245,12 @@ struct fmmbem_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool near_pending = false;  // a near field launched on the side stream that no stream has joined yet
-    // near field (charges + P2P) already launched for this input and precision
-    // ahead of the mat-vec that will use it (see prefetch_near)
+    // charges already launched for this input and precision ahead of the
+    // mat-vec that will use them, with the upward pass of order spec_up_p
+    // (-1: none; see prefetch_charges)
     const double *spec_x = nullptr;
     int spec_prec = -1;
+    int spec_up_p = -1;
 };
 
 namespace fmmbem {
@@ -304,9 +306,12 @@ void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream
 void build_correction(fmmbem_ctx *ctx, hipStream_t st);
 void build_translations(fmmbem_ctx *ctx, hipStream_t st);
 void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hipStream_t st);
-// launch the near field (charges + P2P) of a mat-vec on x at precision prec
-// ahead of time; the next run_matvec with the same x and prec uses it
-void prefetch_near(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
+// launch the charges of a mat-vec on x at precision prec ahead of time (the
+// next run_matvec with the same x and prec uses them and starts the near field
+// from them), then optionally the upward pass (P2M, M2M) of order p_up, whose
+// multipoles that run_matvec uses when its order is <= p_up
+void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
+void prefetch_up(fmmbem_ctx *ctx, int prec, int p_up, hipStream_t st);
 // stored near field (nearfield.hip): assemble at build; one product on
 // stream st of the input in sorted order (nearm.xs, written by the charges)
 void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st);

@@ -655,10 +655,12 @@ __global__ void k_m2m_sum(int p, int ncs, int npar, const int32_t *__restrict__ 
 //   Re L += a S.re - b D.im,   Im L += a S.im + b D.re,
 // times (-1)^k 2^(-eT (k+1)) 2^(-eS n).  Rows of the real operator A are
 // (k, l, re/im), inputs (n, m, re/im), columns (pair, channel): Y = A X.
-// Wave w takes the 16-row tiles w, w + 4, ...; each lane generates its
-// element of A for every 16x16x4 step from the key's table in LDS, and the
-// step runs all (at most 4) column tiles of the chunk, whose inputs the lanes
-// load from the multipole array (L2-resident).  Lane layout
+// The chunk's inputs (at most 64 columns) are staged in LDS in windows of 64,
+// every load issued unguarded at a clamped address and several at a time;
+// wave w takes the 16-row tiles w, w + nwave, ... (accumulators held across
+// the windows); each lane generates its element of A for every 16x16x4 step
+// from the key's table in LDS, branch free, and the step runs all (at most 4)
+// column tiles of the chunk.  Lane layout
 // (both precisions): A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; the
 // result D[i][j] is element i % 4 of lane j + 16 (i / 4) in FP32 and element
 // i / 4 of lane j + 16 (i % 4) in FP64.  The Stokes
@@ -676,7 +678,7 @@ __device__ __forceinline__ Acc4<float>::type mfma_16x16x4(float a, float b, Acc4
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <typename R, int NCH>
+template <typename R, int NCH, int RT>
 __global__ __launch_bounds__(256) void k_m2l_mfma(int p, int ncs, int q_tab, const int32_t *__restrict__ chunk_begin,
                                                   const int32_t *__restrict__ chunk_trans,
                                                   const uint64_t *__restrict__ trans_key,
@@ -685,16 +687,23 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(int p, int ncs, int q_tab, con
                                                   const cplx<R> *__restrict__ M, cplx<R> *__restrict__ Y)
 {
     typedef typename Acc4<R>::type acc_t;
-    constexpr int NT = 4;  // column tiles of a chunk (at most 64 columns)
+    constexpr int NT = 4;   // column tiles of a chunk (at most 64 columns)
+    constexpr int KW = 64;  // inputs per staging window
+    constexpr int U = 8;    // staging loads issued together per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int q = 2 * p;
     const int fq = (q + 1) * (q + 1), nc = ncoef(p), Dp = 2 * nc, Kp = (Dp + 3) & ~3, nrt = (Dp + 15) / 16;
-    cplx<R> *It = reinterpret_cast<cplx<R> *>(smem_raw);    // [(q+1)^2]
-    uint16_t *qnm = reinterpret_cast<uint16_t *>(It + fq);  // [nc]: n | m << 8
+    const int ldb = min(Kp, KW) + 1;
+    int64_t *colsrc = reinterpret_cast<int64_t *>(smem_raw);  // [64]: first real of the column's input, or -1
+    int64_t *coldst = colsrc + 64;                             // [64]: first real of the column's result
+    cplx<R> *It = reinterpret_cast<cplx<R> *>(coldst + 64);    // [(q+1)^2]
+    R *Bs = reinterpret_cast<R *>(It + fq);                    // [64][ldb]: a window of the chunk's inputs
+    uint16_t *qnm = reinterpret_cast<uint16_t *>(Bs + 64 * ldb);  // [nc]: n | m << 8
     const int c = blockIdx.x;
     const int u = chunk_trans[c], pb = chunk_begin[c], pe = chunk_begin[c + 1];
     const uint64_t key = trans_key[u];
     const int eT = (int)((key >> 48) & 63), eS = (int)((key >> 54) & 63);
+    const int ncol = (pe - pb) * NCH, nct = (ncol + 15) / 16;  // nct <= NT
     const cplx<R> *tab = table + (int64_t)u * (q_tab + 1) * (q_tab + 1);
     for (int t = threadIdx.x; t < fq; t += blockDim.x)
         It[t] = tab[t];
@@ -703,82 +712,110 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(int p, int ncs, int q_tab, con
         idx_to_nm(t, n, m);
         qnm[t] = (uint16_t)(n | (m << 8));
     }
-    __syncthreads();
-    const int ncol = (pe - pb) * NCH, nct = (ncol + 15) / 16;  // nct <= NT
+    if (threadIdx.x < 64) {
+        const int col = threadIdx.x;
+        int64_t s = -1, d = 0;
+        if (col < ncol) {
+            const int pl = col / NCH, ch = col - pl * NCH;
+            const int pr = pair_sorted[pb + pl];
+            const int S = pairs[2 * pr + 1];
+            s = 2 * (((int64_t)S * NCH + ch) * ncs);
+            d = 2 * (((int64_t)pr * NCH + ch) * nc);
+        }
+        colsrc[col] = s;
+        coldst[col] = d;
+    }
     const int nwave = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int pin = lk & 1;  // re/im part of this lane's input (fixed: steps advance k by 4)
-    // this lane's B column of each tile: the multipole coefficients of a source box, as reals
-    const R *bcol[NT];
+    const int nrw = (nrt - w + nwave - 1) / nwave;  // row tiles of this wave, <= RT (checked at launch)
+    const R *Mr = reinterpret_cast<const R *>(M);
+    acc_t acc[RT][NT];
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) {
-        const int col = ct * 16 + li;
-        bcol[ct] = nullptr;
-        if (col < ncol) {
-            const int pl = col / NCH, ch = col - pl * NCH;
-            const int S = pairs[2 * pair_sorted[pb + pl] + 1];
-            bcol[ct] = reinterpret_cast<const R *>(M + ((int64_t)S * NCH + ch) * ncs);
-        }
-    }
-    for (int rt = w; rt < nrt; rt += nwave) {
-        const int r = rt * 16 + li;  // operator row of this lane's A elements
-        const bool rv = r < Dp;
-        int k = 0, l = 0;
-        if (rv) {
-            const int e = qnm[r >> 1];
-            k = e & 0xff;
-            l = e >> 8;
-        }
-        const int po = r & 1;
-        // sign of the whole entry and the component (re/im) it takes from P and Q
-        const R sall = (po == 0 && pin == 1) ? R(-1) : R(1);
-        const bool take_im = (po ^ pin) != 0;
-        const R f = rv ? sall * (R)ldexp((k & 1) ? -1.0 : 1.0, -eT * (k + 1)) : R(0);
-        acc_t acc[NT];
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct)
-            acc[ct] = acc_t{0, 0, 0, 0};
-#pragma unroll 2
-        for (int q0 = 0; q0 < Kp; q0 += 4) {
-            const int qi = q0 + lk;
-            const bool qv = qi < Dp;
-            R a = 0;
-            if (rv && qv) {
-                const int e = qnm[qi >> 1];
-                const int n = e & 0xff, m = e >> 8;
-                const cplx<R> *row = It + (n + k) * (n + k + 1);  // I_{n+k}^{0}
-                const cplx<R> P = row[l + m];
-                R pc = take_im ? P.im : P.re;
-                if (m > 0) {
-                    const cplx<R> Q = row[l - m];
-                    const R qc = take_im ? Q.im : Q.re;
-                    // (-1)^m from Q, and + for S (pin 0) or - for D (pin 1)
-                    pc += (((m & 1) != 0) != (pin != 0)) ? -qc : qc;
-                }
-                a = (R)ldexp(f * pc, -eS * n);
-            }
+            acc[i][ct] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < Kp; k0 += KW) {
+        const int kw = min(KW, Kp - k0);
+        __syncthreads();  // the column offsets written, the previous window read
+        // stage inputs k0 .. k0 + kw - 1 of the chunk's column tiles, zero past Dp
+        // and past the last column: lane = (column of the step, input), the
+        // waves take steps of cpw columns; every load unguarded (clamped), U at a time
+        {
+            const int cpw = KW / kw, sub = lane / kw, kk = lane - sub * kw, nstc = nct * 16;
+            const int cstep = nwave * cpw;
+            const bool lv = sub < cpw;
+            const int kc = min(k0 + kk, Dp - 1);
+            for (int cb = w * cpw; cb < nstc; cb += U * cstep) {  // wave-uniform
+                R v[U];
 #pragma unroll
-            for (int ct = 0; ct < NT; ++ct) {
-                if (ct < nct) {
-                    const R b = (qv && bcol[ct]) ? bcol[ct][qi] : R(0);
-                    acc[ct] = mfma_16x16x4(a, b, acc[ct]);
+                for (int j = 0; j < U; ++j) {
+                    const int64_t s = colsrc[min(cb + sub + j * cstep, nstc - 1)];
+                    v[j] = Mr[s < 0 ? 0 : s + kc];
+                }
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    const int col = cb + sub + j * cstep;
+                    if (lv && col < nstc)
+                        Bs[col * ldb + kk] = (colsrc[col] >= 0 && k0 + kk < Dp) ? v[j] : R(0);
                 }
             }
         }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            if (i >= nrw)
+                break;
+            const int r = (w + i * nwave) * 16 + li;  // operator row of this lane's A elements
+            const int er = qnm[min(r, Dp - 1) >> 1];
+            const int k = er & 0xff, l = er >> 8;
+            const int po = r & 1;
+            // sign of the whole entry and the component (re/im) it takes from P and Q
+            const R sall = (po == 0 && pin == 1) ? R(-1) : R(1);
+            const bool take_im = (po ^ pin) != 0;
+            const R f = r < Dp ? sall * (R)ldexp((k & 1) ? -1.0 : 1.0, -eT * (k + 1)) : R(0);
+            const R *bl = Bs + li * ldb + lk;
+#pragma unroll 2
+            for (int s = 0; s < kw; s += 4) {
+                const int qi = k0 + s + lk;
+                const int e = qnm[min(qi, Dp - 1) >> 1];
+                const int n = e & 0xff, m = e >> 8;
+                const cplx<R> *row = It + (n + k) * (n + k + 1);  // I_{n+k}^{0}
+                const cplx<R> P = row[l + m], Q = row[l - m];
+                const R pc = take_im ? P.im : P.re, qc = take_im ? Q.im : Q.re;
+                // (-1)^m from Q, and + for S (pin 0) or - for D (pin 1); no Q for m = 0
+                const R qs = m == 0 ? R(0) : ((((m & 1) != 0) != (pin != 0)) ? -qc : qc);
+                const R a = qi < Dp ? (R)ldexp(f * (pc + qs), -eS * n) : R(0);
+                R b[NT];
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+                    b[ct] = bl[ct * 16 * ldb + s];
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+                    if (ct < nct)
+                        acc[i][ct] = mfma_16x16x4(a, b[ct], acc[i][ct]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        if (i >= nrw)
+            break;
+        const int rt = w + i * nwave;
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
             const int col = ct * 16 + li;
             if (ct >= nct || col >= ncol)
                 continue;
-            const int pl = col / NCH, ch = col - pl * NCH;
-            R *dst = reinterpret_cast<R *>(Y + ((int64_t)pair_sorted[pb + pl] * NCH + ch) * nc);
+            R *dst = reinterpret_cast<R *>(Y) + coldst[col];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 // output element v of this lane: row 4 lk + v (FP32 form), 4 v + lk (FP64 form)
                 const int row = rt * 16 + (sizeof(R) == 8 ? 4 * v + lk : 4 * lk + v);
                 if (row < Dp)
-                    dst[row] = acc[ct][v];
+                    dst[row] = acc[i][ct][v];
             }
         }
     }
@@ -959,8 +996,9 @@ __global__ __launch_bounds__(256, 3) void k_m2l_stored(int p, int ncs, int nrt_s
 
 template <typename R> size_t m2l_mfma_shm(int p)
 {
-    const int q = 2 * p;
-    return sizeof(cplx<R>) * (size_t)(q + 1) * (q + 1) + sizeof(uint16_t) * (size_t)ncoef(p);
+    const int q = 2 * p, Kp = (2 * ncoef(p) + 3) & ~3;
+    return 2 * 64 * sizeof(int64_t) + sizeof(cplx<R>) * (size_t)(q + 1) * (q + 1) +
+           sizeof(R) * 64 * (size_t)(std::min(Kp, 64) + 1) + sizeof(uint16_t) * (size_t)ncoef(p);
 }
 
 // The same pass 1 on the vector units, used for FP64 (where the generated
@@ -1470,11 +1508,11 @@ __global__ void k_combine(int64_t nt, CombineArgs ca, const double *__restrict__
         combine_target<KIND>(ca, i, yfar + NQ * i);
 }
 
-// charges of this mat-vec on st, then P2P on the side stream
+// charges of this mat-vec on st (for P2M, and the sorted input of the stored
+// near field); ev_fork marks them
 template <typename R, int KIND>
-void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
+void launch_charges(fmmbem_ctx *ctx, const double *x, hipStream_t st)
 {
-    constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     constexpr bool VS = vec_src<KIND>();
     constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
     Tree &T = ctx->tree;
@@ -1490,8 +1528,24 @@ void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
                                                           ctx->nearm.v64 ? ctx->nearm.xs : nullptr);
     FB_HIP(hipGetLastError());
     stage_end(ctx, SO + 4, st, ev);
-
     FB_HIP(hipEventRecord(ctx->ev_fork, st));
+}
+
+// the near field (P2P, or the stored near-field product) on the side stream
+// once the charges marked by ev_fork are written; ev_join marks its end
+template <typename R, int KIND>
+void launch_side_near(fmmbem_ctx *ctx)
+{
+    constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
+    constexpr bool VS = vec_src<KIND>();
+    constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
+    Tree &T = ctx->tree;
+    Geometry &G = ctx->geo;
+    const int64_t nt = ctx->nt;
+    Src<R, VS> *src = static_cast<Src<R, VS> *>(ctx->charges);
+    hipEvent_t ev;
+    // a wait on an event that has completed costs the host next to nothing,
+    // one on a pending event about as much as several kernel launches
     FB_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
     stage_begin(ctx, SO + 0, ctx->side, &ev);
     if (ctx->nearm.v64) {
@@ -1513,84 +1567,111 @@ void launch_near(fmmbem_ctx *ctx, const double *x, hipStream_t st)
     ctx->near_pending = true;
 }
 
-// The far field of order p on st, P2M through L2P, from the charges that the
-// near-field launch wrote before it; st joins the side stream before L2P,
-// which combines far and near field into y.  Without a far field: y_far = 0,
-// join and combine.
+// The upward pass of order p on st: P2M of every leaf, then M2M level by level
+// (deepest first), from the charges that the near-field launch wrote before
+// it.  Coefficient (n, m) of every multipole does not depend on the order of
+// the pass (P2M computes each order on its own; M2M takes a parent's order n
+// from children's orders <= n only), so a pass of order p serves every later
+// M2L of order <= p.
 template <typename R, int KIND>
-void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
+void up_pass(fmmbem_ctx *ctx, int p, hipStream_t st)
 {
     constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     constexpr int NCH = STOKES ? 4 : 1;
     constexpr bool VS = vec_src<KIND>();
     constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
     Tree &T = ctx->tree;
+    const int ncs = ncoef(ctx->prm.p_max);
+    const double side = T.cube[3];
+    Src<R, VS> *src = static_cast<Src<R, VS> *>(ctx->charges);
+    cplx<R> *M = static_cast<cplx<R> *>(ctx->M);
+    hipEvent_t ev;
+    stage_begin(ctx, SO + 2, st, &ev);
+    {
+        const int nsl = 256 / (p + 1);
+        const size_t shm = sizeof(cplx<R>) * (size_t)nsl * ncoef(p) + sizeof(Src<R, VS>) * P2M_TILE;
+        if constexpr (KIND == FMMBEM_LAPLACE_DL) {
+            if (p <= 4)
+                k_p2m_dipole<R, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (p <= 8)
+                k_p2m_dipole<R, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (p <= 12)
+                k_p2m_dipole<R, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (p <= 16)
+                k_p2m_dipole<R, 16><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else
+                k_p2m_dipole<R, 20><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+        } else {
+            if (p <= 4)
+                k_p2m<R, NCH, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (p <= 8)
+                k_p2m<R, NCH, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (p <= 12)
+                k_p2m<R, NCH, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (p <= 16)
+                k_p2m<R, NCH, 16><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else
+                k_p2m<R, NCH, 20><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+        }
+        FB_HIP(hipGetLastError());
+    }
+    const M2LPlan &P = ctx->m2l;
+    const R *m2m_op;
+    if constexpr (sizeof(R) == 8)
+        m2m_op = P.m2m64;
+    else
+        m2m_op = P.m2m32;
+    const size_t op_shm = sizeof(R) * 16 * std::max<size_t>(2 * (size_t)ncoef(p), 3 * 64);
+    const int row_chunks = (2 * ncoef(p) + 63) / 64;
+    cplx<R> *Z = static_cast<cplx<R> *>(P.Z);
+    // children of level l into parents of level l - 1, deepest first; levels
+    // above the coarsest M2L source are never read
+    for (int l = T.nlevels - 1; l >= 1 && l - 1 >= P.lmin_src; --l) {
+        const int t0 = P.tile_begin[l], ntile = P.tile_begin[l + 1] - t0;
+        const int q0 = P.par_begin[l - 1], npar = P.par_begin[l] - q0;
+        if (ntile == 0 || npar == 0)
+            continue;
+        k_octant_apply<R, NCH, false><<<dim3(ntile, row_chunks), 256, op_shm, st>>>(p, ncs, P.op_dim, m2m_op, P.tiles, t0,
+                                                                  P.level_list, T.box_i, T.box_r, M, Z);
+        FB_HIP(hipGetLastError());
+        k_m2m_sum<R, NCH><<<grid_for((int64_t)npar * NCH * ncoef(p), 256), 256, 0, st>>>(
+            p, ncs, npar, P.parents + q0, T.box_i, Z, M);
+        FB_HIP(hipGetLastError());
+    }
+    stage_end(ctx, SO + 2, st, ev);
+}
+
+// The far field of order p on st, P2M through L2P (without the upward pass
+// when have_up: multipoles of order >= p already computed on st), from the
+// charges that the near-field launch wrote before it; st joins the side stream before L2P,
+// which combines far and near field into y.  Without a far field: y_far = 0,
+// join and combine.
+template <typename R, int KIND>
+void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bool have_up)
+{
+    constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
+    constexpr int NCH = STOKES ? 4 : 1;
+    constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
+    Tree &T = ctx->tree;
     Geometry &G = ctx->geo;
     const int64_t nt = ctx->nt;
     const int ncs = ncoef(ctx->prm.p_max);
     const double side = T.cube[3];
-    Src<R, VS> *src = static_cast<Src<R, VS> *>(ctx->charges);
     cplx<R> *M = static_cast<cplx<R> *>(ctx->M);
     cplx<R> *L = static_cast<cplx<R> *>(ctx->L);
     hipEvent_t ev;
 
     if (T.n_m2l > 0) {
-        stage_begin(ctx, SO + 2, st, &ev);
-        {
-            const int nsl = 256 / (p + 1);
-            const size_t shm = sizeof(cplx<R>) * (size_t)nsl * ncoef(p) + sizeof(Src<R, VS>) * P2M_TILE;
-            if constexpr (KIND == FMMBEM_LAPLACE_DL) {
-                if (p <= 4)
-                    k_p2m_dipole<R, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-                else if (p <= 8)
-                    k_p2m_dipole<R, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-                else if (p <= 12)
-                    k_p2m_dipole<R, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-                else if (p <= 16)
-                    k_p2m_dipole<R, 16><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-                else
-                    k_p2m_dipole<R, 20><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-            } else {
-                if (p <= 4)
-                    k_p2m<R, NCH, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-                else if (p <= 8)
-                    k_p2m<R, NCH, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-                else if (p <= 12)
-                    k_p2m<R, NCH, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-                else if (p <= 16)
-                    k_p2m<R, NCH, 16><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-                else
-                    k_p2m<R, NCH, 20><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-            }
-            FB_HIP(hipGetLastError());
-        }
+        if (!have_up)
+            up_pass<R, KIND>(ctx, p, st);
         const M2LPlan &P = ctx->m2l;
-        const R *m2m_op, *l2l_op;
-        if constexpr (sizeof(R) == 8) {
-            m2m_op = P.m2m64;
+        const R *l2l_op;
+        if constexpr (sizeof(R) == 8)
             l2l_op = P.l2l64;
-        } else {
-            m2m_op = P.m2m32;
+        else
             l2l_op = P.l2l32;
-        }
         const size_t op_shm = sizeof(R) * 16 * std::max<size_t>(2 * (size_t)ncoef(p), 3 * 64);
         const int row_chunks = (2 * ncoef(p) + 63) / 64;
-        cplx<R> *Z = static_cast<cplx<R> *>(P.Z);
-        // children of level l into parents of level l - 1, deepest first; levels
-        // above the coarsest M2L source are never read
-        for (int l = T.nlevels - 1; l >= 1 && l - 1 >= P.lmin_src; --l) {
-            const int t0 = P.tile_begin[l], ntile = P.tile_begin[l + 1] - t0;
-            const int q0 = P.par_begin[l - 1], npar = P.par_begin[l] - q0;
-            if (ntile == 0 || npar == 0)
-                continue;
-            k_octant_apply<R, NCH, false><<<dim3(ntile, row_chunks), 256, op_shm, st>>>(p, ncs, P.op_dim, m2m_op, P.tiles, t0,
-                                                                      P.level_list, T.box_i, T.box_r, M, Z);
-            FB_HIP(hipGetLastError());
-            k_m2m_sum<R, NCH><<<grid_for((int64_t)npar * NCH * ncoef(p), 256), 256, 0, st>>>(
-                p, ncs, npar, P.parents + q0, T.box_i, Z, M);
-            FB_HIP(hipGetLastError());
-        }
-        stage_end(ctx, SO + 2, st, ev);
 
         stage_begin(ctx, SO + 1, st, &ev);
         {
@@ -1601,8 +1682,17 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
                 table = P.table32;
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
             if constexpr (sizeof(R) == 4) {
-                k_m2l_mfma<R, NCH><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), st>>>(
-                    p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
+                // one wave per 16-row tile up to four tiles (the low orders of the
+                // relaxed iterations: no wave idles, one tile's accumulators per
+                // wave), else four waves of up to four tiles each
+                const int nrt = (2 * ncoef(p) + 15) / 16;
+                FB_REQUIRE(nrt <= 16, FMMBEM_EINVAL, "FP32 M2L beyond its order limit");
+                if (nrt <= 4)
+                    k_m2l_mfma<R, NCH, 1><<<P.n_chunks, 64 * nrt, m2l_mfma_shm<R>(p), st>>>(
+                        p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
+                else
+                    k_m2l_mfma<R, NCH, 4><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), st>>>(
+                        p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
             } else if (P.ops64) {
                 k_m2l_stored<NCH><<<P.n_chunks, 256, 0, st>>>(p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin,
                                                                P.chunk_trans, P.pair_sorted, T.m2l_pairs, P.ops64,
@@ -1653,72 +1743,131 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st)
     }
 }
 
-void far_dispatch(fmmbem_ctx *ctx, int p, int prec, const CombineArgs &ca, hipStream_t st)
+void far_dispatch(fmmbem_ctx *ctx, int p, int prec, const CombineArgs &ca, hipStream_t st, bool have_up)
 {
     const int kind = ctx->kernel;
     if (prec == FMMBEM_FP64) {
         if (kind == FMMBEM_STOKES_SL)
-            far_chain<double, FMMBEM_STOKES_SL>(ctx, p, ca, st);
+            far_chain<double, FMMBEM_STOKES_SL>(ctx, p, ca, st, have_up);
         else if (kind == FMMBEM_LAPLACE_DL)
-            far_chain<double, FMMBEM_LAPLACE_DL>(ctx, p, ca, st);
+            far_chain<double, FMMBEM_LAPLACE_DL>(ctx, p, ca, st, have_up);
         else
-            far_chain<double, FMMBEM_LAPLACE_SL>(ctx, p, ca, st);
+            far_chain<double, FMMBEM_LAPLACE_SL>(ctx, p, ca, st, have_up);
     } else {
         if (kind == FMMBEM_STOKES_SL)
-            far_chain<float, FMMBEM_STOKES_SL>(ctx, p, ca, st);
+            far_chain<float, FMMBEM_STOKES_SL>(ctx, p, ca, st, have_up);
         else if (kind == FMMBEM_LAPLACE_DL)
-            far_chain<float, FMMBEM_LAPLACE_DL>(ctx, p, ca, st);
+            far_chain<float, FMMBEM_LAPLACE_DL>(ctx, p, ca, st, have_up);
         else
-            far_chain<float, FMMBEM_LAPLACE_SL>(ctx, p, ca, st);
+            far_chain<float, FMMBEM_LAPLACE_SL>(ctx, p, ca, st, have_up);
     }
 }
 
-void near_dispatch(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
+void up_dispatch(fmmbem_ctx *ctx, int p, int prec, hipStream_t st)
 {
     const int kind = ctx->kernel;
     if (prec == FMMBEM_FP64) {
         if (kind == FMMBEM_STOKES_SL)
-            launch_near<double, FMMBEM_STOKES_SL>(ctx, x, st);
+            up_pass<double, FMMBEM_STOKES_SL>(ctx, p, st);
         else if (kind == FMMBEM_LAPLACE_DL)
-            launch_near<double, FMMBEM_LAPLACE_DL>(ctx, x, st);
+            up_pass<double, FMMBEM_LAPLACE_DL>(ctx, p, st);
         else
-            launch_near<double, FMMBEM_LAPLACE_SL>(ctx, x, st);
+            up_pass<double, FMMBEM_LAPLACE_SL>(ctx, p, st);
     } else {
         if (kind == FMMBEM_STOKES_SL)
-            launch_near<float, FMMBEM_STOKES_SL>(ctx, x, st);
+            up_pass<float, FMMBEM_STOKES_SL>(ctx, p, st);
         else if (kind == FMMBEM_LAPLACE_DL)
-            launch_near<float, FMMBEM_LAPLACE_DL>(ctx, x, st);
+            up_pass<float, FMMBEM_LAPLACE_DL>(ctx, p, st);
         else
-            launch_near<float, FMMBEM_LAPLACE_SL>(ctx, x, st);
+            up_pass<float, FMMBEM_LAPLACE_SL>(ctx, p, st);
+    }
+}
+
+void charges_dispatch(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
+{
+    const int kind = ctx->kernel;
+    if (prec == FMMBEM_FP64) {
+        if (kind == FMMBEM_STOKES_SL)
+            launch_charges<double, FMMBEM_STOKES_SL>(ctx, x, st);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            launch_charges<double, FMMBEM_LAPLACE_DL>(ctx, x, st);
+        else
+            launch_charges<double, FMMBEM_LAPLACE_SL>(ctx, x, st);
+    } else {
+        if (kind == FMMBEM_STOKES_SL)
+            launch_charges<float, FMMBEM_STOKES_SL>(ctx, x, st);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            launch_charges<float, FMMBEM_LAPLACE_DL>(ctx, x, st);
+        else
+            launch_charges<float, FMMBEM_LAPLACE_SL>(ctx, x, st);
+    }
+}
+
+void side_near_dispatch(fmmbem_ctx *ctx, int prec)
+{
+    const int kind = ctx->kernel;
+    if (prec == FMMBEM_FP64) {
+        if (kind == FMMBEM_STOKES_SL)
+            launch_side_near<double, FMMBEM_STOKES_SL>(ctx);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            launch_side_near<double, FMMBEM_LAPLACE_DL>(ctx);
+        else
+            launch_side_near<double, FMMBEM_LAPLACE_SL>(ctx);
+    } else {
+        if (kind == FMMBEM_STOKES_SL)
+            launch_side_near<float, FMMBEM_STOKES_SL>(ctx);
+        else if (kind == FMMBEM_LAPLACE_DL)
+            launch_side_near<float, FMMBEM_LAPLACE_DL>(ctx);
+        else
+            launch_side_near<float, FMMBEM_LAPLACE_SL>(ctx);
     }
 }
 
 }  // namespace
 
-void prefetch_near(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
+void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
 {
-    near_dispatch(ctx, prec, x, st);
+    charges_dispatch(ctx, prec, x, st);
     ctx->spec_x = x;
     ctx->spec_prec = prec;
+    ctx->spec_up_p = -1;
+}
+
+void prefetch_up(fmmbem_ctx *ctx, int prec, int p_up, hipStream_t st)
+{
+    FB_REQUIRE(ctx->spec_x != nullptr && ctx->spec_prec == prec, FMMBEM_EINTERNAL,
+               "upward pass prefetched without the charges");
+    FB_REQUIRE(p_up >= 1 && p_up <= ctx->prm.p_max && (prec == FMMBEM_FP64 || p_up <= P_MAX_FP32),
+               FMMBEM_EINVAL, "upward pass order out of range");
+    if (ctx->tree.n_m2l > 0) {
+        up_dispatch(ctx, p_up, prec, st);
+        ctx->spec_up_p = p_up;
+    }
 }
 
 void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hipStream_t st)
 {
     const int kind = ctx->kernel;
-    // a near field prefetched for exactly this input and precision is used
-    // as is; any other is dropped
-    const bool have_near = ctx->spec_x == x && ctx->spec_prec == prec;
+    // charges prefetched for exactly this input and precision are used as
+    // they are, and so are the multipoles of an upward pass prefetched with
+    // them at an order >= p; anything else is dropped
+    const bool have_charges = ctx->spec_x == x && ctx->spec_prec == prec;
+    const bool have_up = have_charges && ctx->spec_up_p >= p;
     ctx->spec_x = nullptr;
     ctx->spec_prec = -1;
-    if (!have_near)
-        near_dispatch(ctx, prec, x, st);
+    ctx->spec_up_p = -1;
+    if (!have_charges)
+        charges_dispatch(ctx, prec, x, st);
+    else
+        (void)hipEventQuery(ctx->ev_fork);  // refresh its state: usually complete by now
+    side_near_dispatch(ctx, prec);
     // stored near field: its blocks already hold the corrections of their pairs
     const Correction &C = ctx->prm.near_stored ? ctx->nearm.rest : ctx->corr;
     const double pref = kind == FMMBEM_STOKES_SL   ? -1.0 / (8.0 * M_PI * ctx->prm.mu)
                         : kind == FMMBEM_LAPLACE_DL ? -1.0 / (4.0 * M_PI)
                                                     : 1.0 / (4.0 * M_PI);
     const CombineArgs ca{ctx->tree.perm, C.ptr, C.col_orig, C.val, x, ctx->y_near, pref, y};
-    far_dispatch(ctx, p, prec, ca, st);  // ends with the join and the combine
+    far_dispatch(ctx, p, prec, ca, st, have_up);  // ends with the join and the combine
     ctx->near_pending = false;
 }
 

@@ -428,18 +428,29 @@ void GmresState::enqueue_step()
     FB_HIP(hipGetLastError());
     k_normalize<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->rpt, kw->w, kw->partn, kw->nb, vn, kw->hcol_dev + (k + 1));
     FB_HIP(hipGetLastError());
-    FB_HIP(hipEventRecord(ev_h, st));
-    // While the host waits for the column, start the near field of the next
-    // mat-vec (its input is v_{k+1}).  Its precision follows the schedule at
-    // a residual extrapolated from the last two (a hundredth of the last one when
-    // there is no ratio yet); nothing is started where the extrapolated
-    // residual already meets the tolerance or the cycle ends.
+    // Ahead of the next mat-vec (its input is v_{k+1}): its charges before the
+    // host's event, so that the near field starts from an event the host has
+    // seen complete (a wait on a pending event costs the host about as much as
+    // several launches), and its upward pass after it, run while the host
+    // waits.  The precision follows the schedule at a residual extrapolated
+    // from the last two (a hundredth of the last one when there is no ratio
+    // yet); nothing is started where the extrapolated residual already meets
+    // the tolerance or the cycle ends.  The upward pass takes this mat-vec's
+    // order: the GMRES residual never grows within a cycle and the order
+    // never falls as the residual grows, so the next order is at most this one.
+    int pre_prec = -1, p_up = 0;
     if (k + 1 < m && it + 1 < s.max_iter) {
         const double ratio = rho_prev2 > 0.0 ? std::min(1.0, rho_prev / rho_prev2) : 0.01;
         const double rho_next = rho_prev * ratio;
-        if (rho_next > tol)
-            prefetch_near(ctx, choose(&s, rho_next, tol).prec, vn, st);
+        if (rho_next > tol) {
+            pre_prec = choose(&s, rho_next, tol).prec;
+            p_up = pre_prec == FMMBEM_FP32 ? std::min(cur.p, P_MAX_FP32) : cur.p;
+            prefetch_charges(ctx, pre_prec, vn, st);
+        }
     }
+    FB_HIP(hipEventRecord(ev_h, st));
+    if (pre_prec >= 0)
+        prefetch_up(ctx, pre_prec, p_up, st);
 }
 
 void GmresState::end_cycle()
