@@ -39,6 +39,9 @@ __host__ __device__ constexpr inline int cidx(int n, int m) { return n * (n + 1)
 constexpr int P_MAX = FMMBEM_P_MAX;
 constexpr int P_MAX_FP32 = FMMBEM_P_MAX_FP32;
 constexpr int NC_MAX = ncoef(P_MAX);
+// longest chain of boxes (leaf and its ancestors down from the coarsest M2L
+// target level) that the fused downward pass of one leaf takes
+constexpr int DOWN_LEAF_MAXC = 8;
 // sources per P2P chunk (one LDS tile of a wave)
 constexpr int P2P_TILE = 128;
 

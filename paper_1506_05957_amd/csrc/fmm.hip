@@ -1201,6 +1201,59 @@ __device__ inline void combine_target(const CombineArgs &A, int64_t i, const dou
     }
 }
 
+// The scaled regular harmonics R_n^m(x, y, z), 0 <= m <= n <= p, of one
+// point, in the order m = 0..p, n = m..p: f(index of (n, m), weight * Re,
+// weight * Im), the weight 2 for m > 0 standing for the -m term of a real
+// field (column recurrence in n on the diagonal R_m^m).
+template <typename R, typename F>
+__device__ __forceinline__ void sweep_regular(int p, R x, R y, R z, F &&f)
+{
+    const R r2 = x * x + y * y + z * z;
+    R dre = 1, dim = 0;  // R_m^m
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            R g = -inv_int<R>(2 * m);
+            R a = g * (x * dre - y * dim), bb = g * (x * dim + y * dre);
+            dre = a;
+            dim = bb;
+        }
+        const R wgt = m == 0 ? R(1) : R(2);
+        R cr = dre, ci = dim, pr = 0, pi = 0;
+        for (int n = m; n <= p; ++n) {
+            if (n > m) {
+                R g = inv_int<R>((n - m) * (n + m));
+                R a = R(2 * n - 1) * z;
+                R nr = (a * cr - r2 * pr) * g, ni = (a * ci - r2 * pi) * g;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+            }
+            f(cidx(n, m), n, wgt * cr, wgt * ci);
+        }
+    }
+}
+
+// a target's position relative to the centre c of its leaf, in units of the
+// leaf half-size s (FP32: from the leaf-relative copy)
+template <typename R>
+__device__ __forceinline__ void target_rel(int64_t i, int64_t nt, double s, const double *c,
+                                           const double *__restrict__ tc, const float *__restrict__ tc32, R &x,
+                                           R &y, R &z)
+{
+    if constexpr (sizeof(R) == 8) {
+        double is = 1.0 / s;
+        x = (tc[i] - c[0]) * is;
+        y = (tc[nt + i] - c[1]) * is;
+        z = (tc[2 * nt + i] - c[2]) * is;
+    } else {
+        float is = (float)(1.0 / s);
+        x = tc32[i] * is;
+        y = tc32[nt + i] * is;
+        z = tc32[2 * nt + i] * is;
+    }
+}
+
 // L2P: one block per leaf, one thread per target, which also combines the
 // target's far field with its near field (joined before the launch).
 template <typename R, int KIND>
@@ -1245,21 +1298,9 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
         }
     }
     __syncthreads();
-    const int64_t ntl = nt;
     for (int i = tb + threadIdx.x; i < te; i += blockDim.x) {
         R x, y, z;
-        if constexpr (sizeof(R) == 8) {
-            double is = 1.0 / s;
-            x = (tc[i] - c[0]) * is;
-            y = (tc[ntl + i] - c[1]) * is;
-            z = (tc[2 * ntl + i] - c[2]) * is;
-        } else {
-            float is = (float)(1.0 / s);
-            x = tc32[i] * is;
-            y = tc32[ntl + i] * is;
-            z = tc32[2 * ntl + i] * is;
-        }
-        const R r2 = x * x + y * y + z * z;
+        target_rel<R>(i, nt, s, c, tc, tc32, x, y, z);
         R pot[NV], grd[NG > 0 ? NG : 1];
 #pragma unroll
         for (int a = 0; a < NV; ++a)
@@ -1267,40 +1308,18 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
 #pragma unroll
         for (int a = 0; a < (NG > 0 ? NG : 1); ++a)
             grd[a] = 0;
-        R dre = 1, dim = 0;  // R_m^m
-        for (int m = 0; m <= p; ++m) {
-            if (m > 0) {
-                R f = -inv_int<R>(2 * m);
-                R a = f * (x * dre - y * dim), bb = f * (x * dim + y * dre);
-                dre = a;
-                dim = bb;
-            }
-            const R wgt = m == 0 ? R(1) : R(2);
-            R cr = dre, ci = dim, pr = 0, pi = 0;
-            for (int n = m; n <= p; ++n) {
-                if (n > m) {
-                    R f = inv_int<R>((n - m) * (n + m));
-                    R a = R(2 * n - 1) * z;
-                    R nr = (a * cr - r2 * pr) * f, ni = (a * ci - r2 * pi) * f;
-                    pr = cr;
-                    pi = ci;
-                    cr = nr;
-                    ci = ni;
-                }
-                const int id = cidx(n, m);
-                const R wr = wgt * cr, wi = wgt * ci;
+        sweep_regular<R>(p, x, y, z, [&](int id, int n, R wr, R wi) {
 #pragma unroll
-                for (int a = 0; a < NV; ++a)
-                    pot[a] += V[a][id].re * wr + V[a][id].im * wi;
-                if constexpr (STOKES) {
-                    if (n < p) {
+            for (int a = 0; a < NV; ++a)
+                pot[a] += V[a][id].re * wr + V[a][id].im * wi;
+            if constexpr (STOKES) {
+                if (n < p) {
 #pragma unroll
-                        for (int g = 0; g < NG; ++g)
-                            grd[g] += G[g][id].re * wr + G[g][id].im * wi;
-                    }
+                    for (int g = 0; g < NG; ++g)
+                        grd[g] += G[g][id].re * wr + G[g][id].im * wi;
                 }
             }
-        }
+        });
         if constexpr (!STOKES) {
             const double yf = (double)pot[0] / s;
             combine_target<KIND>(ca, i, &yf);
@@ -1495,6 +1514,115 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, 
                 sum += (double)red[v][a][q * n + tt];
         ynear[(int64_t)NQ * (tb + tt) + a] = sum;
     }
+}
+
+// The downward pass of one leaf in one block, for one channel at the low
+// orders: the local expansion of a box is its own M2L sum (written by the
+// reduce) plus the L2L of its parent's.  The block follows the leaf's chain of
+// ancestors down from the coarsest M2L target level, with the ancestors' own
+// sums and the octant operators of the chain staged in LDS (every leaf
+// recomputes its ancestors: at these orders that costs less than one launch
+// per level), then evaluates the leaf's local expansion at its targets and
+// combines as L2P does.  Dynamic LDS: sizeof(R) ((nc_max - 1) D^2 +
+// (nc_max + 1) D) for chains of at most nc_max boxes, D = 2 ncoef(p).
+template <typename R, int KIND>
+__global__ __launch_bounds__(256) void k_down_leaf(int p, int ncs, int lmin, int opd, const R *__restrict__ l2l_op,
+                                                   const int8_t *__restrict__ box_oct,
+                                                   const int32_t *__restrict__ leaves,
+                                                   const int32_t *__restrict__ box_i,
+                                                   const double *__restrict__ box_r, double side, int64_t nt,
+                                                   const double *__restrict__ tc, const float *__restrict__ tc32,
+                                                   const cplx<R> *__restrict__ L, CombineArgs ca)
+{
+    static_assert(KIND != FMMBEM_STOKES_SL, "one channel");
+    constexpr int MAXC = DOWN_LEAF_MAXC;
+    constexpr int U = 8;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int chain[MAXC];  // chain[0] the leaf, chain[c + 1] the parent of chain[c]
+    __shared__ int nchain_s;
+    const int D = 2 * ncoef(p), DD = D * D;
+    const int tid = threadIdx.x;
+    const int b = leaves[blockIdx.x];
+    if (tid == 0) {
+        int n = 1, x = b;
+        chain[0] = b;
+        while (n < MAXC && box_i[6 * x] > lmin) {
+            x = box_i[6 * x + 3];
+            chain[n++] = x;
+        }
+        nchain_s = n;
+    }
+    __syncthreads();
+    const int nch = nchain_s;
+    R *own = reinterpret_cast<R *>(smem_raw);  // [nch][D]
+    R *ts = own + nch * D;                     // [nch - 1][D][D]: chain[c + 1] into chain[c], input-major
+    R *acc = ts + (nch - 1) * DD;              // [D]: the local expansion walked down the chain
+    {
+        const R *Lr = reinterpret_cast<const R *>(L);
+        for (int d = tid; d < nch * D; d += blockDim.x) {
+            const int c = d / D;
+            own[d] = Lr[(int64_t)chain[c] * 2 * ncs + (d - c * D)];
+        }
+        // operator entries U at a time per thread, unguarded at clamped indices
+        const int ne = (nch - 1) * DD;
+        for (int e0 = 0; e0 < ne; e0 += U * (int)blockDim.x) {
+            R v[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int e = min(e0 + j * (int)blockDim.x + tid, ne - 1);
+                const int c = e / DD, rem = e - c * DD, k = rem / D, r = rem - k * D;
+                const int o = box_oct[chain[c]];
+                v[j] = l2l_op[((int64_t)o * opd + k) * opd + r];
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int e = e0 + j * (int)blockDim.x + tid;
+                if (e < ne)
+                    ts[e] = v[j];
+            }
+        }
+    }
+    __syncthreads();
+    for (int d = tid; d < D; d += blockDim.x)
+        acc[d] = own[(nch - 1) * D + d];
+    __syncthreads();
+    for (int c = nch - 2; c >= 0; --c) {
+        R v = 0;
+        if (tid < D) {
+            const R *t = ts + c * DD + tid;
+            v = own[c * D + tid];
+            for (int k = 0; k < D; ++k)
+                v += t[k * D] * acc[k];
+        }
+        __syncthreads();
+        if (tid < D)
+            acc[tid] = v;
+        __syncthreads();
+    }
+    const cplx<R> *V = reinterpret_cast<const cplx<R> *>(acc);
+    const int lv = box_i[6 * b], tb = box_i[6 * b + 1], te = box_i[6 * b + 2];
+    const double s = ldexp(side, -(lv + 1));
+    const double *cb = box_r + 5 * (int64_t)b;
+    for (int i = tb + tid; i < te; i += blockDim.x) {
+        R x, y, z;
+        target_rel<R>(i, nt, s, cb, tc, tc32, x, y, z);
+        R pot = 0;
+        sweep_regular<R>(p, x, y, z, [&](int id, int, R wr, R wi) { pot += V[id].re * wr + V[id].im * wi; });
+        const double yf = (double)pot / s;
+        combine_target<KIND>(ca, i, &yf);
+    }
+}
+
+// LDS of k_down_leaf for chains of at most nc_max boxes at order p; 0 where
+// the fused downward pass does not apply (more than DOWN_LEAF_MAXC boxes, or
+// more than 48 KiB, or more than 256 rows)
+template <typename R> size_t down_leaf_shm(int p, int nc_max)
+{
+    const size_t D = 2 * (size_t)ncoef(p);
+    if (nc_max < 1 || nc_max > DOWN_LEAF_MAXC || D > 256)
+        return 0;
+    const size_t b = sizeof(R) * ((size_t)(nc_max - 1) * D * D + (size_t)(nc_max + 1) * D);
+    return b <= 48 * 1024 ? b : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1718,19 +1846,38 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 k_m2l_reduce<R, NCH, false><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             FB_HIP(hipGetLastError());
         }
-        // parents of level l - 1 into children of level l; levels above the
-        // coarsest M2L target hold no local expansion
-        for (int l = std::max(1, P.lmin_tgt + 1); l < T.nlevels; ++l) {
-            const int t0 = P.tile_begin[l], ntile = P.tile_begin[l + 1] - t0;
-            if (ntile == 0)
-                continue;
-            k_octant_apply<R, NCH, true><<<dim3(ntile, row_chunks), 256, op_shm, st>>>(p, ncs, P.op_dim, l2l_op, P.tiles, t0,
-                                                                     P.level_list, T.box_i, T.box_r, L, L);
+        // one channel at the low orders: L2L down each leaf's chain of
+        // ancestors (levels from the coarsest M2L target on) and L2P in one
+        // block per leaf, where the chain and its operators fit in LDS
+        bool fused = false;
+        if constexpr (NCH == 1) {
+            const size_t dshm = down_leaf_shm<R>(p, std::max(1, T.nlevels - std::max(P.lmin_tgt, 0)));
+            if (dshm > 0) {
+                FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // the combine needs the near field
+                k_down_leaf<R, KIND><<<T.nleaf, 256, dshm, st>>>(p, ncs, std::max(P.lmin_tgt, 0), P.op_dim,
+                                                                 l2l_op, P.box_oct,
+                                                                 T.leaves, T.box_i, T.box_r, side, nt, G.tc,
+                                                                 G.tc32, L, ca);
+                FB_HIP(hipGetLastError());
+                fused = true;
+            }
+        }
+        if (!fused) {
+            // parents of level l - 1 into children of level l; levels above the
+            // coarsest M2L target hold no local expansion
+            for (int l = std::max(1, P.lmin_tgt + 1); l < T.nlevels; ++l) {
+                const int t0 = P.tile_begin[l], ntile = P.tile_begin[l + 1] - t0;
+                if (ntile == 0)
+                    continue;
+                k_octant_apply<R, NCH, true><<<dim3(ntile, row_chunks), 256, op_shm, st>>>(
+                    p, ncs, P.op_dim, l2l_op, P.tiles, t0, P.level_list, T.box_i, T.box_r, L, L);
+                FB_HIP(hipGetLastError());
+            }
+            FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // L2P combines with the near field
+            k_l2p<R, KIND><<<T.nleaf, 64, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L,
+                                                   ca);
             FB_HIP(hipGetLastError());
         }
-        FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // L2P combines with the near field
-        k_l2p<R, KIND><<<T.nleaf, 64, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L, ca);
-        FB_HIP(hipGetLastError());
         stage_end(ctx, SO + 3, st, ev);
     } else {
         hipEvent_t ev4;
