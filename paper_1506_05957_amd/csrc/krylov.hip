@@ -435,16 +435,21 @@ void GmresState::enqueue_step()
     // waits.  The precision follows the schedule at a residual extrapolated
     // from the last two (a hundredth of the last one when there is no ratio
     // yet); nothing is started where the extrapolated residual already meets
-    // the tolerance or the cycle ends.  The upward pass takes this mat-vec's
-    // order: the GMRES residual never grows within a cycle and the order
-    // never falls as the residual grows, so the next order is at most this one.
+    // the tolerance or the cycle ends.  The upward pass takes at most this
+    // mat-vec's order (the GMRES residual never grows within a cycle and the
+    // order never falls as the residual grows, so the next order is at most
+    // this one) and at most two above the order at the extrapolated residual;
+    // a mat-vec of a higher order runs its own upward pass.
     int pre_prec = -1, p_up = 0;
     if (k + 1 < m && it + 1 < s.max_iter) {
         const double ratio = rho_prev2 > 0.0 ? std::min(1.0, rho_prev / rho_prev2) : 0.01;
         const double rho_next = rho_prev * ratio;
         if (rho_next > tol) {
-            pre_prec = choose(&s, rho_next, tol).prec;
-            p_up = pre_prec == FMMBEM_FP32 ? std::min(cur.p, P_MAX_FP32) : cur.p;
+            const Sched nx = choose(&s, rho_next, tol);
+            pre_prec = nx.prec;
+            p_up = std::min(cur.p, nx.p + 2);
+            if (pre_prec == FMMBEM_FP32)
+                p_up = std::min(p_up, P_MAX_FP32);
             prefetch_charges(ctx, pre_prec, vn, st);
         }
     }
