@@ -13,6 +13,56 @@
 
 namespace fmmbem {
 
+// Block of the Arnoldi reductions (and of every kernel that sums their
+// partials again): 256 threads.
+constexpr int DOT_BLOCK = 256;
+constexpr int DOT_NWV = DOT_BLOCK / 64;
+
+// out[j] = sum_b part[j nb + b] for j < nv, into LDS, in a block of DOT_BLOCK
+// threads (all of them take part): the waves take the vectors four at a time,
+// lanes stride over b, then a shuffle tree.  The order is fixed, so every
+// block that sums the same partials gets the same bits.
+__device__ inline void block_sums(const double *__restrict__ part, int nb, int nv, double *__restrict__ out)
+{
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int jb = 0; jb < nv; jb += 4 * DOT_NWV) {
+        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = lane; k < nb; k += 64) {
+            double v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jb + r * DOT_NWV + wv;
+                v[r] = j < nv ? part[(int64_t)j * nb + k] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                t[r] += v[r];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                t[r] += __shfl_down(t[r], off, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jb + r * DOT_NWV + wv;
+                if (j < nv)
+                    out[j] = t[r];
+            }
+    }
+}
+
+// An Arnoldi normalisation folded into the charges of the next mat-vec: the
+// input is w / |w|, |w|^2 = sum of the nb partials partn (the last Arnoldi
+// step's), stored to nrm2_out; all null: no normalisation.
+struct NormIn {
+    const double *w = nullptr;
+    const double *partn = nullptr;
+    int nb = 0;
+    double *nrm2_out = nullptr;
+};
+
 struct Error : std::runtime_error {
     int code;
     Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
@@ -40,8 +90,12 @@ constexpr int P_MAX = FMMBEM_P_MAX;
 constexpr int P_MAX_FP32 = FMMBEM_P_MAX_FP32;
 constexpr int NC_MAX = ncoef(P_MAX);
 // longest chain of boxes (leaf and its ancestors down from the coarsest M2L
-// target level) that the fused downward pass of one leaf takes
+// target level) that the fused downward pass of one leaf takes, and the
+// int32 fields of its per-leaf record: first target, end target, level,
+// chain length, the chain (leaf first), the chain's octants (3 bits each), pad
 constexpr int DOWN_LEAF_MAXC = 8;
+constexpr int LEAF_REC = 16;
+static_assert(4 + DOWN_LEAF_MAXC + 1 <= LEAF_REC, "leaf record");
 // sources per P2P chunk (one LDS tile of a wave)
 constexpr int P2P_TILE = 128;
 
@@ -166,6 +220,7 @@ struct M2LPlan {
     // coarsest levels holding an M2L source / target: M2M into levels above
     // the first and L2L out of levels above the second carry nothing
     int lmin_src = 0, lmin_tgt = 0;
+    int32_t *leaf_rec = nullptr;        // [nleaf][LEAF_REC]: see LEAF_REC
     void *Z = nullptr;                  // [nbox][nch][ncoef(p_max)] complex FP64: per-child M2M terms
     // stored FP64 pass-1 operators (m2l_stored): per translation, row tiles
     // rt < ops_nrt of 16 rows, column steps kt < ops_k4 of 4 inputs, 64
@@ -310,10 +365,12 @@ void build_correction(fmmbem_ctx *ctx, hipStream_t st);
 void build_translations(fmmbem_ctx *ctx, hipStream_t st);
 void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hipStream_t st);
 // launch the charges of a mat-vec on x at precision prec ahead of time (the
+// input written there first as w / |w| from the partial sums nz.partn when
+// they are given: see k_charges; the
 // next run_matvec with the same x and prec uses them and starts the near field
 // from them), then optionally the upward pass (P2M, M2M) of order p_up, whose
 // multipoles that run_matvec uses when its order is <= p_up
-void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st);
+void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st, const NormIn &nz = NormIn{});
 void prefetch_up(fmmbem_ctx *ctx, int prec, int p_up, hipStream_t st);
 // stored near field (nearfield.hip): assemble at build; one product on
 // stream st of the input in sorted order (nearm.xs, written by the charges)

@@ -129,23 +129,47 @@ template <> struct Src<float, true> { float x, y, z, f0, f1, f2, pad0, pad1; };
 template <int KIND> constexpr bool vec_src() { return KIND != FMMBEM_LAPLACE_SL; }
 
 // With xs (the stored near field), the first thread of every panel also
-// copies the panel's input value(s) to xs in sorted order.
+// copies the panel's input value(s) to xs in sorted order.  With nz.partn (the
+// last Arnoldi step's partial sums of |w|^2), the input is w / |w|: every block
+// sums the partials in the fixed order of the Arnoldi kernels, the first
+// thread of every panel writes the normalised values to xout, and block 0
+// stores |w|^2 to nz.nrm2_out (the normalisation of the Arnoldi step, done
+// here instead of in its own launch).
 template <typename R, int KIND>
-__global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const double *__restrict__ sp,
-                          const float *__restrict__ sp32, const double *__restrict__ nrm,
-                          const double *__restrict__ x, Src<R, vec_src<KIND>()> *__restrict__ src,
-                          double *__restrict__ xs)
+__global__ __launch_bounds__(DOT_BLOCK) void k_charges(int64_t nt, const int32_t *__restrict__ perm,
+                                                       const double *__restrict__ sp, const float *__restrict__ sp32,
+                                                       const double *__restrict__ nrm, const double *__restrict__ xin,
+                                                       Src<R, vec_src<KIND>()> *__restrict__ src,
+                                                       double *__restrict__ xs, NormIn nz, double *__restrict__ xout)
 {
     constexpr int NQ = KIND == FMMBEM_STOKES_SL ? 3 : 1;
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ns = 4 * nt;
+    double scale = 1.0;
+    if (nz.partn) {  // every thread of the block takes part in the sum
+        __shared__ double tot;
+        block_sums(nz.partn, nz.nb, 1, &tot);
+        __syncthreads();
+        scale = 1.0 / sqrt(tot);
+        if (blockIdx.x == 0 && threadIdx.x == 0 && nz.nrm2_out)
+            *nz.nrm2_out = tot;
+    }
     if (s >= ns)
         return;
     const int64_t o = perm[s >> 2];
-    if (xs && (s & 3) == 0)
+    double xv[NQ];
 #pragma unroll
-        for (int a = 0; a < NQ; ++a)
-            xs[NQ * (s >> 2) + a] = x[NQ * o + a];
+    for (int a = 0; a < NQ; ++a)
+        xv[a] = nz.partn ? xin[NQ * o + a] * scale : xin[NQ * o + a];
+    if ((s & 3) == 0) {
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+            if (xs)
+                xs[NQ * (s >> 2) + a] = xv[a];
+            if (nz.partn)
+                xout[NQ * o + a] = xv[a];
+        }
+    }
     const double w = sp[3 * ns + s];
     Src<R, vec_src<KIND>()> v;
     if constexpr (sizeof(R) == 8) {
@@ -158,15 +182,15 @@ __global__ void k_charges(int64_t nt, const int32_t *__restrict__ perm, const do
         v.z = sp32[2 * ns + s];
     }
     if constexpr (KIND == FMMBEM_LAPLACE_SL) {
-        v.q = (R)(w * x[o]);
+        v.q = (R)(w * xv[0]);
     } else if constexpr (KIND == FMMBEM_STOKES_SL) {
-        v.f0 = (R)(w * x[3 * o]);
-        v.f1 = (R)(w * x[3 * o + 1]);
-        v.f2 = (R)(w * x[3 * o + 2]);
+        v.f0 = (R)(w * xv[0]);
+        v.f1 = (R)(w * xv[1]);
+        v.f2 = (R)(w * xv[2]);
         v.pad0 = v.pad1 = 0;
     } else {
         const int64_t i = s >> 2;
-        const double wx = w * x[o];
+        const double wx = w * xv[0];
         v.f0 = (R)(wx * nrm[i]);
         v.f1 = (R)(wx * nrm[nt + i]);
         v.f2 = (R)(wx * nrm[2 * nt + i]);
@@ -1201,6 +1225,20 @@ __device__ inline void combine_target(const CombineArgs &A, int64_t i, const dou
     }
 }
 
+// combine_target for one channel with the target's inputs already read:
+// o = perm[i], its near field yn, its correction range [c0, c1) and (double
+// layer) its input xo; the same arithmetic
+template <int KIND>
+__device__ inline void combine_target_pre(const CombineArgs &A, int64_t o, double yn, int c0, int c1, double xo,
+                                          double yf)
+{
+    static_assert(KIND != FMMBEM_STOKES_SL, "one channel");
+    double acc = yn + yf;
+    for (int e = c0; e < c1; ++e)
+        acc += A.cval[e] * A.x[A.ccol[e]];
+    A.y[o] = KIND == FMMBEM_LAPLACE_DL ? 0.5 * xo + A.pref * acc : A.pref * acc;
+}
+
 // The scaled regular harmonics R_n^m(x, y, z), 0 <= m <= n <= p, of one
 // point, in the order m = 0..p, n = m..p: f(index of (n, m), weight * Re,
 // weight * Im), the weight 2 for m > 0 standing for the -m term of a real
@@ -1519,17 +1557,16 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, 
 // The downward pass of one leaf in one block, for one channel at the low
 // orders: the local expansion of a box is its own M2L sum (written by the
 // reduce) plus the L2L of its parent's.  The block follows the leaf's chain of
-// ancestors down from the coarsest M2L target level, with the ancestors' own
-// sums and the octant operators of the chain staged in LDS (every leaf
-// recomputes its ancestors: at these orders that costs less than one launch
-// per level), then evaluates the leaf's local expansion at its targets and
-// combines as L2P does.  Dynamic LDS: sizeof(R) ((nc_max - 1) D^2 +
+// ancestors (from its record, built with the tree) down from the coarsest M2L
+// target level, with the ancestors' own sums and the octant operators of the
+// chain staged in LDS (every leaf recomputes its ancestors: at these orders
+// that costs less than one launch per level), then evaluates the leaf's local
+// expansion at its targets and combines as L2P does; a thread's first
+// target's inputs are read at the start, beside the chain's.  Dynamic LDS: sizeof(R) ((nc_max - 1) D^2 +
 // (nc_max + 1) D) for chains of at most nc_max boxes, D = 2 ncoef(p).
 template <typename R, int KIND>
-__global__ __launch_bounds__(256) void k_down_leaf(int p, int ncs, int lmin, int opd, const R *__restrict__ l2l_op,
-                                                   const int8_t *__restrict__ box_oct,
-                                                   const int32_t *__restrict__ leaves,
-                                                   const int32_t *__restrict__ box_i,
+__global__ __launch_bounds__(256) void k_down_leaf(int p, int ncs, int opd, const R *__restrict__ l2l_op,
+                                                   const int32_t *__restrict__ leaf_rec,
                                                    const double *__restrict__ box_r, double side, int64_t nt,
                                                    const double *__restrict__ tc, const float *__restrict__ tc32,
                                                    const cplx<R> *__restrict__ L, CombineArgs ca)
@@ -1538,22 +1575,24 @@ __global__ __launch_bounds__(256) void k_down_leaf(int p, int ncs, int lmin, int
     constexpr int MAXC = DOWN_LEAF_MAXC;
     constexpr int U = 8;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int chain[MAXC];  // chain[0] the leaf, chain[c + 1] the parent of chain[c]
-    __shared__ int nchain_s;
+    __shared__ int rec[LEAF_REC];
     const int D = 2 * ncoef(p), DD = D * D;
     const int tid = threadIdx.x;
-    const int b = leaves[blockIdx.x];
-    if (tid == 0) {
-        int n = 1, x = b;
-        chain[0] = b;
-        while (n < MAXC && box_i[6 * x] > lmin) {
-            x = box_i[6 * x + 3];
-            chain[n++] = x;
-        }
-        nchain_s = n;
-    }
+    if (tid < LEAF_REC)
+        rec[tid] = leaf_rec[(int64_t)blockIdx.x * LEAF_REC + tid];
     __syncthreads();
-    const int nch = nchain_s;
+    const int tb = rec[0], te = rec[1], lv = rec[2], nch = rec[3], octs = rec[4 + MAXC];
+    const int b = rec[4];
+    const double s = ldexp(side, -(lv + 1));
+    const double *cb = box_r + 5 * (int64_t)b;
+    // this thread's first target: its inputs are read now, beside the chain's
+    const int64_t i0 = tb + tid, ic = i0 < te ? i0 : (tb < te ? tb : 0);  // a valid index to read
+    R x0, y0, z0;
+    target_rel<R>(ic, nt, s, cb, tc, tc32, x0, y0, z0);
+    const int64_t o0 = ca.perm[ic];
+    const double yn0 = ca.ynear[ic];
+    const int c00 = ca.cptr[ic], c01 = ca.cptr[ic + 1];
+    const double xo0 = KIND == FMMBEM_LAPLACE_DL ? ca.x[o0] : 0.0;
     R *own = reinterpret_cast<R *>(smem_raw);  // [nch][D]
     R *ts = own + nch * D;                     // [nch - 1][D][D]: chain[c + 1] into chain[c], input-major
     R *acc = ts + (nch - 1) * DD;              // [D]: the local expansion walked down the chain
@@ -1561,7 +1600,7 @@ __global__ __launch_bounds__(256) void k_down_leaf(int p, int ncs, int lmin, int
         const R *Lr = reinterpret_cast<const R *>(L);
         for (int d = tid; d < nch * D; d += blockDim.x) {
             const int c = d / D;
-            own[d] = Lr[(int64_t)chain[c] * 2 * ncs + (d - c * D)];
+            own[d] = Lr[(int64_t)rec[4 + c] * 2 * ncs + (d - c * D)];
         }
         // operator entries U at a time per thread, unguarded at clamped indices
         const int ne = (nch - 1) * DD;
@@ -1571,7 +1610,7 @@ __global__ __launch_bounds__(256) void k_down_leaf(int p, int ncs, int lmin, int
             for (int j = 0; j < U; ++j) {
                 const int e = min(e0 + j * (int)blockDim.x + tid, ne - 1);
                 const int c = e / DD, rem = e - c * DD, k = rem / D, r = rem - k * D;
-                const int o = box_oct[chain[c]];
+                const int o = (octs >> (3 * c)) & 7;
                 v[j] = l2l_op[((int64_t)o * opd + k) * opd + r];
             }
 #pragma unroll
@@ -1600,10 +1639,12 @@ __global__ __launch_bounds__(256) void k_down_leaf(int p, int ncs, int lmin, int
         __syncthreads();
     }
     const cplx<R> *V = reinterpret_cast<const cplx<R> *>(acc);
-    const int lv = box_i[6 * b], tb = box_i[6 * b + 1], te = box_i[6 * b + 2];
-    const double s = ldexp(side, -(lv + 1));
-    const double *cb = box_r + 5 * (int64_t)b;
-    for (int i = tb + tid; i < te; i += blockDim.x) {
+    if (i0 < te) {
+        R pot = 0;
+        sweep_regular<R>(p, x0, y0, z0, [&](int id, int, R wr, R wi) { pot += V[id].re * wr + V[id].im * wi; });
+        combine_target_pre<KIND>(ca, o0, yn0, c00, c01, xo0, (double)pot / s);
+    }
+    for (int64_t i = i0 + blockDim.x; i < te; i += blockDim.x) {  // leaves of more than 256 targets
         R x, y, z;
         target_rel<R>(i, nt, s, cb, tc, tc32, x, y, z);
         R pot = 0;
@@ -1639,7 +1680,7 @@ __global__ void k_combine(int64_t nt, CombineArgs ca, const double *__restrict__
 // charges of this mat-vec on st (for P2M, and the sorted input of the stored
 // near field); ev_fork marks them
 template <typename R, int KIND>
-void launch_charges(fmmbem_ctx *ctx, const double *x, hipStream_t st)
+void launch_charges(fmmbem_ctx *ctx, const double *x, hipStream_t st, const NormIn &nz)
 {
     constexpr bool VS = vec_src<KIND>();
     constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
@@ -1652,8 +1693,10 @@ void launch_charges(fmmbem_ctx *ctx, const double *x, hipStream_t st)
         FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
 
     stage_begin(ctx, SO + 4, st, &ev);
-    k_charges<R, KIND><<<grid_for(ns, 256), 256, 0, st>>>(nt, T.perm, G.sp, G.sp32, G.nrm, x, src,
-                                                          ctx->nearm.v64 ? ctx->nearm.xs : nullptr);
+    // normalising: read w, write x = w / |w|; else read x
+    k_charges<R, KIND><<<grid_for(ns, DOT_BLOCK), DOT_BLOCK, 0, st>>>(
+        nt, T.perm, G.sp, G.sp32, G.nrm, nz.partn ? nz.w : x, src, ctx->nearm.v64 ? ctx->nearm.xs : nullptr, nz,
+        const_cast<double *>(x));
     FB_HIP(hipGetLastError());
     stage_end(ctx, SO + 4, st, ev);
     FB_HIP(hipEventRecord(ctx->ev_fork, st));
@@ -1854,10 +1897,8 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
             const size_t dshm = down_leaf_shm<R>(p, std::max(1, T.nlevels - std::max(P.lmin_tgt, 0)));
             if (dshm > 0) {
                 FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // the combine needs the near field
-                k_down_leaf<R, KIND><<<T.nleaf, 256, dshm, st>>>(p, ncs, std::max(P.lmin_tgt, 0), P.op_dim,
-                                                                 l2l_op, P.box_oct,
-                                                                 T.leaves, T.box_i, T.box_r, side, nt, G.tc,
-                                                                 G.tc32, L, ca);
+                k_down_leaf<R, KIND><<<T.nleaf, 256, dshm, st>>>(p, ncs, P.op_dim, l2l_op, P.leaf_rec, T.box_r,
+                                                                 side, nt, G.tc, G.tc32, L, ca);
                 FB_HIP(hipGetLastError());
                 fused = true;
             }
@@ -1930,23 +1971,23 @@ void up_dispatch(fmmbem_ctx *ctx, int p, int prec, hipStream_t st)
     }
 }
 
-void charges_dispatch(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
+void charges_dispatch(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st, const NormIn &nz = NormIn{})
 {
     const int kind = ctx->kernel;
     if (prec == FMMBEM_FP64) {
         if (kind == FMMBEM_STOKES_SL)
-            launch_charges<double, FMMBEM_STOKES_SL>(ctx, x, st);
+            launch_charges<double, FMMBEM_STOKES_SL>(ctx, x, st, nz);
         else if (kind == FMMBEM_LAPLACE_DL)
-            launch_charges<double, FMMBEM_LAPLACE_DL>(ctx, x, st);
+            launch_charges<double, FMMBEM_LAPLACE_DL>(ctx, x, st, nz);
         else
-            launch_charges<double, FMMBEM_LAPLACE_SL>(ctx, x, st);
+            launch_charges<double, FMMBEM_LAPLACE_SL>(ctx, x, st, nz);
     } else {
         if (kind == FMMBEM_STOKES_SL)
-            launch_charges<float, FMMBEM_STOKES_SL>(ctx, x, st);
+            launch_charges<float, FMMBEM_STOKES_SL>(ctx, x, st, nz);
         else if (kind == FMMBEM_LAPLACE_DL)
-            launch_charges<float, FMMBEM_LAPLACE_DL>(ctx, x, st);
+            launch_charges<float, FMMBEM_LAPLACE_DL>(ctx, x, st, nz);
         else
-            launch_charges<float, FMMBEM_LAPLACE_SL>(ctx, x, st);
+            launch_charges<float, FMMBEM_LAPLACE_SL>(ctx, x, st, nz);
     }
 }
 
@@ -1972,9 +2013,9 @@ void side_near_dispatch(fmmbem_ctx *ctx, int prec)
 
 }  // namespace
 
-void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st)
+void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st, const NormIn &nz)
 {
-    charges_dispatch(ctx, prec, x, st);
+    charges_dispatch(ctx, prec, x, st, nz);
     ctx->spec_x = x;
     ctx->spec_prec = prec;
     ctx->spec_up_p = -1;

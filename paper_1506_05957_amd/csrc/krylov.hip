@@ -19,8 +19,6 @@ namespace fmmbem {
 
 namespace {
 
-constexpr int DOT_BLOCK = 256;
-constexpr int DOT_NWV = DOT_BLOCK / 64;
 constexpr int DOT_MAX_BLOCKS = 256;  // row blocks; rows per thread grow beyond that
 constexpr int AXPY_UNROLL = 8;
 
@@ -30,39 +28,6 @@ constexpr int AXPY_UNROLL = 8;
 // fixed order, so that all blocks see bit-identical coefficients and a solve
 // is reproducible.  Row block b holds rows b R + k DOT_BLOCK + t, k < rpt,
 // R = rpt DOT_BLOCK.
-
-// out[j] = sum_b part[j nb + b] for j < nv, into LDS: the waves take the
-// vectors four at a time, lanes stride over b, then a shuffle tree.
-__device__ void block_sums(const double *__restrict__ part, int nb, int nv, double *__restrict__ out)
-{
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int jb = 0; jb < nv; jb += 4 * DOT_NWV) {
-        double t[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int k = lane; k < nb; k += 64) {
-            double v[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = jb + r * DOT_NWV + wv;
-                v[r] = j < nv ? part[(int64_t)j * nb + k] : 0.0;
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                t[r] += v[r];
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                t[r] += __shfl_down(t[r], off, 64);
-        if (lane == 0)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = jb + r * DOT_NWV + wv;
-                if (j < nv)
-                    out[j] = t[r];
-            }
-    }
-}
 
 // Sum over the block of one value per thread (shuffle tree per wave, then
 // the waves in order); the result is valid in thread 0.
@@ -426,8 +391,6 @@ void GmresState::enqueue_step()
     k_update_norm<<<kw->nb, DOT_BLOCK, 2 * sizeof(double) * (k + 1), st>>>(
         n, kw->rpt, kw->V, n, k + 1, kw->part1, kw->part2, kw->nb, kw->w, kw->partn, kw->hcol_dev, m + 2);
     FB_HIP(hipGetLastError());
-    k_normalize<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->rpt, kw->w, kw->partn, kw->nb, vn, kw->hcol_dev + (k + 1));
-    FB_HIP(hipGetLastError());
     // Ahead of the next mat-vec (its input is v_{k+1}): its charges before the
     // host's event, so that the near field starts from an event the host has
     // seen complete (a wait on a pending event costs the host about as much as
@@ -439,7 +402,7 @@ void GmresState::enqueue_step()
     // mat-vec's order (the GMRES residual never grows within a cycle and the
     // order never falls as the residual grows, so the next order is at most
     // this one) and at most two above the order at the extrapolated residual;
-    // a mat-vec of a higher order runs its own upward pass.
+    // a mat-vec of a higher order than the prefetched pass runs its own.
     int pre_prec = -1, p_up = 0;
     if (k + 1 < m && it + 1 < s.max_iter) {
         const double ratio = rho_prev2 > 0.0 ? std::min(1.0, rho_prev / rho_prev2) : 0.01;
@@ -450,8 +413,14 @@ void GmresState::enqueue_step()
             p_up = std::min(cur.p, nx.p + 2);
             if (pre_prec == FMMBEM_FP32)
                 p_up = std::min(p_up, P_MAX_FP32);
-            prefetch_charges(ctx, pre_prec, vn, st);
+            // v_{k+1} = w / |w| (and |w|^2 into the host column) is written
+            // by these charges
+            prefetch_charges(ctx, pre_prec, vn, st, NormIn{kw->w, kw->partn, kw->nb, kw->hcol_dev + (k + 1)});
         }
+    }
+    if (pre_prec < 0) {
+        k_normalize<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->rpt, kw->w, kw->partn, kw->nb, vn, kw->hcol_dev + (k + 1));
+        FB_HIP(hipGetLastError());
     }
     FB_HIP(hipEventRecord(ev_h, st));
     if (pre_prec >= 0)

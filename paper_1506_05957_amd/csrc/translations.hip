@@ -273,6 +273,33 @@ void build_level_plan(fmmbem_ctx *ctx, hipStream_t st)
             P.lmin_tgt = std::min(P.lmin_tgt, hb[6 * b]);
     for (int64_t i = 0; i < T.n_m2l; ++i)
         P.lmin_src = std::min(P.lmin_src, hb[6 * srcs[i]]);
+    // per leaf, for the fused downward pass: target range, level, the chain of
+    // the leaf and its ancestors down to the coarsest M2L target level, and
+    // the octant of each chain box in its parent (3 bits each)
+    {
+        const int lmin = std::max(P.lmin_tgt, 0);
+        std::vector<int32_t> rec((size_t)T.nleaf * LEAF_REC, -1);
+        for (int li = 0; li < T.nleaf; ++li) {
+            int32_t *r = rec.data() + (size_t)li * LEAF_REC;
+            int x = T.h_leaves[li], n = 0, octs = 0;
+            r[0] = hb[6 * x + 1];
+            r[1] = hb[6 * x + 2];
+            r[2] = hb[6 * x];
+            for (;;) {
+                r[4 + n] = x;
+                octs |= (int)oct[x] << (3 * n);
+                ++n;
+                if (n == DOWN_LEAF_MAXC || hb[6 * x] <= lmin)
+                    break;
+                x = hb[6 * x + 3];
+            }
+            r[3] = n;
+            r[4 + DOWN_LEAF_MAXC] = octs;
+        }
+        P.leaf_rec = ctx->arena.alloc<int32_t>(std::max<size_t>(rec.size(), 1));
+        if (!rec.empty())
+            FB_HIP(hipMemcpyAsync(P.leaf_rec, rec.data(), sizeof(int32_t) * rec.size(), hipMemcpyHostToDevice, st));
+    }
     const int per_tile = 16 / ctx->nch;
     std::vector<int4> tiles;
     std::vector<int32_t> list, parents;
