@@ -184,8 +184,10 @@ const char *fmmbem_last_error(void);
  * kernel), 1 M2L pass 1 (the per-pair translations, one kernel), 2 P2M+M2M,
  * 3 the downward pass: the per-target sum of the M2L terms, L2L and L2P (L2P
  * also combines far field, near field and corrections, after waiting for the
- * near field), 4
- * charges (+ the combine when no box pair is far); entry [prec * 5 + stage]
+ * near field; at low orders L2L and L2P run as one kernel per leaf), 4
+ * charges (+ the combine when no box pair is far; inside a solve the charges
+ * of a prefetched mat-vec also normalise the Arnoldi vector and are counted
+ * where they are launched); entry [prec * 5 + stage]
  * holds the launches made in precision
  * prec (FMMBEM_FP64 = 0, FMMBEM_FP32 = 1), FMMBEM_N_STAGES entries in all.
  * t_ms[i] is the total time, launches[i] the number of timed launches and
