@@ -309,6 +309,7 @@ struct fmmbem_ctx {
     const double *spec_x = nullptr;
     int spec_prec = -1;
     int spec_up_p = -1;
+    bool spec_near = false;  // the near field of those charges already launched
 };
 
 namespace fmmbem {
@@ -372,6 +373,8 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
 // multipoles that run_matvec uses when its order is <= p_up
 void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st, const NormIn &nz = NormIn{});
 void prefetch_up(fmmbem_ctx *ctx, int prec, int p_up, hipStream_t st);
+// launch the near field of the prefetched charges on the side stream now
+void prefetch_side_near(fmmbem_ctx *ctx);
 // stored near field (nearfield.hip): assemble at build; one product on
 // stream st of the input in sorted order (nearm.xs, written by the charges)
 void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st);

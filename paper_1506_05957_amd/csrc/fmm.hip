@@ -2019,6 +2019,14 @@ void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st
     ctx->spec_x = x;
     ctx->spec_prec = prec;
     ctx->spec_up_p = -1;
+    ctx->spec_near = false;
+}
+
+void prefetch_side_near(fmmbem_ctx *ctx)
+{
+    FB_REQUIRE(ctx->spec_x != nullptr, FMMBEM_EINTERNAL, "near field prefetched without the charges");
+    side_near_dispatch(ctx, ctx->spec_prec);
+    ctx->spec_near = true;
 }
 
 void prefetch_up(fmmbem_ctx *ctx, int prec, int p_up, hipStream_t st)
@@ -2041,14 +2049,17 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
     // them at an order >= p; anything else is dropped
     const bool have_charges = ctx->spec_x == x && ctx->spec_prec == prec;
     const bool have_up = have_charges && ctx->spec_up_p >= p;
+    const bool have_near = have_charges && ctx->spec_near;
     ctx->spec_x = nullptr;
     ctx->spec_prec = -1;
     ctx->spec_up_p = -1;
+    ctx->spec_near = false;
     if (!have_charges)
         charges_dispatch(ctx, prec, x, st);
     else
         (void)hipEventQuery(ctx->ev_fork);  // refresh its state: usually complete by now
-    side_near_dispatch(ctx, prec);
+    if (!have_near)
+        side_near_dispatch(ctx, prec);
     // stored near field: its blocks already hold the corrections of their pairs
     const Correction &C = ctx->prm.near_stored ? ctx->nearm.rest : ctx->corr;
     const double pref = kind == FMMBEM_STOKES_SL   ? -1.0 / (8.0 * M_PI * ctx->prm.mu)

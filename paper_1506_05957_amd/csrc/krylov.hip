@@ -392,10 +392,8 @@ void GmresState::enqueue_step()
         n, kw->rpt, kw->V, n, k + 1, kw->part1, kw->part2, kw->nb, kw->w, kw->partn, kw->hcol_dev, m + 2);
     FB_HIP(hipGetLastError());
     // Ahead of the next mat-vec (its input is v_{k+1}): its charges before the
-    // host's event, so that the near field starts from an event the host has
-    // seen complete (a wait on a pending event costs the host about as much as
-    // several launches), and its upward pass after it, run while the host
-    // waits.  The precision follows the schedule at a residual extrapolated
+    // host's event, then its upward pass and its near field, run while the
+    // host waits for the column.  The precision follows the schedule at a residual extrapolated
     // from the last two (a hundredth of the last one when there is no ratio
     // yet); nothing is started where the extrapolated residual already meets
     // the tolerance or the cycle ends.  The upward pass takes at most this
@@ -423,8 +421,14 @@ void GmresState::enqueue_step()
         FB_HIP(hipGetLastError());
     }
     FB_HIP(hipEventRecord(ev_h, st));
-    if (pre_prec >= 0)
+    if (pre_prec >= 0) {
         prefetch_up(ctx, pre_prec, p_up, st);
+        // the near field after the launches the GPU needs first: its fork
+        // waits on the pending charges (several launches' worth of host
+        // time, which the host would spend waiting anyway), and the product
+        // is done sooner than when forked after the host's wait
+        prefetch_side_near(ctx);
+    }
 }
 
 void GmresState::end_cycle()
