@@ -340,6 +340,7 @@ struct GmresState {
     double bnorm = 0, beta = 0, rel = 1, true_rel = 1, rho_prev = 1;
     double rho_prev2 = -1;  // the residual before rho_prev, < 0 if none
     bool done = false;
+    bool bnorm_known = true;  // false from the start until the first column is read
     Sched cur{0, 0};
     std::vector<int32_t> p_hist;
     std::vector<uint8_t> prec_hist;

@@ -257,8 +257,10 @@ KrylovWork *get_work(fmmbem_ctx *ctx, int m)
         kw->part2 = kw->arena.alloc<double>((size_t)(m + 1) * kw->nb);
         kw->partn = kw->arena.alloc<double>(kw->nb);
         kw->y = kw->arena.alloc<double>(m + 1);
-        FB_HIP(hipHostMalloc((void **)&kw->hcol, sizeof(double) * 2 * (m + 2), hipHostMallocMapped));
-        std::fill(kw->hcol, kw->hcol + 2 * (m + 2), 0.0);
+        // the Hessenberg column (h1 and |w|^2 at [0, m + 2), h2 at [m + 2,
+        // 2 m + 4)) and |b|^2 of the start at 2 m + 4
+        FB_HIP(hipHostMalloc((void **)&kw->hcol, sizeof(double) * (2 * (m + 2) + 1), hipHostMallocMapped));
+        std::fill(kw->hcol, kw->hcol + 2 * (m + 2) + 1, 0.0);
         FB_HIP(hipHostGetDevicePointer((void **)&kw->hcol_dev, kw->hcol, 0));
         FB_HIP(hipEventCreateWithFlags(&kw->ev_h, hipEventDisableTiming));
     } catch (...) {
@@ -280,11 +282,11 @@ void cgs_dots(KrylovWork *kw, const double *V, int nv, const double *w, double *
     FB_HIP(hipGetLastError());
 }
 
-// |r|^2 into the host column's entry 0 (read after the stream is synchronised)
-void norm2(KrylovWork *kw, const double *r, hipStream_t st)
+// |r|^2 into entry slot of the host column (read after the stream is synchronised)
+void norm2(KrylovWork *kw, const double *r, hipStream_t st, int slot = 0)
 {
     cgs_dots(kw, r, 1, r, kw->part1, st);
-    k_sum_parts<<<1, DOT_BLOCK, sizeof(double), st>>>(kw->part1, kw->nb, 1, kw->hcol_dev);
+    k_sum_parts<<<1, DOT_BLOCK, sizeof(double), st>>>(kw->part1, kw->nb, 1, kw->hcol_dev + slot);
     FB_HIP(hipGetLastError());
 }
 
@@ -359,21 +361,22 @@ void GmresState::start()
     const int64_t n = ctx->n;
     FB_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
     FB_HIP(hipMemcpyAsync(kw->r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    norm2(kw, kw->r, st);
-    FB_HIP(hipStreamSynchronize(st));
-    bnorm = std::sqrt(hbuf[0]);
-    beta = bnorm;
-    if (bnorm == 0.0) {
-        converged = 1;
-        rel = 0.0;
-        true_rel = 0.0;
+    if (s.max_iter <= 0) {  // no iteration: |b| now
+        norm2(kw, kw->r, st);
+        FB_HIP(hipStreamSynchronize(st));
+        bnorm = beta = std::sqrt(hbuf[0]);
+        if (bnorm == 0.0) {
+            converged = 1;
+            rel = true_rel = 0.0;
+        }
         done = true;
         return;
     }
-    if (s.max_iter <= 0) {
-        done = true;
-        return;
-    }
+    // |b| is read with the first Hessenberg column, so the first mat-vec
+    // starts without a round trip to the host (b = 0 is caught there: v_0 is
+    // then not finite, x stays zero)
+    norm2(kw, kw->r, st, 2 * (s.restart + 2));
+    bnorm_known = false;
     begin_cycle();
 }
 
@@ -473,6 +476,17 @@ void GmresState::complete_step()
 {
     const int m = s.restart;
     FB_HIP(hipEventSynchronize(ev_h));
+    if (!bnorm_known) {
+        bnorm_known = true;
+        bnorm = beta = std::sqrt(hbuf[2 * (m + 2)]);
+        g[0] = beta;
+        if (bnorm == 0.0) {
+            converged = 1;
+            rel = true_rel = 0.0;
+            done = true;
+            return;
+        }
+    }
     for (int j = 0; j <= k; ++j)
         H[(size_t)j * m + k] = hbuf[j] + hbuf[m + 2 + j];
     double hn = std::sqrt(hbuf[k + 1]);
