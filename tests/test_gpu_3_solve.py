@@ -130,6 +130,32 @@ def test_solve_parity_stored_near_field(orc, case):
     fb.fmmbem_destroy(ctx)
 
 
+def test_solve_restarts_with_prefetch(orc):
+    """GMRES(6) with the relaxed mixed schedule on the bench configuration
+    (stored near field and M2L operators): several restarts, each resuming the
+    schedule from the true residual, with the next mat-vec's charges (which
+    also normalise the Arnoldi vector), upward pass and near field started
+    ahead inside every cycle, and |b| read with the first column; parity with
+    the oracle at tol 1e-8, the same bits on a second solve, and a zero
+    right-hand side right after it converging at once to x = 0."""
+    from paper_1506_05957_amd import fmmbem as fb
+    announce("restarted relaxed solve, rbc2048, GMRES(6), stored near field and M2L operators")
+    m = MESHES["rbc2048"]()
+    b = syn.ylm_rhs(m, 2, 1)
+    xo = orc.solve(0, m.xyz, m.tri, b, tol=1e-11)[0]
+    ctx = fb.fmmbem_build(m.xyz, m.tri, 0, fb.params(ncrit=64, p_max=12, near_stored=1, m2l_stored=1))
+    sched = fb.schedule(0, restart=6)
+    x, rep = solve(fb, ctx, b, 1e-8, sched)
+    announce(describe(rep, x, xo) + f" restarts={rep['restarts']}")
+    assert rep["converged"] and rep["restarts"] >= 2 and rep["rel_res_true"] <= 1e-7
+    assert rel_l2(x, xo) <= 1e-5
+    x2, rep2 = solve(fb, ctx, b, 1e-8, sched)
+    assert np.array_equal(x, x2) and rep2["iterations"] == rep["iterations"]
+    z, repz = solve(fb, ctx, np.zeros_like(b), 1e-6, sched)
+    assert repz["converged"] and repz["iterations"] == 0 and not z.any()
+    fb.fmmbem_destroy(ctx)
+
+
 @pytest.mark.parametrize("case", ["laplace_sphere_one", "stokes_sphere_u"])
 def test_solve_bench_tolerance(orc, case):
     from paper_1506_05957_amd import fmmbem as fb
