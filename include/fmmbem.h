@@ -103,10 +103,33 @@ typedef struct {
      * real (2 ncoef(p_max))^2 matrix that pass 1 applies, is generated once at
      * build and stored; FP64 mat-vecs stream it through the matrix cores
      * instead of generating it from the translation's harmonics on every
-     * call.  Memory: about 8 (2 ncoef(p_max))^2 bytes per translation (a
-     * sphere of 32768 panels at p_max = 12: 4601 translations, 1.3 GB); see
-     * fmmbem_stats.m2l_op_bytes.  0 (default): generated on the fly. */
+     * call.  Memory: 8 D^2 bytes per translation, D = 2 ncoef(p_max) rounded
+     * up to 16 rows (a sphere of 32768 panels at N_CRIT 64, p_max = 12: 2541
+     * translations, 718 MB); see fmmbem_stats.n_translations and
+     * m2l_op_bytes.  0 (default): generated on the fly. */
     int32_t m2l_stored;
+    /* Quadrature of Sec. 2.3, fixed by the method as built (0 = default;
+     * any other value gives FMMBEM_EINVAL):
+     *   quad_far    4: the degree-3 four-point rule of Eq. 10 on every
+     *               regular panel pair;
+     *   quad_near   25: the 5 x 5 collapsed Gauss-Legendre rule on panels
+     *               closer than near_factor sqrt(2 S_j) to the target;
+     *   near_factor 2.0 (the criterion |x_i - c_j|^2 < 8 S_j). */
+    int32_t quad_far;
+    int32_t quad_near;
+    double near_factor;
+    /* Device memory.  alloc == NULL (default): hipMalloc / hipFree.
+     * Otherwise every device byte the context (and, for a request, the
+     * server) holds comes from alloc(bytes, alloc_user), which returns device
+     * memory of the current device aligned to 256 bytes, or NULL (the call
+     * then fails with FMMBEM_ENOMEM), and goes back through
+     * free(ptr, alloc_user) when the context is destroyed (after the device
+     * is synchronised).  Build-time temporaries use it too.  Both callbacks
+     * may be called from the server's worker thread.  Pinned host memory
+     * (a few KB per context) is not device memory and does not use them. */
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *alloc_user;
 } fmmbem_params;
 
 typedef struct {
@@ -121,10 +144,23 @@ typedef struct {
 
 typedef struct {
     int32_t iterations, restarts, converged;
+    /* restarts forced by a non-finite residual: the step's column is
+     * discarded, the cycle ends with the columns before it and every later
+     * mat-vec of the solve runs in FP64 */
+    int32_t fallbacks;
     double rel_res_implicit;   /* |g_{k+1}| / |b| at exit */
-    double rel_res_true;       /* |b - A x| / |b| with A at p_init in FP64 */
+    /* |b - A x| / |b| with A at p_init in FP64; a solve is converged only
+     * when this is <= tol (an implicit residual at tol with a true residual
+     * above it restarts the solve) */
+    double rel_res_true;
     double t_solve_s;          /* wall time of the solve (host clock, stream synchronised) */
     int64_t matvecs;
+    /* device time of this solve by stage (HIP events, the stages of
+     * fmmbem_set_timing), -1 for a stage that is not timed on the context:
+     * near field (P2P or the stored product), M2L pass 1, the other FMM
+     * stages (charges, P2M, M2M, the M2L sum, L2L, L2P, combine) and the
+     * Krylov kernels (orthogonalisation, update of x, residuals) */
+    double t_p2p_s, t_m2l_s, t_other_fmm_s, t_krylov_s;
     /* caller-owned histories, may be NULL; hist_cap entries each */
     int32_t hist_cap;
     int32_t *p_hist;
@@ -187,20 +223,21 @@ const char *fmmbem_last_error(void);
  * near field; at low orders L2L and L2P run as one kernel per leaf), 4
  * charges (+ the combine when no box pair is far; inside a solve the charges
  * of a prefetched mat-vec also normalise the Arnoldi vector and are counted
- * where they are launched); entry [prec * 5 + stage]
- * holds the launches made in precision
- * prec (FMMBEM_FP64 = 0, FMMBEM_FP32 = 1), FMMBEM_N_STAGES entries in all.
- * t_ms[i] is the total time, launches[i] the number of timed launches and
- * flops[i] the algorithmic flops of those launches: P2P evaluated on the fly
- * counts 12 (Laplace single layer), 18 (double layer) or 30 (Stokes) per
- * source-target pair, the stored near field 2 per stored value (9 values per
- * panel pair for Stokes), M2L 8 ncoef(p)^2 per box pair and channel (the real
- * (2 ncoef(p))^2 operator times a coefficient vector); the other stages
+ * where they are launched); entry [prec * 5 + stage] holds the launches made
+ * in precision prec (FMMBEM_FP64 = 0, FMMBEM_FP32 = 1); entry 10 holds the
+ * Krylov kernels of solves (FP64: Gram-Schmidt dots and update, stand-alone
+ * normalisations, update of x, true residuals); FMMBEM_N_STAGES entries in
+ * all.  t_ms[i] is the total time, launches[i] the number of timed launches
+ * and flops[i] the algorithmic flops of those launches: P2P evaluated on the
+ * fly counts 12 (Laplace single layer), 18 (double layer) or 30 (Stokes) per
+ * source-target pair, the stored near field 2 per stored value (9 values
+ * per panel pair for Stokes), M2L 8 ncoef(p)^2 per box pair and channel (the
+ * real (2 ncoef(p))^2 operator times a coefficient vector); the other stages
  * count 0.  Any output pointer may be NULL. */
-#define FMMBEM_N_STAGES 10
+#define FMMBEM_N_STAGES 11
 int fmmbem_set_timing(fmmbem_ctx_t *ctx, int enabled);
-/* Times only the stages whose bit is set in mask (bit prec * 5 + stage, the
- * entry layout of fmmbem_get_timing); every timed stage records two events on
+/* Times only the stages whose bit is set in mask (bit prec * 5 + stage, or
+ * 10 for the Krylov kernels: the entry layout of fmmbem_get_timing); every timed stage records two events on
  * its stream per mat-vec, so a narrow mask keeps the host work of a timed
  * solve close to that of an untimed one.  0 turns timing off; bits at or past
  * FMMBEM_N_STAGES give FMMBEM_EINVAL. */

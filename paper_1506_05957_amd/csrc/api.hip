@@ -28,7 +28,7 @@ void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev)
     FB_HIP(hipEventRecord(*ev, st));
 }
 
-static void resolve_pending(Timing &T)
+void timing_resolve(Timing &T)
 {
     for (auto &pd : T.pending) {
         FB_HIP(hipEventSynchronize(pd.b));
@@ -58,7 +58,7 @@ void stage_end(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t ev, double
     T.pending.push_back({ev, e2, stage});
     T.flops[stage] += flops;
     if (T.pending.size() > 4096)
-        resolve_pending(T);
+        timing_resolve(T);
 }
 
 }  // namespace fmmbem
@@ -101,6 +101,12 @@ void fmmbem_params_default(fmmbem_params *prm)
     prm->mu = 1.0;
     prm->near_stored = 0;
     prm->m2l_stored = 0;
+    prm->quad_far = 4;
+    prm->quad_near = 25;
+    prm->near_factor = 2.0;
+    prm->alloc = nullptr;
+    prm->free = nullptr;
+    prm->alloc_user = nullptr;
 }
 
 void fmmbem_schedule_default(fmmbem_schedule *s, int kernel)
@@ -140,6 +146,12 @@ static void validate_params(const fmmbem_params *p)
     FB_REQUIRE(p->mu > 0.0 && std::isfinite(p->mu), FMMBEM_EINVAL, "mu must be positive");
     FB_REQUIRE(p->near_stored == 0 || p->near_stored == 1, FMMBEM_EINVAL, "near_stored must be 0 or 1");
     FB_REQUIRE(p->m2l_stored == 0 || p->m2l_stored == 1, FMMBEM_EINVAL, "m2l_stored must be 0 or 1");
+    FB_REQUIRE(p->quad_far == 0 || p->quad_far == 4, FMMBEM_EINVAL, "quad_far: only the 4-point rule is built");
+    FB_REQUIRE(p->quad_near == 0 || p->quad_near == 25, FMMBEM_EINVAL, "quad_near: only the 25-point rule is built");
+    FB_REQUIRE(p->near_factor == 0.0 || p->near_factor == 2.0, FMMBEM_EINVAL,
+               "near_factor: only 2 (|x - c_j|^2 < 8 S_j) is built");
+    FB_REQUIRE((p->alloc == nullptr) == (p->free == nullptr), FMMBEM_EINVAL,
+               "alloc and free must be given together");
 }
 
 int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *params, void *hip_stream,
@@ -161,6 +173,7 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
     try {
         ctx->kernel = kernel;
         ctx->prm = prm;
+        ctx->arena.al = DevAlloc{prm.alloc, prm.free, prm.alloc_user};
         FB_HIP(hipGetDevice(&ctx->device));
         ctx->nt = mesh->n_triangles;
         ctx->nsrc = 4 * ctx->nt;
@@ -246,25 +259,18 @@ int fmmbem_solve(const fmmbem_mesh *mesh, const double *bc_host, int kernel, dou
     int rc = fmmbem_build(mesh, kernel, &prm, nullptr, &ctx);
     if (rc != FMMBEM_OK)
         return rc;
-    double *b = nullptr, *x = nullptr;
     try {
         validate_schedule(ctx, s, tol);
-        FB_HIP(hipMalloc(&b, sizeof(double) * ctx->n));
-        FB_HIP(hipMalloc(&x, sizeof(double) * ctx->n));
+        // the device copies of bc and x belong to the context (its allocator)
+        double *b = ctx->arena.alloc<double>(ctx->n);
+        double *x = ctx->arena.alloc<double>(ctx->n);
         FB_HIP(hipMemcpy(b, bc_host, sizeof(double) * ctx->n, hipMemcpyHostToDevice));
         rc = run_solve(ctx, b, tol, s, x, report, nullptr);
         FB_HIP(hipMemcpy(x_host, x, sizeof(double) * ctx->n, hipMemcpyDeviceToHost));
     } catch (...) {
-        (void)hipDeviceSynchronize();
-        if (b)
-            (void)hipFree(b);
-        if (x)
-            (void)hipFree(x);
         fmmbem_destroy(ctx);
         throw;
     }
-    (void)hipFree(b);
-    (void)hipFree(x);
     fmmbem_destroy(ctx);
     return rc;
     API_END
@@ -339,7 +345,7 @@ int fmmbem_get_timing(fmmbem_ctx_t *ctx, double *t_ms, int64_t *launches, double
 {
     API_BEGIN
     FB_REQUIRE(ctx, FMMBEM_EINVAL, "null argument");
-    resolve_pending(ctx->timing);
+    timing_resolve(ctx->timing);
     for (int s = 0; s < FMMBEM_N_STAGES; ++s) {
         if (t_ms)
             t_ms[s] = ctx->timing.t_ms[s];

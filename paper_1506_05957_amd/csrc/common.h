@@ -99,26 +99,64 @@ static_assert(4 + DOWN_LEAF_MAXC + 1 <= LEAF_REC, "leaf record");
 // sources per P2P chunk (one LDS tile of a wave)
 constexpr int P2P_TILE = 128;
 
-// Device buffers owned by a context; freed in reverse order on destruction.
-struct DevArena {
-    std::vector<void *> ptrs;
-    int64_t bytes = 0;
-    template <typename T> T *alloc(size_t n) {
+// Where device memory comes from: the caller's callbacks (fmmbem_params
+// alloc/free/alloc_user) or, when alloc is null, hipMalloc/hipFree.
+struct DevAlloc {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*free)(void *, void *) = nullptr;
+    void *user = nullptr;
+    void *get(size_t b) const
+    {
         void *p = nullptr;
-        size_t b = n * sizeof(T);
-        if (b == 0)
-            b = 16;
+        if (alloc) {
+            p = alloc(b, user);
+            if (!p)
+                throw Error(FMMBEM_ENOMEM, "caller allocator returned NULL for " + std::to_string(b) + " bytes");
+            if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+                free(p, user);
+                throw Error(FMMBEM_EINVAL, "caller allocator returned memory not aligned to 256 bytes");
+            }
+            return p;
+        }
         hipError_t e = hipMalloc(&p, b);
         if (e != hipSuccess)
             throw Error(FMMBEM_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed: " +
                                            hipGetErrorString(e));
+        return p;
+    }
+    void put(void *p) const
+    {
+        if (!p)
+            return;
+        if (alloc)
+            free(p, user);
+        else
+            (void)hipFree(p);
+    }
+};
+
+// Device buffers owned by a context; freed in reverse order on destruction.
+struct DevArena {
+    DevAlloc al;
+    std::vector<void *> ptrs;
+    int64_t bytes = 0;
+    DevArena() = default;
+    explicit DevArena(const DevAlloc &a) : al(a) {}
+    DevArena(const DevArena &) = delete;
+    DevArena &operator=(const DevArena &) = delete;
+    template <typename T> T *alloc(size_t n) {
+        size_t b = n * sizeof(T);
+        if (b == 0)
+            b = 16;
+        ptrs.reserve(ptrs.size() + 1);  // a throw after the allocation would leak it
+        void *p = al.get(b);
         ptrs.push_back(p);
         bytes += (int64_t)b;
         return static_cast<T *>(p);
     }
     void release() {
         for (auto it = ptrs.rbegin(); it != ptrs.rend(); ++it)
-            (void)hipFree(*it);
+            al.put(*it);
         ptrs.clear();
         bytes = 0;
     }
@@ -251,7 +289,8 @@ struct NearMatrix {
     Correction rest;                // corrections whose pair has no stored block
 };
 
-// GMRES workspace, one per context (krylov.hip)
+// GMRES workspace (krylov.hip): one per context from its allocator, or a
+// view of the library's static scratch array (the allocation-free solve)
 struct KrylovWork {
     int m = 0;
     int64_t n = 0;
@@ -263,15 +302,19 @@ struct KrylovWork {
     double *part1 = nullptr; // [m+1][nb] per-block partials of the first Gram-Schmidt pass
     double *part2 = nullptr; // [m+1][nb] the second pass
     double *partn = nullptr; // [nb] |w|^2
+    double *y = nullptr;     // [m+1] least-squares solution, copied from hcol
     // Hessenberg column in pinned, device-mapped host memory, written by the
-    // kernels directly: h1[0..k], |w|^2 at k + 1, h2 at m + 2 + j
-    double *hcol = nullptr;      // host view, [2*(m+2)]
+    // kernels directly: h1[0..k], |w|^2 at k + 1, h2 at m + 2 + j, |b|^2 at
+    // 2 (m + 2); the least-squares solution y (host-written) after it
+    double *hcol = nullptr;      // host view, [hcol_len(m)]
     double *hcol_dev = nullptr;  // the same memory, device view
     hipEvent_t ev_h = nullptr;   // the column of the last step is complete
-    double *y = nullptr;     // [m+1]
+    bool owned = true;           // V ... hcol, ev_h belong to this workspace
     DevArena arena;
 };
-
+inline int64_t hcol_len(int m) { return 2 * (int64_t)(m + 2) + 1 + (m + 1); }
+// row blocks and rows per thread of the Arnoldi kernels for n rows
+void krylov_blocks(int64_t n, int *nb, int *rpt);
 
 }  // namespace fmmbem
 
@@ -322,8 +365,11 @@ struct Sched {
 // GMRES(m) as a state machine so that a request loop can interleave solves:
 // start(); while (!done) { enqueue_step(); complete_step(); }
 // enqueue_step only enqueues device work on the solve's stream (mat-vec,
-// CGS2, asynchronous copy of the Hessenberg column to pinned memory);
-// complete_step waits for it and applies the Givens update on the host.
+// CGS2, the Hessenberg column into pinned memory); complete_step waits for it
+// and applies the Givens update on the host.  The host arrays (Hessenberg
+// matrix, rotations, right-hand side) come from hostw when given (4 m + 2 +
+// (m + 1) m doubles), else from the state's own vector; the histories go
+// straight to rep's caller-owned arrays.
 struct GmresState {
     fmmbem_ctx *ctx;
     const double *b;
@@ -332,22 +378,25 @@ struct GmresState {
     double tol;
     hipStream_t st;
     KrylovWork *kw = nullptr;
-    std::vector<double> H, cs, sn, g, yv;
+    fmmbem_report *rep = nullptr;
+    std::vector<double> host_own;
+    double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *yv = nullptr;
     double *hbuf = nullptr;     // kw->hcol
     hipEvent_t ev_h = nullptr;  // kw->ev_h
-    int it = 0, restarts = 0, converged = 0, k = 0;
+    int it = 0, restarts = 0, converged = 0, k = 0, fallbacks = 0;
     int64_t matvecs = 0;
     double bnorm = 0, beta = 0, rel = 1, true_rel = 1, rho_prev = 1;
     double rho_prev2 = -1;  // the residual before rho_prev, < 0 if none
     bool done = false;
     bool bnorm_known = true;  // false from the start until the first column is read
+    bool fp64_only = false;   // after a non-finite residual: every later mat-vec in FP64
     Sched cur{0, 0};
-    std::vector<int32_t> p_hist;
-    std::vector<uint8_t> prec_hist;
-    std::vector<double> res_hist;
+    double t_stage0[FMMBEM_N_STAGES] = {0};  // the context's stage times at the start
     std::chrono::steady_clock::time_point t0, t1;
 
-    GmresState(fmmbem_ctx *c, const double *b, double tol, const fmmbem_schedule *s, double *x, hipStream_t st);
+    static size_t host_doubles(int m) { return 4 * (size_t)m + 2 + (size_t)(m + 1) * m; }
+    GmresState(fmmbem_ctx *c, const double *b, double tol, const fmmbem_schedule *s, double *x, hipStream_t st,
+               fmmbem_report *rep = nullptr, KrylovWork *kw_given = nullptr, double *hostw = nullptr);
     ~GmresState();
     GmresState(const GmresState &) = delete;
     GmresState &operator=(const GmresState &) = delete;
@@ -360,6 +409,7 @@ struct GmresState {
     void begin_cycle();
     void end_cycle();
     void record(int p, int prec, double r);
+    void drain_prefetch();
 };
 
 void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream_t st);
@@ -384,8 +434,11 @@ void build_m2l_operators(fmmbem_ctx *ctx, hipStream_t st);
 void launch_near_stored(fmmbem_ctx *ctx, int prec, hipStream_t st);
 int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
               fmmbem_report *rep, hipStream_t st);
+// x[0..n) = 0 by a kernel (no memset node in a caller's capture)
+void fill_zero(double *x, int64_t n, hipStream_t st);
 void free_krylov(fmmbem_ctx *ctx);
-// timing helpers (api.hip)
+// timing helpers (api.hip); timing_resolve reads every pending event pair
+void timing_resolve(Timing &T);
 void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev);
 void stage_end(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t ev, double flops = 0.0);
 // rules (rules.cpp): Gauss-Legendre by Golub-Welsch, near rule tables

@@ -1923,7 +1923,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
     } else {
         hipEvent_t ev4;
         stage_begin(ctx, SO + 4, st, &ev4);
-        FB_HIP(hipMemsetAsync(ctx->y_far, 0, sizeof(double) * ctx->n, st));
+        fill_zero(ctx->y_far, ctx->n, st);
         FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         k_combine<KIND><<<grid_for(nt, 64), 64, 0, st>>>(nt, ca, ctx->y_far);
         FB_HIP(hipGetLastError());

@@ -7,8 +7,9 @@
 // update (a few hundred flops) run in FP64.  The rotated residual
 // rho_k = |g_{k+1}| / |b| picks the order and precision of the next mat-vec
 // (Eq. 17, 19).  A restart and the final check form the true residual with the
-// accurate operator (p_init, FP64).  All reductions use a fixed order, so a
-// solve is bitwise reproducible.
+// accurate operator (p_init, FP64); the solve stops only when that residual
+// meets the tolerance.  All reductions use a fixed order, so a solve is
+// bitwise reproducible.
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -223,13 +224,22 @@ __global__ void k_sub(int64_t n, const double *__restrict__ b, const double *__r
         r[i] = b[i] - a[i];
 }
 
+__global__ void k_zero(int64_t n, double *__restrict__ x)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        x[i] = 0.0;
+}
+
 void release_work(KrylovWork *kw)
 {
-    kw->arena.release();
-    if (kw->hcol)
-        (void)hipHostFree(kw->hcol);
-    if (kw->ev_h)
-        (void)hipEventDestroy(kw->ev_h);
+    if (kw->owned) {
+        kw->arena.release();
+        if (kw->hcol)
+            (void)hipHostFree(kw->hcol);
+        if (kw->ev_h)
+            (void)hipEventDestroy(kw->ev_h);
+    }
     delete kw;
 }
 
@@ -244,12 +254,11 @@ KrylovWork *get_work(fmmbem_ctx *ctx, int m)
         ctx->kw = nullptr;
     }
     kw = new KrylovWork();
+    kw->arena.al = ctx->arena.al;
     try {
         kw->m = m;
         kw->n = ctx->n;
-        kw->rpt = (int)std::max<int64_t>(1, (ctx->n + (int64_t)DOT_BLOCK * DOT_MAX_BLOCKS - 1) /
-                                               ((int64_t)DOT_BLOCK * DOT_MAX_BLOCKS));
-        kw->nb = (int)((ctx->n + (int64_t)DOT_BLOCK * kw->rpt - 1) / ((int64_t)DOT_BLOCK * kw->rpt));
+        krylov_blocks(ctx->n, &kw->nb, &kw->rpt);
         kw->V = kw->arena.alloc<double>((size_t)(m + 1) * ctx->n);
         kw->w = kw->arena.alloc<double>(ctx->n);
         kw->r = kw->arena.alloc<double>(ctx->n);
@@ -257,10 +266,8 @@ KrylovWork *get_work(fmmbem_ctx *ctx, int m)
         kw->part2 = kw->arena.alloc<double>((size_t)(m + 1) * kw->nb);
         kw->partn = kw->arena.alloc<double>(kw->nb);
         kw->y = kw->arena.alloc<double>(m + 1);
-        // the Hessenberg column (h1 and |w|^2 at [0, m + 2), h2 at [m + 2,
-        // 2 m + 4)) and |b|^2 of the start at 2 m + 4
-        FB_HIP(hipHostMalloc((void **)&kw->hcol, sizeof(double) * (2 * (m + 2) + 1), hipHostMallocMapped));
-        std::fill(kw->hcol, kw->hcol + 2 * (m + 2) + 1, 0.0);
+        FB_HIP(hipHostMalloc((void **)&kw->hcol, sizeof(double) * hcol_len(m), hipHostMallocMapped));
+        std::fill(kw->hcol, kw->hcol + hcol_len(m), 0.0);
         FB_HIP(hipHostGetDevicePointer((void **)&kw->hcol_dev, kw->hcol, 0));
         FB_HIP(hipEventCreateWithFlags(&kw->ev_h, hipEventDisableTiming));
     } catch (...) {
@@ -290,7 +297,7 @@ void norm2(KrylovWork *kw, const double *r, hipStream_t st, int slot = 0)
     FB_HIP(hipGetLastError());
 }
 
-Sched choose(const fmmbem_schedule *s, double rho, double eta)
+Sched choose(const fmmbem_schedule *s, double rho, double eta, bool fp64_only = false)
 {
     double rm = std::min(rho, 1.0);
     double eps = std::min(eta / rm, 1.0);
@@ -302,12 +309,27 @@ Sched choose(const fmmbem_schedule *s, double rho, double eta)
     }
     p = std::max(s->p_min, std::min(s->p_init, p));
     int prec = FMMBEM_FP64;
-    if (s->mixed && s->rule != FMMBEM_FIXED && eps >= s->fp32_eps && p <= P_MAX_FP32)
+    if (s->mixed && !fp64_only && s->rule != FMMBEM_FIXED && eps >= s->fp32_eps && p <= P_MAX_FP32)
         prec = FMMBEM_FP32;
     return {p, prec};
 }
 
 }  // namespace
+
+void krylov_blocks(int64_t n, int *nb, int *rpt)
+{
+    *rpt = (int)std::max<int64_t>(1, (n + (int64_t)DOT_BLOCK * DOT_MAX_BLOCKS - 1) /
+                                         ((int64_t)DOT_BLOCK * DOT_MAX_BLOCKS));
+    *nb = (int)((n + (int64_t)DOT_BLOCK * *rpt - 1) / ((int64_t)DOT_BLOCK * *rpt));
+}
+
+void fill_zero(double *x, int64_t n, hipStream_t st)
+{
+    if (n <= 0)
+        return;
+    k_zero<<<grid_for(n, 256), 256, 0, st>>>(n, x);
+    FB_HIP(hipGetLastError());
+}
 
 void free_krylov(fmmbem_ctx *ctx)
 {
@@ -318,39 +340,81 @@ void free_krylov(fmmbem_ctx *ctx)
 }
 
 GmresState::GmresState(fmmbem_ctx *c, const double *b_, double tol_, const fmmbem_schedule *s_, double *x_,
-                       hipStream_t st_)
-    : ctx(c), b(b_), x(x_), s(*s_), tol(tol_), st(st_)
+                       hipStream_t st_, fmmbem_report *rep_, KrylovWork *kw_given, double *hostw)
+    : ctx(c), b(b_), x(x_), s(*s_), tol(tol_), st(st_), rep(rep_)
 {
     const int m = s.restart;
-    kw = get_work(ctx, m);
-    H.assign((size_t)(m + 1) * m, 0.0);
-    cs.assign(m, 0.0);
-    sn.assign(m, 0.0);
-    g.assign(m + 1, 0.0);
-    yv.assign(m, 0.0);
+    kw = kw_given ? kw_given : get_work(ctx, m);
+    FB_REQUIRE(kw->m >= m && kw->n == ctx->n, FMMBEM_EINTERNAL, "Krylov workspace too small");
+    if (!hostw) {
+        host_own.assign(host_doubles(m), 0.0);
+        hostw = host_own.data();
+    } else {
+        std::fill(hostw, hostw + host_doubles(m), 0.0);
+    }
+    cs = hostw;
+    sn = cs + m;
+    g = sn + m;
+    yv = g + (m + 1);
+    H = yv + (m + 1);  // [(m + 1) m]
     hbuf = kw->hcol;
     ev_h = kw->ev_h;
+    if (ctx->timing.mask) {
+        timing_resolve(ctx->timing);
+        std::copy(ctx->timing.t_ms, ctx->timing.t_ms + FMMBEM_N_STAGES, t_stage0);
+    }
 }
 
-GmresState::~GmresState() = default;
+GmresState::~GmresState()
+{
+    // a solve left early (an error, or b = 0) may still have a prefetched
+    // mat-vec in flight: let it end before the context is used again
+    if (ctx->spec_x || ctx->near_pending) {
+        if (ctx->near_pending)
+            (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
+        (void)hipStreamSynchronize(st);
+        ctx->spec_x = nullptr;
+        ctx->spec_prec = ctx->spec_up_p = -1;
+        ctx->spec_near = false;
+        ctx->near_pending = false;
+    }
+}
+
+// wait for the prefetched charges, upward pass and near field, and drop them
+void GmresState::drain_prefetch()
+{
+    if (ctx->near_pending)
+        FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    FB_HIP(hipStreamSynchronize(st));
+    ctx->spec_x = nullptr;
+    ctx->spec_prec = ctx->spec_up_p = -1;
+    ctx->spec_near = false;
+    ctx->near_pending = false;
+}
 
 void GmresState::record(int p, int prec, double r)
 {
-    if (it < (int)p_hist.size())
+    if (!rep || it >= rep->hist_cap)
         return;
-    p_hist.push_back(p);
-    prec_hist.push_back((uint8_t)prec);
-    res_hist.push_back(r);
+    if (rep->p_hist)
+        rep->p_hist[it] = p;
+    if (rep->prec_hist)
+        rep->prec_hist[it] = (uint8_t)prec;
+    if (rep->res_hist)
+        rep->res_hist[it] = r;
 }
 
 void GmresState::begin_cycle()
 {
     // v0 = r / beta
     const int64_t n = ctx->n;
+    hipEvent_t ev;
+    stage_begin(ctx, 10, st, &ev);
     cgs_dots(kw, kw->r, 1, kw->r, kw->part1, st);
     k_normalize<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->rpt, kw->r, kw->part1, kw->nb, kw->V, nullptr);
     FB_HIP(hipGetLastError());
-    std::fill(g.begin(), g.end(), 0.0);
+    stage_end(ctx, 10, st, ev);
+    std::fill(g, g + s.restart + 1, 0.0);
     g[0] = beta;
     k = 0;
 }
@@ -359,19 +423,8 @@ void GmresState::start()
 {
     t0 = std::chrono::steady_clock::now();
     const int64_t n = ctx->n;
-    FB_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+    fill_zero(x, n, st);
     FB_HIP(hipMemcpyAsync(kw->r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    if (s.max_iter <= 0) {  // no iteration: |b| now
-        norm2(kw, kw->r, st);
-        FB_HIP(hipStreamSynchronize(st));
-        bnorm = beta = std::sqrt(hbuf[0]);
-        if (bnorm == 0.0) {
-            converged = 1;
-            rel = true_rel = 0.0;
-        }
-        done = true;
-        return;
-    }
     // |b| is read with the first Hessenberg column, so the first mat-vec
     // starts without a round trip to the host (b = 0 is caught there: v_0 is
     // then not finite, x stays zero)
@@ -384,10 +437,12 @@ void GmresState::enqueue_step()
 {
     const int m = s.restart;
     const int64_t n = ctx->n;
-    cur = choose(&s, rho_prev, tol);
+    cur = choose(&s, rho_prev, tol, fp64_only);
     double *vk = kw->V + (int64_t)k * n, *vn = kw->V + (int64_t)(k + 1) * n;
     run_matvec(ctx, cur.p, cur.prec, vk, kw->w, st);
     ++matvecs;
+    hipEvent_t ev;
+    stage_begin(ctx, 10, st, &ev);
     cgs_dots(kw, kw->V, k + 1, kw->w, kw->part1, st);
     cgs_dots(kw, kw->V, k + 1, kw->w, kw->part2, st, kw->part1);
     // h1[0..k], |w|^2 at k + 1 and h2[0..k] at m + 2 go straight to the host column
@@ -399,29 +454,33 @@ void GmresState::enqueue_step()
     // host waits for the column.  The precision follows the schedule at a residual extrapolated
     // from the last two (a hundredth of the last one when there is no ratio
     // yet); nothing is started where the extrapolated residual already meets
-    // the tolerance or the cycle ends.  The upward pass takes at most this
+    // the tolerance or the cycle ends, nor before |b| is known (b = 0 would
+    // leave it running).  The upward pass takes at most this
     // mat-vec's order (the GMRES residual never grows within a cycle and the
     // order never falls as the residual grows, so the next order is at most
     // this one) and at most two above the order at the extrapolated residual;
     // a mat-vec of a higher order than the prefetched pass runs its own.
     int pre_prec = -1, p_up = 0;
-    if (k + 1 < m && it + 1 < s.max_iter) {
+    if (bnorm_known && k + 1 < m && it + 1 < s.max_iter) {
         const double ratio = rho_prev2 > 0.0 ? std::min(1.0, rho_prev / rho_prev2) : 0.01;
         const double rho_next = rho_prev * ratio;
         if (rho_next > tol) {
-            const Sched nx = choose(&s, rho_next, tol);
+            const Sched nx = choose(&s, rho_next, tol, fp64_only);
             pre_prec = nx.prec;
             p_up = std::min(cur.p, nx.p + 2);
             if (pre_prec == FMMBEM_FP32)
                 p_up = std::min(p_up, P_MAX_FP32);
-            // v_{k+1} = w / |w| (and |w|^2 into the host column) is written
-            // by these charges
-            prefetch_charges(ctx, pre_prec, vn, st, NormIn{kw->w, kw->partn, kw->nb, kw->hcol_dev + (k + 1)});
         }
     }
     if (pre_prec < 0) {
         k_normalize<<<kw->nb, DOT_BLOCK, 0, st>>>(n, kw->rpt, kw->w, kw->partn, kw->nb, vn, kw->hcol_dev + (k + 1));
         FB_HIP(hipGetLastError());
+    }
+    stage_end(ctx, 10, st, ev);
+    if (pre_prec >= 0) {
+        // v_{k+1} = w / |w| (and |w|^2 into the host column) is written
+        // by these charges
+        prefetch_charges(ctx, pre_prec, vn, st, NormIn{kw->w, kw->partn, kw->nb, kw->hcol_dev + (k + 1)});
     }
     FB_HIP(hipEventRecord(ev_h, st));
     if (pre_prec >= 0) {
@@ -437,29 +496,41 @@ void GmresState::enqueue_step()
 void GmresState::end_cycle()
 {
     const int m = s.restart;
-    (void)m;
     const int64_t n = ctx->n;
     for (int i = k - 1; i >= 0; --i) {
         double sum = g[i];
         for (int j = i + 1; j < k; ++j)
-            sum -= H[(size_t)i * s.restart + j] * yv[j];
-        yv[i] = sum / H[(size_t)i * s.restart + i];
+            sum -= H[(size_t)i * m + j] * yv[j];
+        yv[i] = sum / H[(size_t)i * m + i];
     }
+    hipEvent_t ev;
+    stage_begin(ctx, 10, st, &ev);
     if (k > 0) {
-        FB_HIP(hipMemcpyAsync(kw->y, yv.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+        // y through the pinned column buffer: an asynchronous copy from
+        // pageable memory would stage it and block the host
+        double *yh = hbuf + 2 * (m + 2) + 1;
+        std::copy(yv, yv + k, yh);
+        FB_HIP(hipMemcpyAsync(kw->y, yh, sizeof(double) * k, hipMemcpyHostToDevice, st));
         k_xupdate<<<grid_for(n, 256), 256, 0, st>>>(n, kw->V, n, k, kw->y, x);
         FB_HIP(hipGetLastError());
     }
+    stage_end(ctx, 10, st, ev);
     // true residual with the accurate operator
     run_matvec(ctx, s.p_init, FMMBEM_FP64, x, kw->w, st);
     ++matvecs;
+    stage_begin(ctx, 10, st, &ev);
     k_sub<<<grid_for(n, 256), 256, 0, st>>>(n, b, kw->w, kw->r);
     FB_HIP(hipGetLastError());
     norm2(kw, kw->r, st);
+    stage_end(ctx, 10, st, ev);
     FB_HIP(hipStreamSynchronize(st));
     beta = std::sqrt(hbuf[0]);
     true_rel = beta / bnorm;
-    if (rel <= tol || true_rel <= tol) {
+    FB_REQUIRE(std::isfinite(true_rel), FMMBEM_EINTERNAL, "non-finite true residual (FP64, p_init)");
+    // converged only by the true residual: with relaxed products the implicit
+    // residual can reach tol while the true one has not; then the solve
+    // restarts from the true residual
+    if (true_rel <= tol) {
         converged = 1;
         done = true;
     } else if (it >= s.max_iter) {
@@ -479,11 +550,13 @@ void GmresState::complete_step()
     if (!bnorm_known) {
         bnorm_known = true;
         bnorm = beta = std::sqrt(hbuf[2 * (m + 2)]);
+        FB_REQUIRE(std::isfinite(bnorm), FMMBEM_EINVAL, "right-hand side is not finite");
         g[0] = beta;
         if (bnorm == 0.0) {
             converged = 1;
             rel = true_rel = 0.0;
             done = true;
+            drain_prefetch();
             return;
         }
     }
@@ -491,6 +564,23 @@ void GmresState::complete_step()
         H[(size_t)j * m + k] = hbuf[j] + hbuf[m + 2 + j];
     double hn = std::sqrt(hbuf[k + 1]);
     H[(size_t)(k + 1) * m + k] = hn;
+    bool finite = std::isfinite(hn);
+    for (int j = 0; j <= k; ++j)
+        finite = finite && std::isfinite(H[(size_t)j * m + k]);
+    if (!finite) {
+        // a non-finite column (an FP32 range overflow in the mat-vec): it is
+        // discarded, the cycle ends with the k columns before it (x, the true
+        // residual) and the solve restarts with every later mat-vec in FP64;
+        // the same in FP64 cannot be recovered
+        FB_REQUIRE(cur.prec == FMMBEM_FP32 && !fp64_only, FMMBEM_EINTERNAL,
+                   "non-finite Hessenberg column in an FP64 step");
+        record(cur.p, cur.prec, std::nan(""));
+        ++it;
+        ++fallbacks;
+        fp64_only = true;
+        end_cycle();
+        return;
+    }
     for (int j = 0; j < k; ++j) {
         double a = H[(size_t)j * m + k], c2 = H[(size_t)(j + 1) * m + k];
         H[(size_t)j * m + k] = cs[j] * a + sn[j] * c2;
@@ -515,37 +605,47 @@ void GmresState::complete_step()
         end_cycle();
 }
 
-void GmresState::fill_report(fmmbem_report *rep) const
+void GmresState::fill_report(fmmbem_report *r) const
 {
-    if (!rep)
+    if (!r)
         return;
-    rep->iterations = it;
-    rep->restarts = restarts;
-    rep->converged = converged;
-    rep->rel_res_implicit = rel;
-    rep->rel_res_true = true_rel;
-    rep->matvecs = matvecs;
-    rep->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
-    for (int i = 0; i < rep->hist_cap && i < (int)p_hist.size(); ++i) {
-        if (rep->p_hist)
-            rep->p_hist[i] = p_hist[i];
-        if (rep->prec_hist)
-            rep->prec_hist[i] = prec_hist[i];
-        if (rep->res_hist)
-            rep->res_hist[i] = res_hist[i];
+    r->iterations = it;
+    r->restarts = restarts;
+    r->converged = converged;
+    r->fallbacks = fallbacks;
+    r->rel_res_implicit = rel;
+    r->rel_res_true = true_rel;
+    r->matvecs = matvecs;
+    r->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
+    // per-stage device time of this solve (timed stages only)
+    double t[4] = {0, 0, 0, 0};
+    bool timed[4] = {false, false, false, false};
+    const Timing &T = ctx->timing;
+    for (int i = 0; i < FMMBEM_N_STAGES; ++i) {
+        const int grp = i == 10 ? 3 : (i % 5 == 0 ? 0 : i % 5 == 1 ? 1 : 2);
+        if ((T.mask >> i) & 1u) {
+            timed[grp] = true;
+            t[grp] += (T.t_ms[i] - t_stage0[i]) * 1e-3;
+        }
     }
+    r->t_p2p_s = timed[0] ? t[0] : -1.0;
+    r->t_m2l_s = timed[1] ? t[1] : -1.0;
+    r->t_other_fmm_s = timed[2] ? t[2] : -1.0;
+    r->t_krylov_s = timed[3] ? t[3] : -1.0;
 }
 
 int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x, fmmbem_report *rep,
               hipStream_t st)
 {
-    GmresState G(ctx, b, tol, s, x, st);
+    GmresState G(ctx, b, tol, s, x, st, rep);
     G.start();
     while (!G.done) {
         G.enqueue_step();
         G.complete_step();
     }
     G.t1 = std::chrono::steady_clock::now();
+    if (ctx->timing.mask)
+        timing_resolve(ctx->timing);
     G.fill_report(rep);
     return G.converged ? FMMBEM_OK : FMMBEM_ENOCONV;
 }

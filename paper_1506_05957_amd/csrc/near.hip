@@ -225,7 +225,7 @@ void build_correction(fmmbem_ctx *ctx, hipStream_t st)
     Tree &T = ctx->tree;
     Geometry &G = ctx->geo;
     Correction &C = ctx->corr;
-    DevArena tmp;
+    DevArena tmp(ctx->arena.al);
     try {
         RuleTables R;
         near_rule_table(5, R.nb, R.nw);

@@ -263,7 +263,7 @@ void fold_corrections(fmmbem_ctx *ctx, const std::vector<int4> &units, const std
         FB_HIP(hipMemcpyAsync(Rr.val, rval.data(), sizeof(double) * rval.size(), hipMemcpyHostToDevice, st));
     }
     if (!dst.empty()) {
-        DevArena tmp;
+        DevArena tmp(ctx->arena.al);
         try {
             int64_t *d_dst = tmp.alloc<int64_t>(dst.size());
             int32_t *d_step = tmp.alloc<int32_t>(step.size());

@@ -114,11 +114,7 @@ struct fmmbem_server {
             fmmbem_destroy(r->ctx);
             r->ctx = nullptr;
         }
-        if (r->d_b)
-            (void)hipFree(r->d_b);
-        if (r->d_x)
-            (void)hipFree(r->d_x);
-        r->d_b = r->d_x = nullptr;
+        r->d_b = r->d_x = nullptr;  // held by the context's arena
         r->info.finish_s = now();
         std::lock_guard<std::mutex> lk(mu);
         used_bytes -= r->est_bytes;
@@ -138,8 +134,8 @@ struct fmmbem_server {
                 finish(r, rc);
                 return false;
             }
-            FB_HIP(hipMalloc(&r->d_b, sizeof(double) * r->ctx->n));
-            FB_HIP(hipMalloc(&r->d_x, sizeof(double) * r->ctx->n));
+            r->d_b = r->ctx->arena.alloc<double>(r->ctx->n);
+            r->d_x = r->ctx->arena.alloc<double>(r->ctx->n);
             FB_HIP(hipMemcpyAsync(r->d_b, r->bc.data(), sizeof(double) * r->ctx->n, hipMemcpyHostToDevice, st));
             r->gm.reset(new GmresState(r->ctx, r->d_b, r->tol, &r->sched, r->d_x, st));
             r->gm->start();

@@ -358,7 +358,7 @@ void build_translations(fmmbem_ctx *ctx, hipStream_t st)
     build_level_plan(ctx, st);
     if (n == 0)
         return;
-    DevArena tmp;
+    DevArena tmp(ctx->arena.al);
     try {
         uint64_t *key = tmp.alloc<uint64_t>(n), *key_sorted = tmp.alloc<uint64_t>(n);
         int32_t *idx = tmp.alloc<int32_t>(n);

@@ -473,7 +473,7 @@ void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream
     Tree &T = ctx->tree;
     Geometry &G = ctx->geo;
     DevArena &A = ctx->arena;
-    DevArena tmp;  // build-time scratch
+    DevArena tmp(ctx->arena.al);  // build-time scratch
     try {
         T.nt = nt;
         // ---- upload mesh, caller-order geometry

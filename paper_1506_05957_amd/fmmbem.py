@@ -24,9 +24,9 @@ LAPLACE, STOKES, LAPLACE_DL = 0, 1, 2  # single layer, Stokes single layer, 1/2 
 FP64, FP32 = 0, 1
 FIXED, RELAX_SHIFT, RELAX_BF = 0, 1, 2
 P_MAX, P_MAX_FP32 = 20, 14
-N_STAGES = 10
+N_STAGES = 11
 STAGES = tuple(f"{s}_{pr}" for pr in ("fp64", "fp32")
-               for s in ("p2p", "m2l", "p2m_m2m", "l2l_l2p", "charges_correction"))
+               for s in ("p2p", "m2l", "p2m_m2m", "l2l_l2p", "charges_correction")) + ("krylov",)
 
 c_i32, c_i64, c_d, c_u8, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint8, ctypes.c_void_p
 P = ctypes.POINTER
@@ -36,9 +36,14 @@ class fmmbem_mesh(ctypes.Structure):
     _fields_ = [("n_vertices", c_i64), ("n_triangles", c_i64), ("xyz", P(c_d)), ("tri", P(c_i32))]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_vp, ctypes.c_size_t, c_vp)
+FREE_FN = ctypes.CFUNCTYPE(None, c_vp, c_vp)
+
+
 class fmmbem_params(ctypes.Structure):
     _fields_ = [("theta", c_d), ("ncrit", c_i32), ("p_max", c_i32), ("mu", c_d), ("near_stored", c_i32),
-                ("m2l_stored", c_i32)]
+                ("m2l_stored", c_i32), ("quad_far", c_i32), ("quad_near", c_i32), ("near_factor", c_d),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", c_vp)]
 
 
 class fmmbem_schedule(ctypes.Structure):
@@ -47,9 +52,10 @@ class fmmbem_schedule(ctypes.Structure):
 
 
 class fmmbem_report(ctypes.Structure):
-    _fields_ = [("iterations", c_i32), ("restarts", c_i32), ("converged", c_i32), ("rel_res_implicit", c_d),
-                ("rel_res_true", c_d), ("t_solve_s", c_d), ("matvecs", c_i64), ("hist_cap", c_i32),
-                ("p_hist", P(c_i32)), ("prec_hist", P(c_u8)), ("res_hist", P(c_d))]
+    _fields_ = [("iterations", c_i32), ("restarts", c_i32), ("converged", c_i32), ("fallbacks", c_i32),
+                ("rel_res_implicit", c_d), ("rel_res_true", c_d), ("t_solve_s", c_d), ("matvecs", c_i64),
+                ("t_p2p_s", c_d), ("t_m2l_s", c_d), ("t_other_fmm_s", c_d), ("t_krylov_s", c_d),
+                ("hist_cap", c_i32), ("p_hist", P(c_i32)), ("prec_hist", P(c_u8)), ("res_hist", P(c_d))]
 
 
 class fmmbem_stats(ctypes.Structure):
@@ -141,8 +147,30 @@ def make_mesh(xyz, tri):
     return m, (xyz, tri)
 
 
-def params(theta=0.5, ncrit=64, p_max=16, mu=1.0, near_stored=0, m2l_stored=0) -> fmmbem_params:
-    return fmmbem_params(theta, ncrit, p_max, mu, near_stored, m2l_stored)
+class DeviceAllocator:
+    """Device memory for fmmbem_params.alloc/free from Python callables:
+    alloc(nbytes) -> device address (int), free(address).  Keep the object
+    alive as long as any context or request that uses it."""
+
+    def __init__(self, alloc, free):
+        self._alloc, self._free = alloc, free
+        self.c_alloc = ALLOC_FN(lambda nbytes, _user: int(self._alloc(int(nbytes))) or None)
+        self.c_free = FREE_FN(lambda ptr, _user: self._free(int(ptr)))
+
+
+def torch_allocator(device=0) -> DeviceAllocator:
+    """Device memory from PyTorch's caching allocator."""
+    return DeviceAllocator(lambda n: torch.cuda.caching_allocator_alloc(n, device),
+                           torch.cuda.caching_allocator_delete)
+
+
+def params(theta=0.5, ncrit=64, p_max=16, mu=1.0, near_stored=0, m2l_stored=0, quad_far=4, quad_near=25,
+           near_factor=2.0, allocator: DeviceAllocator | None = None) -> fmmbem_params:
+    prm = fmmbem_params(theta, ncrit, p_max, mu, near_stored, m2l_stored, quad_far, quad_near, near_factor)
+    if allocator is not None:
+        prm.alloc, prm.free = allocator.c_alloc, allocator.c_free
+        prm._allocator = allocator  # the callbacks live as long as the params
+    return prm
 
 
 def schedule(kernel=LAPLACE, **kw) -> fmmbem_schedule:
@@ -198,9 +226,10 @@ def _report(cap: int):
 def _report_dict(r, bufs):
     ph, pr, rh = bufs
     k = min(r.iterations, r.hist_cap)
-    return dict(iterations=r.iterations, restarts=r.restarts, converged=bool(r.converged),
+    return dict(iterations=r.iterations, restarts=r.restarts, converged=bool(r.converged), fallbacks=r.fallbacks,
                 rel_res_implicit=r.rel_res_implicit, rel_res_true=r.rel_res_true, t_solve_s=r.t_solve_s,
-                matvecs=r.matvecs, p_hist=ph[:k].copy(), prec_hist=pr[:k].copy(), res_hist=rh[:k].copy())
+                matvecs=r.matvecs, t_p2p_s=r.t_p2p_s, t_m2l_s=r.t_m2l_s, t_other_fmm_s=r.t_other_fmm_s,
+                t_krylov_s=r.t_krylov_s, p_hist=ph[:k].copy(), prec_hist=pr[:k].copy(), res_hist=rh[:k].copy())
 
 
 def fmmbem_solve_ctx(ctx: Context, b: torch.Tensor, tol: float, sched: fmmbem_schedule, x: torch.Tensor,

@@ -90,3 +90,43 @@ def test_schedule_defaults(fb):
     assert (s.p_init, s.p_min, s.restart, s.rule) == (16, 4, 50, fb.RELAX_BF)
     s = fb.schedule(fb.LAPLACE)
     assert (s.p_init, s.p_min) == (12, 3)
+
+
+def test_binding_struct_layouts_match_the_header(fb, tmp_path):
+    """Every field offset and struct size of the ctypes binding equals the C
+    header's (a C program built against include/fmmbem.h prints them)."""
+    import subprocess
+    structs = {name: getattr(fb, name) for name in ("fmmbem_mesh", "fmmbem_params", "fmmbem_schedule",
+                                                      "fmmbem_report", "fmmbem_stats", "fmmbem_server_params",
+                                                      "fmmbem_request_info")}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fmmbem.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        name, field, value = line.split()
+        cls = structs[name]
+        got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(value), (name, field, got, value)
+        seen += 1
+    assert seen == sum(len(c._fields_) + 1 for c in structs.values())
+
+
+def test_build_rejects_quadrature_it_does_not_implement(fb):
+    xyz = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0]])
+    tri = np.array([[0, 1, 2]], dtype=np.int32)
+    for prm in (fb.params(quad_far=7), fb.params(quad_near=16), fb.params(near_factor=3.0)):
+        rc, h = _build_rc(fb, xyz, tri, prm=prm)
+        assert rc == fb.EINVAL and not h.value
+    prm = fb.params()
+    prm.alloc = fb.ALLOC_FN(lambda n, u: None)  # alloc without free
+    rc, h = _build_rc(fb, xyz, tri, prm=prm)
+    assert rc == fb.EINVAL and "together" in fb.fmmbem_last_error()

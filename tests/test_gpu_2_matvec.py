@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import synthetic as syn
-from gpu_util import MESHES, announce, rel_l2, to_dev
+from gpu_util import MESHES, announce, max_rel, rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -35,9 +35,9 @@ def test_all_p2p_equals_dense(orc, kernel, name, near_stored):
     x = syn.random_vector(n, 5)
     yr = orc.matvec(kernel, m.xyz, m.tri, x)
     y64 = matvec(fb, ctx, 4, fb.FP64, x)
-    assert rel_l2(y64, yr) < 1e-12
+    assert rel_l2(y64, yr) < 1e-12 and max_rel(y64, yr) < 1e-12
     y32 = matvec(fb, ctx, 4, fb.FP32, x)
-    assert rel_l2(y32, yr) < 2e-6
+    assert rel_l2(y32, yr) < 2e-6 and max_rel(y32, yr) < 1e-5
     fb.fmmbem_destroy(ctx)
 
 
@@ -52,11 +52,14 @@ def test_error_falls_with_p(orc, kernel, name):
     n = m.n_panels * (3 if kernel else 1)
     x = syn.random_vector(n, 6)
     yr = orc.matvec(kernel, m.xyz, m.tri, x)
-    errs = {p: rel_l2(matvec(fb, ctx, p, fb.FP64, x), yr) for p in range(1, 17)}
+    ys = {p: matvec(fb, ctx, p, fb.FP64, x) for p in range(1, 17)}
+    errs = {p: rel_l2(y, yr) for p, y in ys.items()}
+    emax = {p: max_rel(y, yr) for p, y in ys.items()}
     announce("  " + " ".join(f"{p}:{e:.1e}" for p, e in errs.items()))
-    assert errs[6] <= 1e-3
+    announce("  max " + " ".join(f"{p}:{e:.1e}" for p, e in emax.items()))
+    assert errs[6] <= 1e-3 and emax[6] <= 1e-2
     for p in range(12, 17):
-        assert errs[p] <= 1e-6
+        assert errs[p] <= 1e-6 and emax[p] <= 1e-5
     # monotone in steps of two orders (odd/even p can tie)
     for p in range(1, 15):
         assert errs[p + 2] < errs[p] or errs[p + 2] < 1e-12
@@ -137,25 +140,26 @@ def test_stored_near_field_matches_on_the_fly(orc, kernel, name):
 
 
 
-@pytest.mark.parametrize("kernel,name", [(0, "sphere8192"), (1, "cells8x512"), (2, "sphere2048")])
-def test_stored_m2l_operators_match_generated(orc, kernel, name):
+@pytest.mark.parametrize("kernel,name,p_max", [(0, "sphere8192", 12), (1, "cells8x512", 12), (2, "sphere2048", 12),
+                                               (1, "cells8x512", 16)])
+def test_stored_m2l_operators_match_generated(orc, kernel, name, p_max):
     """FP64 M2L from operators stored at build (m2l_stored = 1) against the same
     operators generated on every call: the same product up to rounding, at
     p_max and below it (leading blocks of the stored operators); the FP32 path
     is untouched; against the oracle the stored path keeps <= 1e-6 at p = 12."""
     from paper_1506_05957_amd import fmmbem as fb
-    announce(f"stored vs generated M2L operators kernel={kernel} {name}")
+    announce(f"stored vs generated M2L operators kernel={kernel} {name} p_max={p_max}")
     m = MESHES[name]()
-    prm = dict(ncrit=64, p_max=12, near_stored=1)
+    prm = dict(ncrit=64, p_max=p_max, near_stored=1)
     a = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(**prm))
     b = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(**prm, m2l_stored=1))
     sa, sb = fb.fmmbem_get_stats(a), fb.fmmbem_get_stats(b)
     assert sa["m2l_op_bytes"] == 0 and sb["n_translations"] == sa["n_translations"] > 0
-    D = 2 * 91
+    D = (p_max + 1) * (p_max + 2)
     assert sb["m2l_op_bytes"] == sb["n_translations"] * ((D + 15) // 16) * ((D + 3) // 4) * 64 * 8
     n = m.n_panels * (3 if kernel == 1 else 1)
     x = syn.random_vector(n, 31)
-    for p in (12, 9, 5, 2):
+    for p in sorted({p_max, 12, 9, 5, 2}, reverse=True):
         ya = matvec(fb, a, p, fb.FP64, x)
         yb = matvec(fb, b, p, fb.FP64, x)
         e = rel_l2(yb, ya)
@@ -163,6 +167,7 @@ def test_stored_m2l_operators_match_generated(orc, kernel, name):
         assert e <= 1e-13
     assert np.array_equal(matvec(fb, a, 6, fb.FP32, x), matvec(fb, b, 6, fb.FP32, x))
     yr = orc.matvec(kernel, m.xyz, m.tri, x)
-    assert rel_l2(matvec(fb, b, 12, fb.FP64, x), yr) <= 1e-6
+    yb = matvec(fb, b, p_max, fb.FP64, x)
+    assert rel_l2(yb, yr) <= 1e-6 and max_rel(yb, yr) <= 1e-5
     fb.fmmbem_destroy(a)
     fb.fmmbem_destroy(b)

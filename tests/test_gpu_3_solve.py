@@ -20,11 +20,13 @@ import pytest
 import torch
 
 import synthetic as syn
-from gpu_util import MESHES, announce, rel_l2, to_dev
+from gpu_util import MESHES, announce, compare, max_rel, rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
-RULES = [(0, 0), (2, 0), (2, 1)]  # (rule, mixed): fixed FP64, relaxed FP64, relaxed mixed
+# (rule, mixed): fixed FP64; the Eq. 19 rule (RELAX_BF) FP64 and mixed; the
+# shifted rule (RELAX_SHIFT) FP64 and mixed
+RULES = [(0, 0), (2, 0), (2, 1), (1, 0), (1, 1)]
 
 
 def solve(fb, ctx, b, tol, sched):
@@ -38,42 +40,6 @@ def solve(fb, ctx, b, tol, sched):
 def describe(rep, x, xo):
     return (f"  it={rep['iterations']} p={[int(v) for v in rep['p_hist']]} "
             f"prec={[int(v) for v in rep['prec_hist']]} true={rep['rel_res_true']:.1e} err={rel_l2(x, xo):.1e}")
-
-
-def bodies_of(name, n_panels):
-    if name.startswith("cells"):
-        k = int(name[5:].split("x")[0])
-        return [range(i * (n_panels // k), (i + 1) * (n_panels // k)) for i in range(k)]
-    return [range(n_panels)]
-
-
-def strip_normal(orc, m, t, bodies):
-    """t minus, per body, its area-weighted normal component."""
-    _, S, nrm = orc.panels(m.xyz, m.tri)
-    t = t.reshape(-1, 3).copy()
-    for b in bodies:
-        idx = np.fromiter(b, dtype=np.int64)
-        a = np.sum(np.einsum("ij,ij->i", t[idx], nrm[idx]) * S[idx]) / np.sum(S[idx])
-        t[idx] -= a * nrm[idx]
-    return t.reshape(-1)
-
-
-def body_forces(orc, m, t, bodies):
-    _, S, _ = orc.panels(m.xyz, m.tri)
-    t = t.reshape(-1, 3)
-    return np.array([np.sum(t[np.fromiter(b, dtype=np.int64)] * S[np.fromiter(b, dtype=np.int64), None], axis=0)
-                     for b in bodies])
-
-
-def compare(orc, kernel, mesh_name, m, x, xo):
-    """relative error of x against the oracle solution, null-space free for Stokes"""
-    if kernel == 0:
-        return rel_l2(x, xo)
-    bodies = bodies_of(mesh_name, m.n_panels)
-    e = rel_l2(strip_normal(orc, m, x, bodies), strip_normal(orc, m, xo, bodies))
-    Fo = body_forces(orc, m, xo, bodies)
-    eF = float(np.max(np.abs(body_forces(orc, m, x, bodies) - Fo)) / np.max(np.abs(Fo)))
-    return max(e, eF)
 
 
 CASES = {
@@ -96,11 +62,12 @@ def test_solve_parity_tight(orc, case, rule, mixed):
     xo = orc.solve(kernel, m.xyz, m.tri, b, tol=1e-11)[0]
     ctx = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(ncrit=64, p_max=p_init))
     x, rep = solve(fb, ctx, b, 1e-8, fb.schedule(kernel, rule=rule, mixed=mixed, p_init=p_init, p_min=p_min))
-    err = compare(orc, kernel, mesh_name, m, x, xo)
-    announce(describe(rep, x, xo) + f" cmp={err:.1e}")
+    err, emax = compare(orc, kernel, mesh_name, m, x, xo, elementwise=True)
+    announce(describe(rep, x, xo) + f" cmp={err:.1e} max={emax:.1e} restarts={rep['restarts']}")
     assert rep["converged"]
-    assert rep["rel_res_true"] <= 1e-7
+    assert rep["rel_res_true"] <= 1e-8  # converged means the true residual met tol
     assert err <= 1e-5
+    assert emax <= 1e-4
     if rule == 0:
         assert set(int(v) for v in rep["p_hist"]) == {p_init}
         assert set(int(v) for v in rep["prec_hist"]) == {0}
@@ -170,7 +137,7 @@ def test_solve_bench_tolerance(orc, case):
     announce(describe(rf, xf, xo))
     announce(describe(rr, xr, xo))
     assert rf["converged"] and rr["converged"]
-    assert rr["rel_res_true"] <= 1.5e-6
+    assert rf["rel_res_true"] <= 1e-6 and rr["rel_res_true"] <= 1e-6
     ef, er = compare(orc, kernel, mesh_name, m, xf, xo), compare(orc, kernel, mesh_name, m, xr, xo)
     announce(f"  fixed {ef:.1e} relaxed {er:.1e}")
     assert er <= 2 * ef + 1e-5
@@ -205,3 +172,98 @@ def test_one_shot_solve_and_errors(orc):
     rep = fb.fmmbem_solve_ctx(ctx, z, 1e-6, fb.schedule(fb.LAPLACE), xd)
     assert rep["converged"] and rep["iterations"] == 0 and float(xd.abs().max()) == 0.0
     fb.fmmbem_destroy(ctx)
+
+
+def test_fp32_overflow_falls_back_to_fp64(orc):
+    """A surface scaled by 1e20 has panel areas (1e40) beyond the FP32 range,
+    so the first FP32 mat-vec of a mixed solve is not finite.  The solve
+    discards that column, ends the cycle with the columns before it, restarts
+    from the true residual and runs every later mat-vec in FP64.  The Laplace
+    single layer scales as V_R[s](R x) = R V_1[s](x), so the density for
+    phi = 1 is the unit sphere's divided by R: parity with the oracle on the
+    unit sphere at tol 1e-8."""
+    from paper_1506_05957_amd import fmmbem as fb
+    announce("FP32 range overflow -> FP64 restart, sphere2048 scaled by 1e20")
+    m = MESHES["sphere2048"]()
+    R = 1e20
+    b = np.ones(m.n_panels)
+    xo = orc.solve(orc.LAPLACE, m.xyz, m.tri, b, tol=1e-11)[0] / R
+    ctx = fb.fmmbem_build(m.xyz * R, m.tri, fb.LAPLACE, fb.params(ncrit=64, p_max=12))
+    x, rep = solve(fb, ctx, b, 1e-8, fb.schedule(fb.LAPLACE))
+    prec = [int(v) for v in rep["prec_hist"]]
+    announce(describe(rep, x, xo) + f" fallbacks={rep['fallbacks']} restarts={rep['restarts']}")
+    assert rep["converged"] and rep["fallbacks"] == 1 and rep["restarts"] >= 1
+    first32 = prec.index(1)
+    assert np.isnan(rep["res_hist"][first32])
+    assert all(v == 0 for v in prec[first32 + 1:])
+    assert rep["rel_res_true"] <= 1e-8
+    assert rel_l2(x, xo) <= 1e-5 and max_rel(x, xo) <= 1e-4
+    fb.fmmbem_destroy(ctx)
+
+
+def test_report_stage_seconds(orc):
+    """Per-stage device seconds in the report: -1 for untimed stages, the
+    timed stages' event times otherwise (all stages: each >= 0 and their
+    sum within the solve's wall time plus the overlap of the two streams)."""
+    from paper_1506_05957_amd import fmmbem as fb
+    announce("report: per-stage seconds")
+    m = MESHES["sphere2048"]()
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE, fb.params(ncrit=64, p_max=12))
+    b = np.ones(m.n_panels)
+    _, rep = solve(fb, ctx, b, 1e-6, fb.schedule(fb.LAPLACE))
+    keys = ("t_p2p_s", "t_m2l_s", "t_other_fmm_s", "t_krylov_s")
+    assert all(rep[k] == -1.0 for k in keys)
+    fb.fmmbem_set_timing(ctx, True)
+    _, rep = solve(fb, ctx, b, 1e-6, fb.schedule(fb.LAPLACE))
+    announce("  " + " ".join(f"{k}={rep[k] * 1e3:.3f}ms" for k in keys) + f" wall={rep['t_solve_s'] * 1e3:.3f}ms")
+    assert all(rep[k] > 0.0 for k in keys)
+    assert sum(rep[k] for k in keys) <= 2.0 * rep["t_solve_s"]
+    fb.fmmbem_set_timing_stages(ctx, ["m2l_fp64", "m2l_fp32"])
+    _, rep = solve(fb, ctx, b, 1e-6, fb.schedule(fb.LAPLACE))
+    assert rep["t_m2l_s"] > 0.0 and rep["t_p2p_s"] == rep["t_krylov_s"] == rep["t_other_fmm_s"] == -1.0
+    fb.fmmbem_destroy(ctx)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_caller_allocator_holds_every_device_byte(orc, kernel):
+    """With fmmbem_params.alloc/free (here PyTorch's caching allocator behind a
+    counter), every byte of fmmbem_stats.device_bytes was handed out by the
+    callbacks, nothing is left with them after destroy, and the results are
+    those of a context on hipMalloc bit for bit.  The one-shot solve too."""
+    from paper_1506_05957_amd import fmmbem as fb
+    announce(f"caller allocator, kernel {kernel}")
+    held, peak = {}, [0]
+
+    def alloc(n):
+        p = torch.cuda.caching_allocator_alloc(n, 0)
+        held[p] = n
+        peak[0] = max(peak[0], sum(held.values()))
+        return p
+
+    def free(p):
+        held.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    A = fb.DeviceAllocator(alloc, free)
+    m = MESHES["sphere2048"]()
+    b = np.ones(m.n_panels) if kernel == 0 else np.tile([1.0, 0.0, 0.0], m.n_panels)
+    extra = dict(near_stored=1, m2l_stored=1) if kernel == 0 else {}
+    ref = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(ncrit=64, p_max=12, **extra))
+    ctx = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(ncrit=64, p_max=12, allocator=A, **extra))
+    st = fb.fmmbem_get_stats(ctx)
+    assert sum(held.values()) == st["device_bytes"] > 0
+    sched = fb.schedule(kernel, p_init=12)
+    xr, _ = solve(fb, ref, b, 1e-6, sched)
+    x, rep = solve(fb, ctx, b, 1e-6, sched)
+    st = fb.fmmbem_get_stats(ctx)
+    announce(f"  device_bytes={st['device_bytes']} held={sum(held.values())} allocations={len(held)}")
+    assert sum(held.values()) == st["device_bytes"]  # the Krylov workspace too
+    assert rep["converged"] and np.array_equal(x, xr)
+    fb.fmmbem_destroy(ctx)
+    fb.fmmbem_destroy(ref)
+    assert not held
+    peak[0] = 0
+    x1, rep1 = fb.fmmbem_solve(m.xyz, m.tri, b, kernel, 1e-6, sched,
+                               fb.params(ncrit=64, p_max=12, allocator=A, **extra))
+    assert rep1["converged"] and peak[0] > 0 and not held
+    assert np.array_equal(x1, xr)

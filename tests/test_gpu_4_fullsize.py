@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import synthetic as syn
-from gpu_util import announce, to_dev
+from gpu_util import announce, compare, max_rel, rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -41,18 +41,24 @@ def matvec(fb, ctx, p, prec, x):
     return yd.cpu().numpy()
 
 
-def test_laplace_sphere_32768(orc):
+@pytest.mark.parametrize("stored", [0, 1])
+def test_laplace_sphere_32768(orc, stored):
+    """The 32768-panel sphere, five Y_l^m right-hand sides, relaxed mixed
+    solves at tol 1e-6; stored = 1 is the benchmark's configuration (near field
+    and FP64 M2L operators stored at build)."""
     from paper_1506_05957_amd import fmmbem as fb
-    announce("full size: Laplace sphere 32768, Y_l^m, relaxed 12 -> 3 mixed")
+    announce(f"full size: Laplace sphere 32768, Y_l^m, relaxed 12 -> 3 mixed, stored={stored}")
     m = syn.sphere(6)
-    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE, fb.params(ncrit=64, p_max=12))
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE,
+                          fb.params(ncrit=64, p_max=12, near_stored=stored, m2l_stored=stored))
     rows = sampled_rows(m.n_panels, 256, 0)
     x = syn.random_vector(m.n_panels, 3)
     yr = orc.matvec(orc.LAPLACE, m.xyz, m.tri, x, rows=rows)
     for p, prec, bar in ((12, fb.FP64, 1e-6), (12, fb.FP32, 1e-5), (6, fb.FP32, 1e-3)):
-        e = np.linalg.norm(matvec(fb, ctx, p, prec, x)[rows] - yr) / np.linalg.norm(yr)
-        announce(f"  mat-vec p={p} prec={prec}: sampled rel err {e:.1e}")
-        assert e <= bar
+        y = matvec(fb, ctx, p, prec, x)[rows]
+        e, emax = rel_l2(y, yr), max_rel(y, yr)
+        announce(f"  mat-vec p={p} prec={prec}: sampled rel err {e:.1e} max {emax:.1e}")
+        assert e <= bar and emax <= 10 * bar
     for l, mm in syn.ylm_orders(0):
         b = syn.ylm_rhs(m, l, mm)
         bd = to_dev(b)
@@ -64,7 +70,7 @@ def test_laplace_sphere_32768(orc):
         eclosed = np.linalg.norm(xs - exact) / np.linalg.norm(exact)
         announce(f"  Y_{l}^{mm}: it={rep['iterations']} true={rep['rel_res_true']:.1e} sampled={rel:.1e} "
                  f"closed-form err={eclosed:.1e}")
-        assert rep["converged"] and rep["rel_res_true"] <= 1.5e-6
+        assert rep["converged"] and rep["rel_res_true"] <= 1e-6
         assert rel <= 5e-6
         assert eclosed <= 1e-2
     fb.fmmbem_destroy(ctx)
@@ -96,65 +102,101 @@ def test_stokes_sphere_8192_drag(orc):
     fb.fmmbem_destroy(ctx)
 
 
-def test_stokes_64_cells(orc):
+@pytest.mark.parametrize("ncrit", [128, 256])
+def test_stokes_64_cells(orc, ncrit):
+    """64 red blood cells x 2048 panels (131072 panels, 393216 unknowns), the
+    relaxed mixed schedule (16 -> 4, the benchmark's headline) and fixed
+    p = 16 in FP64, at each N_CRIT the benchmark uses: both converge to a true
+    residual <= 1e-6, the oracle's residual b - A x on 4096 sampled rows is
+    <= 5e-6 of b there, and the force on every cell agrees between the two
+    schedules (the normal field that the single layer nearly annihilates
+    carries no force)."""
     from paper_1506_05957_amd import fmmbem as fb
-    announce("full size: 64 red blood cells x 2048 panels (131072 panels, 393216 unknowns)")
+    announce(f"full size: 64 red blood cells x 2048 panels, N_CRIT {ncrit}, relaxed and fixed")
     m = syn.rbc_scene(64, 4, 0)
     assert m.n_panels == 131072
-    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=64, p_max=16))
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=ncrit, p_max=16))
     st = fb.fmmbem_get_stats(ctx)
     announce(f"  stats: {st}")
     u = np.tile([1.0, 0.0, 0.0], m.n_panels)
     ud = to_dev(u)
-    xd = torch.empty_like(ud)
-    rep = fb.fmmbem_solve_ctx(ctx, ud, 1e-6, fb.schedule(fb.STOKES), xd)
-    t = xd.cpu().numpy()
-    rows = sampled_rows(m.n_panels, 64, 2)
-    rel = check_solution(orc, orc.STOKES, m, u, t, rows)
-    announce(f"  relaxed: it={rep['iterations']} restarts={rep['restarts']} true={rep['rel_res_true']:.1e} "
-             f"sampled={rel:.1e} t={rep['t_solve_s']:.2f}s p={[int(v) for v in rep['p_hist']]}")
-    assert rep["converged"] and rep["rel_res_true"] <= 1.5e-6
-    assert rel <= 1e-5
-    # every cell drags along the flow with a force of the single-cell size
+    rows = sampled_rows(m.n_panels, 4096, 2)
     _, S, _ = orc.panels(m.xyz, m.tri)
-    tt = t.reshape(64, -1, 3)
-    F = np.einsum("cpa,cp->ca", tt, S.reshape(64, -1))
-    assert np.all(F[:, 0] < 0)
+    forces = {}
+    for name, sched in (("relaxed", fb.schedule(fb.STOKES)),
+                        ("fixed", fb.schedule(fb.STOKES, rule=fb.FIXED, p_min=16, mixed=0))):
+        xd = torch.empty_like(ud)
+        rep = fb.fmmbem_solve_ctx(ctx, ud, 1e-6, sched, xd)
+        t = xd.cpu().numpy()
+        rel = check_solution(orc, orc.STOKES, m, u, t, rows)
+        announce(f"  {name}: it={rep['iterations']} restarts={rep['restarts']} true={rep['rel_res_true']:.1e} "
+                 f"sampled={rel:.1e} t={rep['t_solve_s']:.2f}s")
+        assert rep["converged"] and rep["rel_res_true"] <= 1e-6
+        assert rel <= 5e-6
+        F = np.einsum("cpa,cp->ca", t.reshape(64, -1, 3), S.reshape(64, -1))
+        assert np.all(F[:, 0] < 0)  # every cell drags along the flow
+        forces[name] = F
+    dF = np.max(np.abs(forces["relaxed"] - forces["fixed"])) / np.max(np.abs(forces["fixed"]))
+    announce(f"  per-cell force, relaxed vs fixed: max rel diff {dF:.1e}")
+    assert dF <= 1e-4
     fb.fmmbem_destroy(ctx)
 
 
-def test_serving_alone_equals_in_the_mix(orc):
+@pytest.fixture(scope="module")
+def serving_requests():
+    """12 requests of the serving mix (Laplace or Stokes on sphere, ellipsoid
+    or red-blood-cell surfaces of 512 and 2048 panels), each solved alone on a
+    context of its own at tol 1e-8 (relaxed mixed schedule)."""
     from paper_1506_05957_amd import fmmbem as fb
-    announce("serving: 12 mixed requests, alone vs in the mix")
     reqs = syn.request_stream(12, 1000.0, 0, levels=(3, 4))
-    inputs = []
+    out = []
     for r in reqs:
         m = r.mesh()
         kernel = fb.LAPLACE if r.kernel == "laplace" else fb.STOKES
         b = np.ones(m.n_panels) if kernel == fb.LAPLACE else np.tile([1.0, 0.0, 0.0], m.n_panels)
-        inputs.append((m, kernel, b))
-    alone = []
-    for m, kernel, b in inputs:
         ctx = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(p_max=16))
         bd = to_dev(b)
         xd = torch.empty_like(bd)
-        fb.fmmbem_solve_ctx(ctx, bd, 1e-6, fb.schedule(kernel), xd)
-        alone.append(xd.cpu().numpy())
+        rep = fb.fmmbem_solve_ctx(ctx, bd, 1e-8, fb.schedule(kernel), xd)
+        assert rep["converged"]
+        out.append((r, m, kernel, b, xd.cpu().numpy()))
         fb.fmmbem_destroy(ctx)
+    return out
+
+
+def test_serving_alone_equals_in_the_mix(serving_requests):
+    """Every request's result from the request loop equals, bit for bit, the
+    same solve alone: with room for all (continuous batching of 12), under a
+    tight memory budget (admission waits for memory) and one at a time."""
+    from paper_1506_05957_amd import fmmbem as fb
+    announce("serving: 12 mixed requests, alone vs in the mix")
     for budget, max_active in ((8 << 30, 16), (96 << 20, 16), (8 << 30, 1)):
         srv = fb.fmmbem_server_create(hbm_budget_bytes=budget, max_active=max_active, n_streams=4)
-        tickets = [fb.fmmbem_submit(srv, m.xyz, m.tri, b, kernel, 1e-6, fb.schedule(kernel))
-                   for m, kernel, b in inputs]
+        tickets = [fb.fmmbem_submit(srv, m.xyz, m.tri, b, kernel, 1e-8, fb.schedule(kernel))
+                   for _, m, kernel, b, _ in serving_requests]
         infos = []
-        for tk, (m, kernel, b), xa in zip(tickets, inputs, alone):
+        for tk, (_, m, kernel, b, xa) in zip(tickets, serving_requests):
             x, info = fb.fmmbem_wait(srv, tk, b.shape[0])
             infos.append(info)
-            assert info["status"] == fb.OK and info["converged"]
+            assert info["status"] == fb.OK and info["converged"] and info["rel_res_true"] <= 1e-8
             assert np.array_equal(x, xa), np.max(np.abs(x - xa))
         fb.fmmbem_server_destroy(srv)
         lat = np.array([i["finish_s"] - i["arrival_s"] for i in infos])
         announce(f"  budget={budget >> 20} MiB max_active={max_active}: latency p50={np.median(lat) * 1e3:.1f} ms "
                  f"max={lat.max() * 1e3:.1f} ms")
+
+
+def test_serving_results_match_the_oracle(orc, serving_requests):
+    """The served solutions (equal bit for bit to the solves alone, see the
+    test above) against the oracle's dense GMRES solution at tol 1e-11:
+    <= 1e-5 relative L2 (Stokes without each body's normal field, plus the
+    body force) and <= 1e-4 in the largest element."""
+    announce("serving: each request against the oracle")
+    for r, m, kernel, b, x in serving_requests:
+        xo = orc.solve(kernel, m.xyz, m.tri, b, tol=1e-11)[0]
+        e, emax = compare(orc, kernel, "one", m, x, xo, elementwise=True)
+        announce(f"  {r.kernel} {r.shape} {m.n_panels}: err {e:.1e} max {emax:.1e}")
+        assert e <= 1e-5 and emax <= 1e-4
 
 
 def test_serving_errors():
