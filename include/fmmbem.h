@@ -148,6 +148,13 @@ typedef struct {
      * discarded, the cycle ends with the columns before it and every later
      * mat-vec of the solve runs in FP64 */
     int32_t fallbacks;
+    /* restarted cycles whose true residual exceeded twice the larger of
+     * their implicit residual and tol (the relaxed products were too coarse
+     * for the residual reached); each raises a floor under every later order
+     * by ceil(log2(true / max(implicit, tol))) + 1 orders (the 2^-p error
+     * model of Eq. 19), capped at p_init; p_floor is the floor at exit (0 if
+     * no stall) */
+    int32_t stalls, p_floor;
     double rel_res_implicit;   /* |g_{k+1}| / |b| at exit */
     /* |b - A x| / |b| with A at p_init in FP64; a solve is converged only
      * when this is <= tol (an implicit residual at tol with a true residual
@@ -231,9 +238,10 @@ const char *fmmbem_last_error(void);
  * and flops[i] the algorithmic flops of those launches: P2P evaluated on the
  * fly counts 12 (Laplace single layer), 18 (double layer) or 30 (Stokes) per
  * source-target pair, the stored near field 2 per stored value (9 values
- * per panel pair for Stokes), M2L 8 ncoef(p)^2 per box pair and channel (the
- * real (2 ncoef(p))^2 operator times a coefficient vector); the other stages
- * count 0.  Any output pointer may be NULL. */
+ * per panel pair for Stokes), M2L 4 (p + 1)^3 (p + 2) per box pair and
+ * channel (the complex translation of Sec. 2.5 as the method states it; the
+ * kernels apply it as a real (2 ncoef(p))^2 operator, 8 ncoef(p)^2 flops);
+ * the other stages count 0.  Any output pointer may be NULL. */
 #define FMMBEM_N_STAGES 11
 int fmmbem_set_timing(fmmbem_ctx_t *ctx, int enabled);
 /* Times only the stages whose bit is set in mask (bit prec * 5 + stage, or

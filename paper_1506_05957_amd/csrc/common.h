@@ -383,7 +383,8 @@ struct GmresState {
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *yv = nullptr;
     double *hbuf = nullptr;     // kw->hcol
     hipEvent_t ev_h = nullptr;  // kw->ev_h
-    int it = 0, restarts = 0, converged = 0, k = 0, fallbacks = 0;
+    int it = 0, restarts = 0, converged = 0, k = 0, fallbacks = 0, stalls = 0;
+    int p_floor = 0;  // raised by a stalled cycle: no later order falls below it
     int64_t matvecs = 0;
     double bnorm = 0, beta = 0, rel = 1, true_rel = 1, rho_prev = 1;
     double rho_prev2 = -1;  // the residual before rho_prev, < 0 if none
@@ -437,6 +438,9 @@ int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedul
 // x[0..n) = 0 by a kernel (no memset node in a caller's capture)
 void fill_zero(double *x, int64_t n, hipStream_t st);
 void free_krylov(fmmbem_ctx *ctx);
+// allocate the context's Krylov workspace for GMRES(m) now (a solve would on
+// its first call)
+void reserve_krylov(fmmbem_ctx *ctx, int m);
 // timing helpers (api.hip); timing_resolve reads every pending event pair
 void timing_resolve(Timing &T);
 void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev);

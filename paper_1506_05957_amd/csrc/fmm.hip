@@ -1876,8 +1876,11 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
             }
             FB_HIP(hipGetLastError());
         }
-        // real form: a (2 nc) x (2 nc) operator times each pair's coefficients, per channel
-        stage_end(ctx, SO + 1, st, ev, 8.0 * ncoef(p) * ncoef(p) * NCH * (double)T.n_m2l);
+        // the method's count: the complex O(p^4) translation of Sec. 2.5,
+        // 4 (p + 1)^3 (p + 2) flops per box pair and channel (the kernels
+        // apply it as a real (2 nc) x (2 nc) operator, 8 nc^2 flops)
+        const double q1 = p + 1.0;
+        stage_end(ctx, SO + 1, st, ev, 4.0 * q1 * q1 * q1 * (p + 2.0) * NCH * (double)T.n_m2l);
 
         // the downward pass: the per-target sum of the M2L terms, then L2L and L2P
         stage_begin(ctx, SO + 3, st, &ev);

@@ -12,6 +12,8 @@
 // bitwise reproducible.
 #include <chrono>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -297,7 +299,7 @@ void norm2(KrylovWork *kw, const double *r, hipStream_t st, int slot = 0)
     FB_HIP(hipGetLastError());
 }
 
-Sched choose(const fmmbem_schedule *s, double rho, double eta, bool fp64_only = false)
+Sched choose(const fmmbem_schedule *s, double rho, double eta, bool fp64_only = false, int p_floor = 0)
 {
     double rm = std::min(rho, 1.0);
     double eps = std::min(eta / rm, 1.0);
@@ -307,7 +309,7 @@ Sched choose(const fmmbem_schedule *s, double rho, double eta, bool fp64_only = 
     } else if (s->rule == FMMBEM_RELAX_BF) {
         p = (int)std::ceil(-std::log2(eps));
     }
-    p = std::max(s->p_min, std::min(s->p_init, p));
+    p = std::max(std::max(s->p_min, p_floor), std::min(s->p_init, p));
     int prec = FMMBEM_FP64;
     if (s->mixed && !fp64_only && s->rule != FMMBEM_FIXED && eps >= s->fp32_eps && p <= P_MAX_FP32)
         prec = FMMBEM_FP32;
@@ -329,6 +331,11 @@ void fill_zero(double *x, int64_t n, hipStream_t st)
         return;
     k_zero<<<grid_for(n, 256), 256, 0, st>>>(n, x);
     FB_HIP(hipGetLastError());
+}
+
+void reserve_krylov(fmmbem_ctx *ctx, int m)
+{
+    (void)get_work(ctx, m);
 }
 
 void free_krylov(fmmbem_ctx *ctx)
@@ -437,7 +444,7 @@ void GmresState::enqueue_step()
 {
     const int m = s.restart;
     const int64_t n = ctx->n;
-    cur = choose(&s, rho_prev, tol, fp64_only);
+    cur = choose(&s, rho_prev, tol, fp64_only, p_floor);
     double *vk = kw->V + (int64_t)k * n, *vn = kw->V + (int64_t)(k + 1) * n;
     run_matvec(ctx, cur.p, cur.prec, vk, kw->w, st);
     ++matvecs;
@@ -465,7 +472,7 @@ void GmresState::enqueue_step()
         const double ratio = rho_prev2 > 0.0 ? std::min(1.0, rho_prev / rho_prev2) : 0.01;
         const double rho_next = rho_prev * ratio;
         if (rho_next > tol) {
-            const Sched nx = choose(&s, rho_next, tol, fp64_only);
+            const Sched nx = choose(&s, rho_next, tol, fp64_only, p_floor);
             pre_prec = nx.prec;
             p_up = std::min(cur.p, nx.p + 2);
             if (pre_prec == FMMBEM_FP32)
@@ -537,6 +544,18 @@ void GmresState::end_cycle()
         done = true;
     } else {
         ++restarts;
+        const double gap = true_rel / std::max(rel, tol);
+        if (gap > 2.0) {
+            // a stall: the true residual is well above what the cycle's
+            // implicit residual (or tol) promised, so the relaxed products
+            // were less accurate than the residual needs.  The gap follows
+            // the mat-vec error, which Eq. 19 takes to fall as 2^-p: every
+            // later order is at least the floor raised by the orders that
+            // close the gap, plus one
+            ++stalls;
+            const int dp = (int)std::ceil(std::log2(gap)) + 1;
+            p_floor = std::min(s.p_init, std::max(p_floor, s.p_min) + dp);
+        }
         rho_prev = true_rel;  // the schedule continues from the true residual
         rho_prev2 = -1.0;
         begin_cycle();
@@ -613,6 +632,8 @@ void GmresState::fill_report(fmmbem_report *r) const
     r->restarts = restarts;
     r->converged = converged;
     r->fallbacks = fallbacks;
+    r->stalls = stalls;
+    r->p_floor = p_floor;
     r->rel_res_implicit = rel;
     r->rel_res_true = true_rel;
     r->matvecs = matvecs;

@@ -53,7 +53,8 @@ class fmmbem_schedule(ctypes.Structure):
 
 class fmmbem_report(ctypes.Structure):
     _fields_ = [("iterations", c_i32), ("restarts", c_i32), ("converged", c_i32), ("fallbacks", c_i32),
-                ("rel_res_implicit", c_d), ("rel_res_true", c_d), ("t_solve_s", c_d), ("matvecs", c_i64),
+                ("stalls", c_i32), ("p_floor", c_i32), ("rel_res_implicit", c_d), ("rel_res_true", c_d),
+                ("t_solve_s", c_d), ("matvecs", c_i64),
                 ("t_p2p_s", c_d), ("t_m2l_s", c_d), ("t_other_fmm_s", c_d), ("t_krylov_s", c_d),
                 ("hist_cap", c_i32), ("p_hist", P(c_i32)), ("prec_hist", P(c_u8)), ("res_hist", P(c_d))]
 
@@ -227,6 +228,7 @@ def _report_dict(r, bufs):
     ph, pr, rh = bufs
     k = min(r.iterations, r.hist_cap)
     return dict(iterations=r.iterations, restarts=r.restarts, converged=bool(r.converged), fallbacks=r.fallbacks,
+                stalls=r.stalls, p_floor=r.p_floor,
                 rel_res_implicit=r.rel_res_implicit, rel_res_true=r.rel_res_true, t_solve_s=r.t_solve_s,
                 matvecs=r.matvecs, t_p2p_s=r.t_p2p_s, t_m2l_s=r.t_m2l_s, t_other_fmm_s=r.t_other_fmm_s,
                 t_krylov_s=r.t_krylov_s, p_hist=ph[:k].copy(), prec_hist=pr[:k].copy(), res_hist=rh[:k].copy())

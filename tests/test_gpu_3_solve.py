@@ -63,16 +63,23 @@ def test_solve_parity_tight(orc, case, rule, mixed):
     ctx = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(ncrit=64, p_max=p_init))
     x, rep = solve(fb, ctx, b, 1e-8, fb.schedule(kernel, rule=rule, mixed=mixed, p_init=p_init, p_min=p_min))
     err, emax = compare(orc, kernel, mesh_name, m, x, xo, elementwise=True)
-    announce(describe(rep, x, xo) + f" cmp={err:.1e} max={emax:.1e} restarts={rep['restarts']}")
+    announce(describe(rep, x, xo) + f" cmp={err:.1e} max={emax:.1e} restarts={rep['restarts']}"
+             f" stalls={rep['stalls']} p_floor={rep['p_floor']}")
     assert rep["converged"]
     assert rep["rel_res_true"] <= 1e-8  # converged means the true residual met tol
+    # a stalled cycle raises the floor of the later orders
+    assert (rep["stalls"] == 0) == (rep["p_floor"] == 0)
+    if rep["stalls"]:
+        assert p_min < rep["p_floor"] <= p_init
+        assert int(rep["p_hist"][-1]) >= rep["p_floor"]
     assert err <= 1e-5
     assert emax <= 1e-4
     if rule == 0:
         assert set(int(v) for v in rep["p_hist"]) == {p_init}
         assert set(int(v) for v in rep["prec_hist"]) == {0}
     else:
-        assert int(rep["p_hist"][0]) == p_init and int(rep["p_hist"][-1]) < p_init
+        assert int(rep["p_hist"][0]) == p_init
+        assert min(int(v) for v in rep["p_hist"]) < p_init
     fb.fmmbem_destroy(ctx)
 
 
