@@ -1,16 +1,20 @@
 // Request loop: continuous batching of BEM solves of uneven sizes.
 //
-// A worker thread owns the device work.  Queued requests are admitted in
-// arrival order while a slot is free and their estimated device footprint
-// fits the budget; each admitted request gets its own context (octree, lists,
-// corrections, Krylov basis, all resident on the device) and one of the
-// server's streams.  A tick advances every active solve by one GMRES
-// iteration: all solves first enqueue their mat-vec and orthogonalisation on
-// their streams, so the device overlaps them, and only then does the thread
-// wait for each and apply its Givens update.  A finished request releases its
-// device memory and slot at once, and the next queued request is admitted in
-// the same tick.  Each solve's arithmetic is independent of the others, so a
-// result is bitwise the same alone or in the mix.
+// Two host threads own the device work.  Queued requests are admitted in
+// arrival order while a slot is free and their device footprint fits the
+// budget; an admitted request is handed to the builder thread, which builds
+// its context (octree, lists, corrections, Krylov basis, all resident on the
+// device) on a stream of its own, so a build never stalls the solves in
+// flight.  Until its context exists a request holds an upper estimate of its
+// footprint against the budget; once built it holds the context's real device
+// bytes, and the difference goes back to admission at once.  The worker
+// thread starts built requests on one of the server's streams and, each
+// tick, advances every active solve by one GMRES iteration: all solves first
+// enqueue their mat-vec and orthogonalisation on their streams, so the device
+// overlaps them, and only then does the thread wait for each and apply its
+// Givens update.  A finished request releases its device memory and slot at
+// once.  Each solve's arithmetic is independent of the others, so a result is
+// bitwise the same alone or in the mix.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -36,6 +40,7 @@ struct Request {
     fmmbem_schedule sched{};
     fmmbem_params prm{};
     int64_t est_bytes = 0;
+    int64_t held_bytes = 0;  // charged against the budget: the estimate, then the real bytes
     // state
     int status = FMMBEM_OK;
     bool done = false;
@@ -46,6 +51,8 @@ struct Request {
     int stream = 0;
 };
 
+// An upper estimate of a request's device footprint, used until its context
+// is built.
 int64_t estimate_bytes(int64_t nt, int kernel, const fmmbem_params &prm, const fmmbem_schedule &s)
 {
     const int64_t n = kernel == FMMBEM_STOKES_SL ? 3 * nt : nt;
@@ -69,26 +76,56 @@ int64_t estimate_bytes(int64_t nt, int kernel, const fmmbem_params &prm, const f
     return geo + corr + exp + ops + lists + work + kry + io + near + m2l + (16 << 20);
 }
 
+int64_t context_bytes(const fmmbem_ctx *ctx)
+{
+    return ctx->arena.bytes + (ctx->kw ? ctx->kw->arena.bytes : 0);
+}
+
 }  // namespace
 
 struct fmmbem_server {
     fmmbem_server_params prm{};
     int device = 0;
     std::vector<hipStream_t> streams;
+    hipStream_t build_stream = nullptr;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<Request *> queue;
+    std::condition_variable cv_work, cv_build, cv_done;
+    std::deque<Request *> queue;     // waiting for admission
+    std::deque<Request *> to_build;  // admitted, waiting for the builder
+    std::deque<Request *> ready;     // built, waiting for the worker
     std::map<uint64_t, std::unique_ptr<Request>> all;
-    std::vector<Request *> active;
+    std::vector<Request *> active;   // worker thread only
+    int n_admitted = 0;              // admitted and not finished (building, ready or active)
     int64_t used_bytes = 0;
     uint64_t next_ticket = 1;
     bool stop = false;
-    std::thread worker;
+    std::thread worker, builder;
     std::chrono::steady_clock::time_point t_origin;
 
     double now() const
     {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_origin).count();
+    }
+
+    // admit queued requests in arrival order while a slot is free and the
+    // footprint fits; a request alone is always admitted (called with mu held)
+    void admit_locked()
+    {
+        bool any = false;
+        while (!queue.empty() && n_admitted < prm.max_active) {
+            Request *r = queue.front();
+            if (used_bytes + r->est_bytes > prm.hbm_budget_bytes && n_admitted > 0)
+                break;  // wait for memory
+            queue.pop_front();
+            r->held_bytes = r->est_bytes;
+            used_bytes += r->held_bytes;
+            ++n_admitted;
+            r->info.admit_s = now();
+            to_build.push_back(r);
+            any = true;
+        }
+        if (any)
+            cv_build.notify_all();
     }
 
     void finish(Request *r, int status)
@@ -110,33 +147,74 @@ struct fmmbem_server {
         }
         r->gm.reset();
         if (r->ctx) {
-            r->info.device_bytes = r->ctx->arena.bytes;
+            r->info.device_bytes = context_bytes(r->ctx);
             fmmbem_destroy(r->ctx);
             r->ctx = nullptr;
         }
         r->d_b = r->d_x = nullptr;  // held by the context's arena
         r->info.finish_s = now();
         std::lock_guard<std::mutex> lk(mu);
-        used_bytes -= r->est_bytes;
+        used_bytes -= r->held_bytes;
+        r->held_bytes = 0;
+        --n_admitted;
         r->done = true;
+        admit_locked();
         cv_done.notify_all();
     }
 
-    // build the context and start the solve; false if it failed (request finished)
-    bool activate(Request *r)
+    // builder thread: context, device copies of b and x, Krylov workspace
+    void build_loop()
     {
-        r->info.admit_s = now();
-        try {
-            fmmbem_mesh mesh{(int64_t)(r->xyz.size() / 3), (int64_t)(r->tri.size() / 3), r->xyz.data(), r->tri.data()};
-            hipStream_t st = streams[r->stream];
-            int rc = fmmbem_build(&mesh, r->kernel, &r->prm, st, &r->ctx);
-            if (rc != FMMBEM_OK) {
-                finish(r, rc);
-                return false;
+        (void)hipSetDevice(device);
+        while (true) {
+            Request *r;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_build.wait(lk, [&] { return stop || !to_build.empty(); });
+                if (stop)
+                    break;
+                r = to_build.front();
+                to_build.pop_front();
             }
-            r->d_b = r->ctx->arena.alloc<double>(r->ctx->n);
-            r->d_x = r->ctx->arena.alloc<double>(r->ctx->n);
-            FB_HIP(hipMemcpyAsync(r->d_b, r->bc.data(), sizeof(double) * r->ctx->n, hipMemcpyHostToDevice, st));
+            try {
+                fmmbem_mesh mesh{(int64_t)(r->xyz.size() / 3), (int64_t)(r->tri.size() / 3), r->xyz.data(),
+                                 r->tri.data()};
+                int rc = fmmbem_build(&mesh, r->kernel, &r->prm, build_stream, &r->ctx);
+                if (rc != FMMBEM_OK) {
+                    finish(r, rc);
+                    continue;
+                }
+                r->d_b = r->ctx->arena.alloc<double>(r->ctx->n);
+                r->d_x = r->ctx->arena.alloc<double>(r->ctx->n);
+                FB_HIP(hipMemcpyAsync(r->d_b, r->bc.data(), sizeof(double) * r->ctx->n, hipMemcpyHostToDevice,
+                                      build_stream));
+                reserve_krylov(r->ctx, r->sched.restart);
+                FB_HIP(hipStreamSynchronize(build_stream));
+            } catch (const Error &e) {
+                set_last_error(e.what());
+                (void)hipStreamSynchronize(build_stream);
+                finish(r, e.code);
+                continue;
+            } catch (...) {
+                (void)hipStreamSynchronize(build_stream);
+                finish(r, FMMBEM_EINTERNAL);
+                continue;
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            const int64_t real = context_bytes(r->ctx);
+            used_bytes += real - r->held_bytes;
+            r->held_bytes = real;
+            ready.push_back(r);
+            admit_locked();
+            cv_work.notify_all();
+        }
+    }
+
+    // start the solve of a built request; false if it finished already
+    bool start(Request *r)
+    {
+        try {
+            hipStream_t st = streams[r->stream];
             r->gm.reset(new GmresState(r->ctx, r->d_b, r->tol, &r->sched, r->d_x, st));
             r->gm->start();
             if (r->gm->done) {
@@ -145,9 +223,11 @@ struct fmmbem_server {
             }
         } catch (const Error &e) {
             set_last_error(e.what());
+            (void)hipStreamSynchronize(streams[r->stream]);
             finish(r, e.code);
             return false;
         } catch (...) {
+            (void)hipStreamSynchronize(streams[r->stream]);
             finish(r, FMMBEM_EINTERNAL);
             return false;
         }
@@ -159,24 +239,18 @@ struct fmmbem_server {
         (void)hipSetDevice(device);
         int rr = 0;
         while (true) {
-            std::vector<Request *> admit;
+            std::vector<Request *> fresh;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+                cv_work.wait(lk, [&] { return stop || !ready.empty() || !active.empty(); });
                 if (stop)
                     break;
-                while (!queue.empty() && (int)(active.size() + admit.size()) < prm.max_active) {
-                    Request *r = queue.front();
-                    if (used_bytes + r->est_bytes > prm.hbm_budget_bytes && !(active.empty() && admit.empty()))
-                        break;  // wait for memory; a lone request is always admitted
-                    queue.pop_front();
-                    used_bytes += r->est_bytes;
-                    admit.push_back(r);
-                }
+                fresh.assign(ready.begin(), ready.end());
+                ready.clear();
             }
-            for (Request *r : admit) {
+            for (Request *r : fresh) {
                 r->stream = rr++ % (int)streams.size();
-                if (activate(r))
+                if (start(r))
                     active.push_back(r);
             }
             if (active.empty())
@@ -245,8 +319,10 @@ int fmmbem_server_create(const fmmbem_server_params *p, fmmbem_server_t **out)
             FB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
             s->streams.push_back(st);
         }
+        FB_HIP(hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking));
         s->t_origin = std::chrono::steady_clock::now();
         s->worker = std::thread([s] { s->loop(); });
+        s->builder = std::thread([s] { s->build_loop(); });
         *out = s;
         return FMMBEM_OK;
     } catch (const Error &e) {
@@ -288,7 +364,7 @@ int fmmbem_submit(fmmbem_server_t *srv, const fmmbem_mesh *mesh, const double *b
         *ticket = r->ticket;
         srv->queue.push_back(r.get());
         srv->all[r->ticket] = std::move(r);
-        srv->cv_work.notify_all();
+        srv->admit_locked();
         return FMMBEM_OK;
     } catch (const Error &e) {
         set_last_error(e.what());
@@ -349,11 +425,25 @@ void fmmbem_server_destroy(fmmbem_server_t *srv)
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stop = true;
         srv->cv_work.notify_all();
+        srv->cv_build.notify_all();
     }
+    if (srv->builder.joinable())
+        srv->builder.join();
     if (srv->worker.joinable())
         srv->worker.join();
+    // built but never started: release their contexts
+    std::vector<Request *> left;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        left.assign(srv->ready.begin(), srv->ready.end());
+        srv->ready.clear();
+    }
+    for (Request *r : left)
+        srv->finish(r, FMMBEM_EBUSY);
     for (auto st : srv->streams)
         (void)hipStreamDestroy(st);
+    if (srv->build_stream)
+        (void)hipStreamDestroy(srv->build_stream);
     delete srv;
 }
 

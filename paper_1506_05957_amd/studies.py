@@ -54,10 +54,10 @@ def solve_cell(fb, torch, mesh, tol, sched, ncrit=64):
     return t.cpu().numpy().reshape(-1, 3), rep, dt
 
 
-def richardson(fb, syn, torch):
+def richardson(fb, syn, torch, levels=(3, 4, 5, 6)):
     relaxed = fb.schedule(fb.STOKES)
     rows = []
-    for level in (3, 4, 5, 6):
+    for level in levels:
         m = syn.rbc(level)
         t, rep, dt = solve_cell(fb, torch, m, 1e-6, relaxed)
         fx = float(np.sum(t[:, 0] * panel_areas(m.xyz, m.tri)))
@@ -74,10 +74,10 @@ def richardson(fb, syn, torch):
             "paper": {"f_x": {"512": -0.057, "2048": -0.070, "8192": -0.077}, "observed_order": 0.52}}
 
 
-def iterations_vs_n(fb, syn, torch):
+def iterations_vs_n(fb, syn, torch, levels=(2, 3, 4, 5, 6)):
     fixed = fb.schedule(fb.STOKES, rule=fb.FIXED, p_min=16, mixed=0)
     out = []
-    for level in (2, 3, 4, 5, 6):
+    for level in levels:
         m = syn.rbc(level)
         _, rep, dt = solve_cell(fb, torch, m, 1e-5, fixed)
         out.append({"panels": m.n_panels, "iterations": rep["iterations"], "solve_s": dt,
@@ -85,11 +85,11 @@ def iterations_vs_n(fb, syn, torch):
     return {"runs": out, "paper": "18 iterations at N = 128 rising to 39 at 8192, about the same beyond"}
 
 
-def multi_cell(fb, syn, torch):
+def multi_cell(fb, syn, torch, cells=(2, 4, 8), levels=(4, 5, 6)):
     sched = fb.schedule(fb.STOKES, p_init=16, p_min=5)
     out = []
-    for n_cells in (2, 4, 8):
-        for level in (4, 5, 6):
+    for n_cells in cells:
+        for level in levels:
             m = syn.rbc_scene(n_cells, level, 0)
             _, rep, dt = solve_cell(fb, torch, m, 1e-5, sched)
             out.append({"cells": n_cells, "panels_per_cell": m.n_panels // n_cells, "iterations": rep["iterations"],
