@@ -212,6 +212,23 @@ int fmmbem_matvec(fmmbem_ctx_t *ctx, int32_t p, int32_t precision, const double 
 int fmmbem_solve_ctx(fmmbem_ctx_t *ctx, const double *b_dev, double tol, const fmmbem_schedule *s,
                      double *x_dev, fmmbem_report *report, void *hip_stream);
 
+/* The same solve as fmmbem_solve_ctx with nothing allocated, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the Krylov workspace
+ * (basis, residual, partial sums) comes from one static device array of
+ * FMMBEM_STATIC_SCRATCH_BYTES per device, held until the process ends, and
+ * the Hessenberg column from pinned memory the context made at build.
+ * GMRES(m) on n unknowns needs about 8 ((m + 3) n + 2 (m + 1) 256) bytes;
+ * EINVAL beyond the array, for restart > FMMBEM_STATIC_MAX_RESTART, when the
+ * context's device is not the current one, or while per-stage timing is on.
+ * Every call on one device shares that array: calls that overlap on one
+ * device (any contexts, any streams) race.  Results equal fmmbem_solve_ctx's
+ * bit for bit.  Synchronises hip_stream like fmmbem_solve_ctx. */
+#define FMMBEM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+#define FMMBEM_STATIC_MAX_RESTART 64
+int fmmbem_solve_ctx_static(fmmbem_ctx_t *ctx, const double *b_dev, double tol, const fmmbem_schedule *s,
+                            double *x_dev, fmmbem_report *report, void *hip_stream);
+
 /* One-shot solve: build with default params (mu from params when given),
  * copy bc (n doubles, host) to the device, solve, copy x back (host). */
 int fmmbem_solve(const fmmbem_mesh *mesh, const double *bc_host, int kernel, double tol,

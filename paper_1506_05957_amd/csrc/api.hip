@@ -182,6 +182,10 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         FB_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
         FB_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
         FB_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+        FB_HIP(hipEventCreateWithFlags(&ctx->ev_h_s, hipEventDisableTiming));
+        FB_HIP(hipHostMalloc((void **)&ctx->hcol_s, sizeof(double) * hcol_len(FMMBEM_STATIC_MAX_RESTART),
+                             hipHostMallocMapped));
+        FB_HIP(hipHostGetDevicePointer((void **)&ctx->hcol_s_dev, ctx->hcol_s, 0));
         build_geometry_and_tree(ctx, mesh, st);
         build_correction(ctx, st);
         build_translations(ctx, st);
@@ -241,6 +245,20 @@ int fmmbem_solve_ctx(fmmbem_ctx_t *ctx, const double *b_dev, double tol, const f
     FB_REQUIRE(ctx && b_dev && x_dev, FMMBEM_EINVAL, "null argument");
     validate_schedule(ctx, s, tol);
     return run_solve(ctx, b_dev, tol, s, x_dev, report, static_cast<hipStream_t>(hip_stream));
+    API_END
+}
+
+int fmmbem_solve_ctx_static(fmmbem_ctx_t *ctx, const double *b_dev, double tol, const fmmbem_schedule *s,
+                            double *x_dev, fmmbem_report *report, void *hip_stream)
+{
+    API_BEGIN
+    FB_REQUIRE(ctx && b_dev && x_dev, FMMBEM_EINVAL, "null argument");
+    validate_schedule(ctx, s, tol);
+    FB_REQUIRE(s->restart <= FMMBEM_STATIC_MAX_RESTART, FMMBEM_EINVAL,
+               "restart above FMMBEM_STATIC_MAX_RESTART for the static workspace");
+    FB_REQUIRE(ctx->timing.mask == 0u, FMMBEM_EINVAL,
+               "per-stage timing creates HIP events: turn it off for the allocation-free solve");
+    return run_solve_static(ctx, b_dev, tol, s, x_dev, report, static_cast<hipStream_t>(hip_stream));
     API_END
 }
 
@@ -317,6 +335,10 @@ void fmmbem_destroy(fmmbem_ctx_t *ctx)
         (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join)
         (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_h_s)
+        (void)hipEventDestroy(ctx->ev_h_s);
+    if (ctx->hcol_s)
+        (void)hipHostFree(ctx->hcol_s);
     if (ctx->side)
         (void)hipStreamDestroy(ctx->side);
     delete ctx;

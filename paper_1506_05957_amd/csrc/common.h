@@ -353,6 +353,10 @@ struct fmmbem_ctx {
     int spec_prec = -1;
     int spec_up_p = -1;
     bool spec_near = false;  // the near field of those charges already launched
+    // Hessenberg column of fmmbem_solve_ctx_static (pinned, device-mapped,
+    // made at build for restarts up to FMMBEM_STATIC_MAX_RESTART) and its event
+    double *hcol_s = nullptr, *hcol_s_dev = nullptr;
+    hipEvent_t ev_h_s = nullptr;
 };
 
 namespace fmmbem {
@@ -441,6 +445,10 @@ void free_krylov(fmmbem_ctx *ctx);
 // allocate the context's Krylov workspace for GMRES(m) now (a solve would on
 // its first call)
 void reserve_krylov(fmmbem_ctx *ctx, int m);
+// GMRES with the Krylov workspace in the library's static device array
+// (fmmbem_solve_ctx_static); no device or host memory is allocated
+int run_solve_static(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
+                     fmmbem_report *rep, hipStream_t st);
 // timing helpers (api.hip); timing_resolve reads every pending event pair
 void timing_resolve(Timing &T);
 void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev);

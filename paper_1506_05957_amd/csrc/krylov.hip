@@ -655,6 +655,93 @@ void GmresState::fill_report(fmmbem_report *r) const
     r->t_krylov_s = timed[3] ? t[3] : -1.0;
 }
 
+namespace {
+
+// Workspace of the allocation-free solve: the Krylov basis, w, r, the
+// per-block partial sums and y of GMRES(m), carved from one static device
+// array of FMMBEM_STATIC_SCRATCH_BYTES.  Each device holds its own copy at
+// its own address, which hipGetSymbolAddress gives once per device; host
+// code uses only that address.  Every such solve on a device shares its copy
+// (calls that overlap on one device race; nothing in it needs clearing: each
+// buffer is written before it is read).
+static __device__ __align__(256) double scratch[FMMBEM_STATIC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[MAX_DEVICES] = {};
+
+double *scratch_ptr(int device)
+{
+    FB_REQUIRE(device >= 0 && device < MAX_DEVICES, FMMBEM_EDEVICE, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *ptr = nullptr;
+        FB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch[device] = static_cast<double *>(ptr);
+    }
+    return g_scratch[device];
+}
+
+// host arrays of the Givens update for restarts up to FMMBEM_STATIC_MAX_RESTART
+thread_local double g_host_static[4 * FMMBEM_STATIC_MAX_RESTART + 2 +
+                                  (FMMBEM_STATIC_MAX_RESTART + 1) * FMMBEM_STATIC_MAX_RESTART];
+
+}  // namespace
+
+int run_solve_static(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x,
+                     fmmbem_report *rep, hipStream_t st)
+{
+    int dev = -1;
+    FB_HIP(hipGetDevice(&dev));
+    FB_REQUIRE(dev == ctx->device, FMMBEM_EINVAL, "the context's device is not the current device");
+    const int m = s->restart;
+    const int64_t n = ctx->n;
+    KrylovWork kw;
+    kw.owned = false;
+    kw.m = m;
+    kw.n = n;
+    krylov_blocks(n, &kw.nb, &kw.rpt);
+    // sub-buffers at 256-byte boundaries (32 doubles)
+    auto up = [](int64_t v) { return (v + 31) / 32 * 32; };
+    const int64_t sizes[7] = {(int64_t)(m + 1) * n, n, n, (int64_t)(m + 1) * kw.nb, (int64_t)(m + 1) * kw.nb,
+                              kw.nb, m + 1};
+    int64_t need = 0;
+    for (int64_t v : sizes)
+        need += up(v);
+    const int64_t cap = (int64_t)(FMMBEM_STATIC_SCRATCH_BYTES / sizeof(double));
+    FB_REQUIRE(need <= cap, FMMBEM_EINVAL,
+               "GMRES(" + std::to_string(m) + ") on " + std::to_string(n) + " unknowns needs " +
+                   std::to_string(need * 8) + " bytes of workspace; the static workspace holds " +
+                   std::to_string(cap * 8));
+    double *base = scratch_ptr(dev);
+    double *bufs[7];
+    int64_t off = 0;
+    for (int i = 0; i < 7; ++i) {
+        bufs[i] = base + off;
+        off += up(sizes[i]);
+    }
+    kw.V = bufs[0];
+    kw.w = bufs[1];
+    kw.r = bufs[2];
+    kw.part1 = bufs[3];
+    kw.part2 = bufs[4];
+    kw.partn = bufs[5];
+    kw.y = bufs[6];
+    kw.hcol = ctx->hcol_s;
+    kw.hcol_dev = ctx->hcol_s_dev;
+    kw.ev_h = ctx->ev_h_s;
+    std::fill(kw.hcol, kw.hcol + hcol_len(m), 0.0);
+    GmresState G(ctx, b, tol, s, x, st, rep, &kw, g_host_static);
+    G.start();
+    while (!G.done) {
+        G.enqueue_step();
+        G.complete_step();
+    }
+    G.t1 = std::chrono::steady_clock::now();
+    G.fill_report(rep);
+    return G.converged ? FMMBEM_OK : FMMBEM_ENOCONV;
+}
+
 int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedule *s, double *x, fmmbem_report *rep,
               hipStream_t st)
 {

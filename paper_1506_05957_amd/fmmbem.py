@@ -88,6 +88,7 @@ _sig("fmmbem_schedule_default", None, [P(fmmbem_schedule), ctypes.c_int])
 _sig("fmmbem_build", ctypes.c_int, [P(fmmbem_mesh), ctypes.c_int, P(fmmbem_params), c_vp, P(c_vp)])
 _sig("fmmbem_matvec", ctypes.c_int, [c_vp, c_i32, c_i32, c_vp, c_vp, c_vp])
 _sig("fmmbem_solve_ctx", ctypes.c_int, [c_vp, c_vp, c_d, P(fmmbem_schedule), c_vp, P(fmmbem_report), c_vp])
+_sig("fmmbem_solve_ctx_static", ctypes.c_int, [c_vp, c_vp, c_d, P(fmmbem_schedule), c_vp, P(fmmbem_report), c_vp])
 _sig("fmmbem_solve", ctypes.c_int, [P(fmmbem_mesh), P(c_d), ctypes.c_int, c_d, P(fmmbem_schedule),
                                     P(fmmbem_params), P(c_d), P(fmmbem_report)])
 _sig("fmmbem_get_stats", ctypes.c_int, [c_vp, P(fmmbem_stats)])
@@ -239,6 +240,19 @@ def fmmbem_solve_ctx(ctx: Context, b: torch.Tensor, tol: float, sched: fmmbem_sc
     r, bufs = _report(hist_cap)
     rc = _check(_lib.fmmbem_solve_ctx(ctx.handle, _dev_ptr(b, ctx.n, "b"), tol, ctypes.byref(sched),
                                       _dev_ptr(x, ctx.n, "x"), ctypes.byref(r), _stream(stream)),
+                allow=(OK, ENOCONV))
+    d = _report_dict(r, bufs)
+    d["status"] = rc
+    return d
+
+
+def fmmbem_solve_ctx_static(ctx: Context, b: torch.Tensor, tol: float, sched: fmmbem_schedule, x: torch.Tensor,
+                            stream=None, hist_cap: int = 1000):
+    """fmmbem_solve_ctx with the Krylov workspace in the library's static
+    device array: allocates nothing."""
+    r, bufs = _report(hist_cap)
+    rc = _check(_lib.fmmbem_solve_ctx_static(ctx.handle, _dev_ptr(b, ctx.n, "b"), tol, ctypes.byref(sched),
+                                             _dev_ptr(x, ctx.n, "x"), ctypes.byref(r), _stream(stream)),
                 allow=(OK, ENOCONV))
     d = _report_dict(r, bufs)
     d["status"] = rc
