@@ -49,7 +49,7 @@ TOL = 1e-6
 # stage of the library's timing -> kernel that runs it (rocprofv3 names)
 STAGE_KERNEL = {
     "stokes": {"p2p_fp32": "k_p2p<float, 1>", "p2p_fp64": "k_p2p<double, 1>",
-               "m2l_fp32": "k_m2l_mfma<float, 4, 1|4>", "m2l_fp64": "k_m2l_valu<double, 4, 2>"},
+               "m2l_fp32": "k_m2l_mfma<float, 4, 1|4>", "m2l_fp64": "k_m2l_stored<4>|k_m2l_valu<double, 4, 2>"},
     "laplace": {"p2p_fp32": "k_p2p<float, 0>", "p2p_fp64": "k_p2p<double, 0>",
                 "m2l_fp32": "k_m2l_mfma<float, 1, 1|4>", "m2l_fp64": "k_m2l_valu<double, 1, 8>"},
 }
@@ -174,7 +174,8 @@ def cells_headline(args, fb, syn, torch, dev):
     fixed = fb.schedule(fb.STOKES, rule=fb.FIXED, p_init=16, p_min=16, mixed=0, restart=50)
 
     t0 = time.perf_counter()
-    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=args.ncrit_relaxed, p_max=16))
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=args.ncrit_relaxed, p_max=16,
+                                                             m2l_stored=int(args.m2l == "stored")))
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     stats = fb.fmmbem_get_stats(ctx)
@@ -228,7 +229,8 @@ def cells_headline(args, fb, syn, torch, dev):
         return out
 
     # relaxed on the fixed schedule's tree (N_CRIT 256), for a same-tree factor
-    ctx2 = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=args.ncrit_fixed, p_max=16))
+    ctx2 = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=args.ncrit_fixed, p_max=16,
+                                                              m2l_stored=int(args.m2l == "stored")))
     fb.fmmbem_solve_ctx(ctx2, u, TOL, fixed, x)  # warm-up
     t_fix, r_fix = timed_solves(fb, torch, ctx2, u, x, fixed, args.fixed_reps)
     out["fixed"] = {"solve_ms": summary_ms(t_fix), **rep_summary(r_fix), "ncrit": args.ncrit_fixed}
@@ -611,6 +613,8 @@ def main():
     ap.add_argument("--ncrit-relaxed", type=int, default=128)
     ap.add_argument("--ncrit-fixed", type=int, default=256)
     ap.add_argument("--fixed-reps", type=int, default=5, help="fixed-p solves of the 64-cell case (>= 5)")
+    ap.add_argument("--m2l", choices=("stored", "fly"), default="stored",
+                    help="FP64 M2L operators of the 64-cell case: stored at build or generated per mat-vec")
     ap.add_argument("--cmp-reps", type=int, default=20, help="solves per schedule of the secondary workloads")
     ap.add_argument("--matvec-reps", type=int, default=100, help="event-timed mat-vecs per order")
     ap.add_argument("--cpu-rows", type=int, default=4096, help="rows of the oracle's sampled mat-vec")
@@ -687,7 +691,7 @@ def main():
         "config": {"workload": "stokes_sl_64rbc_131072panels_uniform_flow_relaxed16to4_mixed_tol1e-6",
                    "panels": stats["n_panels"], "unknowns": stats["n_unknowns"], "sources": stats["n_sources"],
                    "cells": 64, "panels_per_cell": 2048, "scene_seed": 0, "mu": 1.0, "theta": 0.5,
-                   "ncrit": args.ncrit_relaxed, "restart": 50, "near_field": "on the fly"},
+                   "ncrit": args.ncrit_relaxed, "restart": 50, "near_field": "on the fly", "m2l_fp64": args.m2l},
         "solve_ms": {"relaxed_mixed": rel["solve_ms"], "fixed_p16_fp64": fixed["solve_ms"] if fixed else None},
         "speedup_relaxed_vs_fixed": fixed["solve_ms"]["p50"] / rel["solve_ms"]["p50"] if fixed else None,
         "relaxed_mixed": {k: v for k, v in rel.items() if k != "solve_ms"},

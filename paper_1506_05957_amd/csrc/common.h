@@ -163,6 +163,18 @@ struct DevArena {
 };
 
 // The octree and lists in sorted (Morton) order, as built on the device.
+// first unit of each of the 8 XCD groups of a launch, and the end
+struct XcdGroups {
+    int32_t b[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t max_count() const
+    {
+        int32_t m = 0;
+        for (int x = 0; x < 8; ++x)
+            m = b[x + 1] - b[x] > m ? b[x + 1] - b[x] : m;
+        return m;
+    }
+};
+
 struct Tree {
     int64_t nt = 0;
     int32_t nbox = 0, nlevels = 0, nleaf = 0, max_leaf = 0;
@@ -185,6 +197,16 @@ struct Tree {
     int32_t n_unit = 0;
     int64_t n_chunk = 0;
     int4 *p2p_unit = nullptr;     // [n_unit] first target, end target, first chunk, end chunk
+    // launch order of the on-the-fly P2P: block b runs unit p2p_xcd.b[b % 8] +
+    // b / 8 of XCD group b % 8 (groups of consecutive units with equal work,
+    // heaviest unit first within a group).  A unit whose work exceeds the cap
+    // is cut into pieces (chunk ranges of the same targets) that write partial
+    // sums to slots of p2p_part, added in piece order by k_p2p_pieces
+    XcdGroups p2p_xcd;
+    int32_t *p2p_dst = nullptr;   // [n_unit] -1: the unit writes y_near; else its partial slot
+    int32_t n_slot = 0, n_split = 0;
+    double *p2p_part = nullptr;   // [n_slot][3][64] partial sums of the pieces
+    int4 *p2p_split = nullptr;    // [n_split] first target, target count, first slot, pieces
     int2 *p2p_chunk = nullptr;    // [n_chunk] first source, count | 1 << 16 if it is the target's own leaf
     float4 *p2p_choff = nullptr;  // [n_chunk] target leaf centre - source leaf centre (FP32), 0
     // host copies of small metadata

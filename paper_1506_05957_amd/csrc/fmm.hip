@@ -1433,10 +1433,12 @@ __device__ __forceinline__ void p2p_phase(const Src<R, vec_src<KIND>()> *__restr
         if constexpr (KIND == FMMBEM_LAPLACE_SL) {
             acc[0] += sv.q * rinv;
         } else if constexpr (KIND == FMMBEM_STOKES_SL) {
-            const R dot = (dx * sv.f0 + dy * sv.f1 + dz * sv.f2) * (rinv * rinv * rinv);
-            acc[0] += sv.f0 * rinv + dx * dot;
-            acc[1] += sv.f1 * rinv + dy * dot;
-            acc[2] += sv.f2 * rinv + dz * dot;
+            // f / r + d (d . f) / r^3 = (f + d q) / r with q = (d . f) / r^2:
+            // two fused multiply-adds per component, straight into acc
+            const R q = (dx * sv.f0 + dy * sv.f1 + dz * sv.f2) * (rinv * rinv);
+            acc[0] += rinv * (sv.f0 + dx * q);
+            acc[1] += rinv * (sv.f1 + dy * q);
+            acc[2] += rinv * (sv.f2 + dz * q);
         } else {  // dipole w x n: (w x n) . (t - y) / r^3
             acc[0] += (dx * sv.f0 + dy * sv.f1 + dz * sv.f2) * (rinv * rinv * rinv);
         }
@@ -1444,11 +1446,12 @@ __device__ __forceinline__ void p2p_phase(const Src<R, vec_src<KIND>()> *__restr
 }
 
 template <typename R, int KIND>
-__global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, const int4 *__restrict__ units,
+__global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(XcdGroups xg, const int4 *__restrict__ units,
                                                         const int2 *__restrict__ chunks,
                                                         const float4 *__restrict__ choff, int64_t nt,
                                                         const double *__restrict__ tc, const float *__restrict__ tc32,
                                                         const Src<R, vec_src<KIND>()> *__restrict__ src,
+                                                        const int32_t *__restrict__ dst, double *__restrict__ part,
                                                         double *__restrict__ ynear)
 {
     static_assert(P2P_TILE == 128, "two staged sources per lane");
@@ -1456,10 +1459,11 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, 
     constexpr int NQ = KIND == FMMBEM_STOKES_SL ? 3 : 1;
     __shared__ Src<R, VS> tile[P2P_WAVES][P2P_TILE];
     __shared__ R red[P2P_WAVES][NQ][64];
-    // blocks are dealt to the 8 XCDs round robin; give each XCD a contiguous
-    // run of units so that neighbouring units share its L2
-    const int g = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
-    if (g >= nunit)
+    // blocks are dealt to the 8 XCDs round robin; XCD x runs the units of
+    // its group (consecutive units, which share source leaves in its L2)
+    const int x = (int)(blockIdx.x % 8);
+    const int g = xg.b[x] + (int)(blockIdx.x / 8);
+    if (g >= xg.b[x + 1])
         return;
     const int4 u = units[g];
     const int tb = u.x, n = u.y - u.x;  // 1 <= n <= 64; chunks hold at most (128 / P) P sources
@@ -1544,13 +1548,31 @@ __global__ __launch_bounds__(64 * P2P_WAVES) void k_p2p(int nunit, int per_xcd, 
     for (int a = 0; a < NQ; ++a)
         red[w][a][lane] = active ? acc[a] : R(0);
     __syncthreads();
-    for (int x = threadIdx.x; x < NQ * n; x += 64 * P2P_WAVES) {
-        const int a = x / n, tt = x - a * n;
+    // a whole unit writes its targets' sums, a piece of one its partial slot
+    const int slot = dst[g];
+    double *out = slot < 0 ? ynear + (int64_t)NQ * tb : part + (int64_t)slot * 3 * 64;
+    for (int e = threadIdx.x; e < NQ * n; e += 64 * P2P_WAVES) {
+        const int a = e / n, tt = e - a * n;
         double sum = 0.0;
         for (int v = 0; v < P2P_WAVES; ++v)
             for (int q = 0; q < P; ++q)
                 sum += (double)red[v][a][q * n + tt];
-        ynear[(int64_t)NQ * (tb + tt) + a] = sum;
+        out[NQ * tt + a] = sum;
+    }
+}
+
+// The targets of units cut into pieces: the pieces' partial sums added in
+// piece order (one block per cut unit).
+template <int NQ>
+__global__ __launch_bounds__(256) void k_p2p_pieces(const int4 *__restrict__ splits, const double *__restrict__ part,
+                                                    double *__restrict__ ynear)
+{
+    const int4 r = splits[blockIdx.x];  // first target, count, first slot, pieces
+    for (int e = threadIdx.x; e < NQ * r.y; e += blockDim.x) {
+        double sum = 0.0;
+        for (int j = 0; j < r.w; ++j)
+            sum += part[(int64_t)(r.z + j) * 3 * 64 + e];
+        ynear[(int64_t)NQ * r.x + e] = sum;
     }
 }
 
@@ -1725,10 +1747,15 @@ void launch_side_near(fmmbem_ctx *ctx)
         stage_end(ctx, SO + 0, ctx->side, ev, 2.0 * (STOKES ? 9.0 : 1.0) * (double)ctx->nearm.entries);
     } else {
         if (T.n_unit > 0) {
-            const int per_xcd = (T.n_unit + 7) / 8;
-            k_p2p<R, KIND><<<8 * per_xcd, 64 * P2P_WAVES, 0, ctx->side>>>(
-                T.n_unit, per_xcd, T.p2p_unit, T.p2p_chunk, T.p2p_choff, nt, G.tc, G.tc32, src, ctx->y_near);
+            k_p2p<R, KIND><<<8 * T.p2p_xcd.max_count(), 64 * P2P_WAVES, 0, ctx->side>>>(
+                T.p2p_xcd, T.p2p_unit, T.p2p_chunk, T.p2p_choff, nt, G.tc, G.tc32, src, T.p2p_dst, T.p2p_part,
+                ctx->y_near);
             FB_HIP(hipGetLastError());
+            if (T.n_split > 0) {
+                constexpr int NQ = STOKES ? 3 : 1;
+                k_p2p_pieces<NQ><<<T.n_split, 256, 0, ctx->side>>>(T.p2p_split, T.p2p_part, ctx->y_near);
+                FB_HIP(hipGetLastError());
+            }
         }
         // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
         const double fl = STOKES ? 30.0 : KIND == FMMBEM_LAPLACE_DL ? 18.0 : 12.0;

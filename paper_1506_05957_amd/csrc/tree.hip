@@ -398,14 +398,103 @@ template <typename T> void exclusive_scan(const T *in, T *out, int64_t n, hipStr
     FB_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, st));
 }
 
-// P2P work units.  Each leaf gives ceil(n / 64) units of at most 64 targets
-// (one per lane when the wave runs one phase).  A unit of n targets runs
-// P = floor(64 / n) phases; its sources are the leaf's P2P source leaves cut
+// P2P work units.  A leaf's targets are cut into units of at most 64 (one
+// per lane when the wave runs one phase).  A unit of n targets runs
+// P = floor(64 / n) phases, so it costs the waves about S / P steps for S
+// sources: a leaf of 33 to 53 targets left whole costs S (a third to half of
+// the lanes idle), cut into 32 + the rest it costs S / 2 + S / floor(64 /
+// rest) <= 0.83 S, and that cut is made (from 54 on it would save less than
+// the second pass over the sources costs) unless the near field is stored
+// (its product takes one lane per target and gains nothing from phases).
+// Its sources are the leaf's P2P source leaves cut
 // into chunks of at most floor(P2P_TILE / P) P consecutive sources, so that a
 // chunk padded to a multiple of P still fits one tile.  The chunks are sorted
 // by decreasing size so that dealing them round robin to the waves of a block
 // balances the waves.  The FP32 offset of a chunk
 // is the difference of the two leaf centres, rounded once from FP64.
+// Launch order of the on-the-fly P2P (the units as built are in Morton
+// order).  A unit's work is its wave steps, sum over its chunks of
+// ceil(count / P).  Blocks are dealt to the XCDs round robin and a unit runs
+// as one block of P2P_WAVES waves, so a unit with a large share of the work
+// (a dense cluster of panels) ends long after the others and leaves its XCD
+// idle: units above 1/1024 of the total are cut into pieces of about that
+// work (contiguous chunk ranges; each writes a partial slot), the units are
+// split into 8 consecutive groups of equal work, one per XCD (consecutive,
+// so that a group's units share source leaves in its L2), and within a group
+// the heaviest come first, so the light ones fill the end.
+void schedule_p2p(std::vector<int4> &units, const std::vector<int2> &chunks, std::vector<int32_t> &dst,
+                  std::vector<int4> &splits, XcdGroups &xg)
+{
+    auto steps = [&](int c, int P) { return (int64_t)((chunks[c].y & 0xffff) + P - 1) / P; };
+    std::vector<int64_t> work(units.size(), 0);
+    int64_t total = 0;
+    for (size_t i = 0; i < units.size(); ++i) {
+        const int P = 64 / (units[i].y - units[i].x);
+        for (int c = units[i].z; c < units[i].w; ++c)
+            work[i] += steps(c, P);
+        total += work[i];
+    }
+    const int64_t cap = std::max<int64_t>(1, (total + 1023) / 1024);
+    struct Item { int4 u; int32_t dst; int64_t work; };
+    std::vector<Item> items;
+    items.reserve(units.size() + 64);
+    int32_t slot = 0;
+    for (size_t i = 0; i < units.size(); ++i) {
+        const int4 u = units[i];
+        const int nch = u.w - u.z;
+        const int64_t k = std::min<int64_t>(nch, (work[i] + cap - 1) / cap);
+        if (k <= 1) {
+            items.push_back({u, -1, work[i]});
+            continue;
+        }
+        const int P = 64 / (u.y - u.x);
+        splits.push_back(make_int4(u.x, u.y - u.x, slot, (int)k));
+        int c = u.z;
+        int64_t acc = 0;
+        for (int64_t j = 0; j < k; ++j) {
+            const int c0 = c;
+            int64_t wj = 0;
+            // at least one chunk per piece and enough left for the rest
+            while (c < u.w - (k - 1 - j) && (c == c0 || acc + steps(c, P) <= (j + 1) * work[i] / k)) {
+                acc += steps(c, P);
+                wj += steps(c, P);
+                ++c;
+            }
+            if (j == k - 1)
+                while (c < u.w) {
+                    wj += steps(c, P);
+                    ++c;
+                }
+            items.push_back({make_int4(u.x, u.y, c0, c), slot++, wj});
+        }
+    }
+    // 8 consecutive groups of equal work, heaviest first within each
+    std::vector<int> grp(items.size());
+    int64_t pre = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+        const int64_t mid = 2 * pre + items[i].work;  // twice the item's midpoint
+        grp[i] = (int)std::min<int64_t>(7, total > 0 ? (8 * mid) / (2 * total) : 0);
+        pre += items[i].work;
+    }
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < items.size(); ++i)
+        order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return grp[a] != grp[b] ? grp[a] < grp[b] : items[a].work > items[b].work;
+    });
+    units.resize(items.size());
+    dst.assign(items.size(), -1);
+    for (int x = 0; x <= 8; ++x)
+        xg.b[x] = 0;
+    for (size_t i = 0; i < order.size(); ++i) {
+        units[i] = items[order[i]].u;
+        dst[i] = items[order[i]].dst;
+        xg.b[grp[order[i]] + 1]++;
+    }
+    for (int x = 0; x < 8; ++x)
+        xg.b[x + 1] += xg.b[x];
+}
+
 void build_p2p_units(fmmbem_ctx *ctx, const std::vector<int32_t> &hp, int64_t n_p2p, hipStream_t st)
 {
     Tree &T = ctx->tree;
@@ -424,10 +513,12 @@ void build_p2p_units(fmmbem_ctx *ctx, const std::vector<int32_t> &hp, int64_t n_
     std::vector<float4> offs;
     struct Piece { int32_t begin, count, self, leaf; };
     std::vector<Piece> pieces;
+    const bool split = ctx->prm.near_stored == 0;
     for (int t : leaves) {
         const int tb = hb[6 * t + 1], te = hb[6 * t + 2];
-        for (int u0 = tb; u0 < te; u0 += 64) {
-            const int nu = std::min(te, u0 + 64) - u0;
+        for (int u0 = tb, nu = 0; u0 < te; u0 += nu) {
+            const int rest = te - u0;
+            nu = rest >= 64 ? 64 : (split && rest > 32 && rest <= 53) ? 32 : rest;
             const int cap = (P2P_TILE / (64 / nu)) * (64 / nu);  // a multiple of the unit's phase count
             pieces.clear();
             for (int64_t e = first[t]; e < first[t + 1]; ++e) {
@@ -449,14 +540,32 @@ void build_p2p_units(fmmbem_ctx *ctx, const std::vector<int32_t> &hp, int64_t n_
             units.push_back(make_int4(u0, u0 + nu, c0, (int32_t)chunks.size()));
         }
     }
+    std::vector<int32_t> dst(units.size(), -1);
+    std::vector<int4> splits;
+    if (split)
+        schedule_p2p(units, chunks, dst, splits, T.p2p_xcd);
+    else
+        for (int x = 0; x <= 8; ++x)  // consecutive groups of equal count
+            T.p2p_xcd.b[x] = (int32_t)std::min<size_t>(units.size(), x * ((units.size() + 7) / 8));
     T.n_unit = (int32_t)units.size();
     T.n_chunk = (int64_t)chunks.size();
+    T.n_split = (int32_t)splits.size();
+    T.n_slot = 0;
+    for (const int4 &r : splits)
+        T.n_slot += r.w;
     DevArena &A = ctx->arena;
     T.p2p_unit = A.alloc<int4>(std::max<size_t>(units.size(), 1));
     T.p2p_chunk = A.alloc<int2>(std::max<size_t>(chunks.size(), 1));
     T.p2p_choff = A.alloc<float4>(std::max<size_t>(offs.size(), 1));
-    if (!units.empty())
+    T.p2p_dst = A.alloc<int32_t>(std::max<size_t>(dst.size(), 1));
+    T.p2p_split = A.alloc<int4>(std::max<size_t>(splits.size(), 1));
+    T.p2p_part = A.alloc<double>((size_t)std::max(T.n_slot, 1) * 3 * 64);
+    if (!units.empty()) {
         FB_HIP(hipMemcpyAsync(T.p2p_unit, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice, st));
+        FB_HIP(hipMemcpyAsync(T.p2p_dst, dst.data(), sizeof(int32_t) * dst.size(), hipMemcpyHostToDevice, st));
+    }
+    if (!splits.empty())
+        FB_HIP(hipMemcpyAsync(T.p2p_split, splits.data(), sizeof(int4) * splits.size(), hipMemcpyHostToDevice, st));
     if (!chunks.empty()) {
         FB_HIP(hipMemcpyAsync(T.p2p_chunk, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice, st));
         FB_HIP(hipMemcpyAsync(T.p2p_choff, offs.data(), sizeof(float4) * offs.size(), hipMemcpyHostToDevice, st));
