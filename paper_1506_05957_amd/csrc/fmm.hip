@@ -340,6 +340,122 @@ __global__ __launch_bounds__(256) void k_p2m(int p, int ncs, const int32_t *__re
     }
 }
 
+// P2M at the high orders, where the per-thread accumulators of k_p2m (2 (p+1)
+// values per channel and the step coefficients) no longer fit the registers
+// of several waves.  One block per leaf; the leaf's sources go through in
+// tiles of TS = floor(blockDim / (p + 1)).  Phase 1: thread (s, m) runs the
+// recurrence of k_p2m for source s and order m and writes conj(R_n^m), n =
+// m..p, to the tile's harmonics in LDS.  Phase 2: thread (coefficient,
+// channel) adds q conj(R) over the tile's sources in source order into one
+// accumulator that it keeps across the tiles.  The charges of a tile sit
+// beside the harmonics (Stokes: f and f . (y - c)).
+template <typename R, int NCH>
+__global__ __launch_bounds__(256) void k_p2m_tile(int p, int ncs, const int32_t *__restrict__ leaves,
+                                                  const int32_t *__restrict__ box_i, const double *__restrict__ box_r,
+                                                  double side, const Src<R, NCH == 4> *__restrict__ src,
+                                                  cplx<R> *__restrict__ M)
+{
+    using S = Src<R, NCH == 4>;
+    constexpr int ITEMS = 4;  // (coefficient, channel) items per thread: nc NCH <= 4 * 256 up to p = 20
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nm = p + 1, nc = ncoef(p);
+    const int ts = (int)blockDim.x / nm;
+    cplx<R> *H = reinterpret_cast<cplx<R> *>(smem_raw);  // [ts][nc]
+    R *Q = reinterpret_cast<R *>(smem_raw + sizeof(cplx<R>) * (size_t)ts * nc);  // [ts][NCH]
+    const int b = leaves[blockIdx.x];
+    const int lv = box_i[6 * b], pb = box_i[6 * b + 1], pe = box_i[6 * b + 2];
+    const double s = ldexp(side, -(lv + 1));
+    const double *c = box_r + 5 * (int64_t)b;
+    const R is = (R)(1.0 / s);
+    const int m = threadIdx.x % nm, sl = threadIdx.x / nm;
+    R ar[ITEMS], ai[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        ar[k] = ai[k] = 0;
+    const int64_t s0 = 4 * (int64_t)pb, s1 = 4 * (int64_t)pe;
+    for (int64_t t0 = s0; t0 < s1; t0 += ts) {
+        const int cnt = (int)std::min<int64_t>(ts, s1 - t0);
+        __syncthreads();  // the previous tile has been read
+        if (sl < cnt) {
+            const S sv = src[t0 + sl];
+            R x, y, z;  // relative to the leaf centre
+            if constexpr (sizeof(R) == 8) {
+                x = sv.x - c[0];
+                y = sv.y - c[1];
+                z = sv.z - c[2];
+            } else {
+                x = sv.x;
+                y = sv.y;
+                z = sv.z;
+            }
+            if (m == 0) {
+                if constexpr (NCH == 1) {
+                    Q[sl] = sv.q;
+                } else {
+                    Q[4 * sl] = sv.f0;
+                    Q[4 * sl + 1] = sv.f1;
+                    Q[4 * sl + 2] = sv.f2;
+                    Q[4 * sl + 3] = (sv.f0 * x + sv.f1 * y) + sv.f2 * z;
+                }
+            }
+            x *= is;
+            y *= is;
+            z *= is;
+            const R r2 = x * x + y * y + z * z;
+            cplx<R> *h = H + (int64_t)sl * nc;
+            // the diagonal R_m^m, then the column R_n^m, n > m
+            R cr = 1, ci = 0;
+            for (int n = 1; n <= m; ++n) {
+                const R al = -inv_int<R>(2 * n);
+                const R A = al * x, B = al * y;
+                const R nr = A * cr - B * ci, ni = A * ci + B * cr;
+                cr = nr;
+                ci = ni;
+            }
+            h[cidx(m, m)] = cplx<R>{cr, -ci};
+            R pr = 0, pi = 0;
+            for (int n = m + 1; n <= p; ++n) {
+                const R f = inv_int<R>((n - m) * (n + m));
+                const R A = R(2 * n - 1) * f * z, G = n >= m + 2 ? f * r2 : R(0);
+                const R nr = A * cr - G * pr, ni = A * ci - G * pi;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+                h[cidx(n, m)] = cplx<R>{cr, -ci};
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int it = threadIdx.x + k * (int)blockDim.x;
+            if (it < nc * NCH) {
+                const int ch = it / nc, idx = it - ch * nc;
+                for (int j = 0; j < cnt; ++j) {
+                    const cplx<R> hv = H[(int64_t)j * nc + idx];
+                    const R q = Q[NCH * j + ch];
+                    ar[k] += q * hv.re;
+                    ai[k] += q * hv.im;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int it = threadIdx.x + k * (int)blockDim.x;
+        if (it < nc * NCH) {
+            const int ch = it / nc, idx = it - ch * nc;
+            M[((int64_t)b * NCH + ch) * ncs + idx] = cplx<R>{ar[k], ai[k]};
+        }
+    }
+}
+
+template <typename R, int NCH> size_t p2m_tile_shm(int p)
+{
+    const int ts = 256 / (p + 1);
+    return sizeof(cplx<R>) * (size_t)ts * ncoef(p) + sizeof(R) * (size_t)ts * NCH;
+}
+
 // P2M of dipole sources (the double layer): a moment d = w x n at y has
 // the multipole sum conj(d . grad R_n^m(y - c)), and with the gradient
 // identities of the factorial-normalised harmonics
@@ -1143,36 +1259,47 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_
         const int nsl_here = max(1, (int)blockDim.x / span);
         const int ch = t / nc, idx = t - ch * nc;
         R sr = 0, si = 0;
-        if (sl < nsl_here && !FIXC) {
+        if (sl < nsl_here) {
             // U reads issued together (clamped to the last pair, the extra
-            // ones dropped), then added in pair order
-            constexpr int U = 8;
+            // ones dropped), then added in pair order; the fourth channel's
+            // change of centre reads its pair's first three channels and
+            // source centre in the same batch
+            constexpr int U = FIXC ? 4 : 8;
             for (int e = e0 + sl; e < e1; e += U * nsl_here) {
                 cplx<R> v[U];
+                int64_t ee[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    v[u] = Y[(int64_t)min(e + u * nsl_here, e1 - 1) * no + t];
+                for (int u = 0; u < U; ++u) {
+                    ee[u] = min(e + u * nsl_here, e1 - 1);
+                    v[u] = Y[ee[u] * no + t];
+                }
+                if constexpr (FIXC) {
+                    if (ch == 3) {
+                        cplx<R> y0[U], y1[U], y2[U];
+                        int sb[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const cplx<R> *y = Y + ee[u] * no + idx;
+                            y0[u] = y[0];
+                            y1[u] = y[nc];
+                            y2[u] = y[2 * nc];
+                            sb[u] = src[ee[u]];
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const double *cS = box_r + 5 * (int64_t)sb[u];
+                            const R g0 = (R)(cS[0] - cT[0]), g1 = (R)(cS[1] - cT[1]), g2 = (R)(cS[2] - cT[2]);
+                            v[u].re += g0 * y0[u].re + g1 * y1[u].re + g2 * y2[u].re;
+                            v[u].im += g0 * y0[u].im + g1 * y1[u].im + g2 * y2[u].im;
+                        }
+                    }
+                }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
                     if (e + u * nsl_here < e1) {
                         sr += v[u].re;
                         si += v[u].im;
                     }
-            }
-        } else if (sl < nsl_here) {
-            for (int e = e0 + sl; e < e1; e += nsl_here) {
-                const cplx<R> v = Y[(int64_t)e * no + t];
-                sr += v.re;
-                si += v.im;
-                if constexpr (FIXC) {
-                    if (ch == 3) {
-                        const double *cS = box_r + 5 * (int64_t)src[e];
-                        const R g0 = (R)(cS[0] - cT[0]), g1 = (R)(cS[1] - cT[1]), g2 = (R)(cS[2] - cT[2]);
-                        const cplx<R> *y = Y + (int64_t)e * no + idx;
-                        sr += g0 * y[0].re + g1 * y[nc].re + g2 * y[2 * nc].re;
-                        si += g0 * y[0].im + g1 * y[nc].im + g2 * y[2 * nc].im;
-                    }
-                }
             }
         }
         __syncthreads();
@@ -1305,17 +1432,20 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
     constexpr int NCH = STOKES ? 4 : 1;
     constexpr int NV = STOKES ? 3 : 1;        // potentials evaluated
     constexpr int NG = STOKES ? 12 : 0;       // gradients evaluated (channel x direction)
-    __shared__ cplx<R> V[NV][NC_MAX];
-    __shared__ cplx<R> G[NG > 0 ? NG : 1][STOKES ? NC_MAX : 1];
+    // the expansions of the order at hand only (l2p_shm): sized for p, not
+    // for the largest order, so that many leaves' blocks share a CU
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nc = ncoef(p);
+    cplx<R> *V = reinterpret_cast<cplx<R> *>(smem_raw);  // [NV][nc]
+    cplx<R> *G = V + NV * nc;                              // [NG][nc] (gradients: order p - 1)
     const int b = leaves[blockIdx.x];
     const int lv = box_i[6 * b], tb = box_i[6 * b + 1], te = box_i[6 * b + 2];
     const double s = ldexp(side, -(lv + 1));
     const double *c = box_r + 5 * (int64_t)b;
-    const int nc = ncoef(p);
     const cplx<R> *Lb = L + (int64_t)b * NCH * ncs;
     for (int t = threadIdx.x; t < nc; t += blockDim.x)
         for (int a = 0; a < NV; ++a)
-            V[a][t] = Lb[a * ncs + t];
+            V[a * nc + t] = Lb[a * ncs + t];
     if constexpr (STOKES) {
         // gradient expansions (order p-1): dz: L_{j+1}^k; dx: (L_{j+1}^{k-1} - L_{j+1}^{k+1}) / 2;
         // dy: (i/2) (L_{j+1}^{k-1} + L_{j+1}^{k+1})
@@ -1329,9 +1459,9 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
                 if (k + 1 > j + 1)
                     bb = cplx<R>{0, 0};
                 cplx<R> cz = load_full(E, j + 1, k);
-                G[3 * ch + 0][t] = cplx<R>{R(0.5) * (a.re - bb.re), R(0.5) * (a.im - bb.im)};
-                G[3 * ch + 1][t] = cplx<R>{-R(0.5) * (a.im + bb.im), R(0.5) * (a.re + bb.re)};
-                G[3 * ch + 2][t] = cz;
+                G[(3 * ch + 0) * nc + t] = cplx<R>{R(0.5) * (a.re - bb.re), R(0.5) * (a.im - bb.im)};
+                G[(3 * ch + 1) * nc + t] = cplx<R>{-R(0.5) * (a.im + bb.im), R(0.5) * (a.re + bb.re)};
+                G[(3 * ch + 2) * nc + t] = cz;
             }
         }
     }
@@ -1349,12 +1479,12 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
         sweep_regular<R>(p, x, y, z, [&](int id, int n, R wr, R wi) {
 #pragma unroll
             for (int a = 0; a < NV; ++a)
-                pot[a] += V[a][id].re * wr + V[a][id].im * wi;
+                pot[a] += V[a * nc + id].re * wr + V[a * nc + id].im * wi;
             if constexpr (STOKES) {
                 if (n < p) {
 #pragma unroll
                     for (int g = 0; g < NG; ++g)
-                        grd[g] += G[g][id].re * wr + G[g][id].im * wi;
+                        grd[g] += G[g * nc + id].re * wr + G[g * nc + id].im * wi;
                 }
             }
         });
@@ -1804,12 +1934,9 @@ void up_pass(fmmbem_ctx *ctx, int p, hipStream_t st)
                 k_p2m<R, NCH, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
             else if (p <= 8)
                 k_p2m<R, NCH, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-            else if (p <= 12)
-                k_p2m<R, NCH, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
-            else if (p <= 16)
-                k_p2m<R, NCH, 16><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
             else
-                k_p2m<R, NCH, 20><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+                k_p2m_tile<R, NCH><<<T.nleaf, 256, p2m_tile_shm<R, NCH>(p), st>>>(p, ncs, T.leaves, T.box_i, T.box_r,
+                                                                                side, src, M);
         }
         FB_HIP(hipGetLastError());
     }
@@ -1945,8 +2072,9 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 FB_HIP(hipGetLastError());
             }
             FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // L2P combines with the near field
-            k_l2p<R, KIND><<<T.nleaf, 64, 0, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L,
-                                                   ca);
+            constexpr int NQS = KIND == FMMBEM_STOKES_SL ? 3 + 12 : 1;
+            k_l2p<R, KIND><<<T.nleaf, 64, sizeof(cplx<R>) * NQS * ncoef(p), st>>>(
+                p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L, ca);
             FB_HIP(hipGetLastError());
         }
         stage_end(ctx, SO + 3, st, ev);
