@@ -73,14 +73,16 @@ def summary_ms(ts):
 
 # source regions the HBM counter records were taken on: file, first marker, end marker
 COUNTED_SOURCES = {
-    "k_p2p<float, 1>": [("fmm.hip", "// P2P: one block per work unit", "// ----"),
+    "k_p2p<float, 1>": [("fmm.hip", "// P2P: one block per work unit", "// The downward pass of one leaf"),
                         ("tree.hip", "// P2P work units", "}  // namespace")],
-    "k_p2p<float, 0>": [("fmm.hip", "// P2P: one block per work unit", "// ----"),
+    "k_p2p<float, 0>": [("fmm.hip", "// P2P: one block per work unit", "// The downward pass of one leaf"),
                         ("tree.hip", "// P2P work units", "}  // namespace")],
     "k_near_spmv<float, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
     "k_near_spmv<double, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
     "k_m2l_mfma<float, 4, 1|4>": [("fmm.hip", "// M2L, in two passes.", "// LDS of k_m2l_mfma")],
     "k_m2l_stored<1>": [("fmm.hip", "// Pass 1 in FP64 from the stored operators",
+                         "template <typename R> size_t m2l_mfma_shm")],
+    "k_m2l_stored<4>": [("fmm.hip", "// Pass 1 in FP64 from the stored operators",
                          "template <typename R> size_t m2l_mfma_shm")],
 }
 
@@ -507,7 +509,7 @@ def _requests(fb, syn, n_req, rate_hz):
 
 def _serve(fb, work, budget, max_active, saturate=False):
     scheds = {fb.LAPLACE: fb.schedule(fb.LAPLACE), fb.STOKES: fb.schedule(fb.STOKES)}
-    srv = fb.fmmbem_server_create(hbm_budget_bytes=budget, max_active=max_active, n_streams=4)
+    srv = fb.fmmbem_server_create(hbm_budget_bytes=budget, max_active=max_active, n_streams=max_active)
     tickets = []
     t0 = time.perf_counter()
     for r, mesh, kernel, bc in work:
@@ -554,7 +556,7 @@ def serving(args, fb, syn):
     fb.fmmbem_server_destroy(srv)
     T = float(np.mean(solo))
     out = {"workload": f"{n_req} requests, Laplace|Stokes on sphere|ellipsoid|RBC, 512-32768 panels, tol 1e-6, "
-                       f"8 GB admission budget, 16 slots",
+                       f"8 GB admission budget, 16 slots, 16 streams",
            "solo_service_ms": {"mean": 1e3 * T, "p50": 1e3 * pct(solo, 50), "n": len(solo)}}
     for f in args.serve_loads:
         lam = f / T
@@ -572,7 +574,8 @@ def serving(args, fb, syn):
 # ------------------------------------------------------------------ N_CRIT sweep
 def ncrit_sweep(args, fb, syn, torch, dev):
     """Solve time against N_CRIT for both schedules on the Laplace 32768-panel
-    sphere (on-the-fly near field) and the 64-cell Stokes case."""
+    sphere (on-the-fly near field) and the 64-cell Stokes case (stored FP64
+    M2L operators, as the headline)."""
     out = {"laplace_sphere32768": {}, "stokes_64rbc": {}}
     m = syn.sphere(6)
     b = torch.tensor(syn.ylm_rhs(m, 3, 0), device=dev)
@@ -591,8 +594,8 @@ def ncrit_sweep(args, fb, syn, torch, dev):
     m = syn.rbc_scene(64, 4, 0)
     u = torch.tensor(np.tile([1.0, 0.0, 0.0], m.n_panels), device=dev)
     x = torch.empty_like(u)
-    for nc in (32, 64, 128, 256, 512):
-        ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=nc, p_max=16))
+    for nc in (48, 64, 96, 128, 192, 256, 384):
+        ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=nc, p_max=16, m2l_stored=1))
         row = {}
         for name, s in (("relaxed_mixed", fb.schedule(fb.STOKES, p_init=16, p_min=4)),
                         ("fixed_p16_fp64", fb.schedule(fb.STOKES, rule=fb.FIXED, p_init=16, p_min=16, mixed=0))):

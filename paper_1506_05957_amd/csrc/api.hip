@@ -9,6 +9,7 @@
 namespace fmmbem {
 
 static thread_local std::string g_last_error;
+thread_local const PinnedProvider *t_pinned = nullptr;
 
 void set_last_error(const std::string &m) { g_last_error = m; }
 
@@ -183,8 +184,7 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         FB_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
         FB_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
         FB_HIP(hipEventCreateWithFlags(&ctx->ev_h_s, hipEventDisableTiming));
-        FB_HIP(hipHostMalloc((void **)&ctx->hcol_s, sizeof(double) * hcol_len(FMMBEM_STATIC_MAX_RESTART),
-                             hipHostMallocMapped));
+        ctx->hcol_s = pinned_get(sizeof(double) * hcol_len(FMMBEM_STATIC_MAX_RESTART), &ctx->hcol_s_src);
         FB_HIP(hipHostGetDevicePointer((void **)&ctx->hcol_s_dev, ctx->hcol_s, 0));
         build_geometry_and_tree(ctx, mesh, st);
         build_correction(ctx, st);
@@ -200,6 +200,7 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         ctx->L = ctx->arena.alloc<double>(2 * (size_t)ctx->tree.nbox * ctx->nch * ncs);
         ctx->y_near = ctx->arena.alloc<double>(ctx->n);
         ctx->y_far = ctx->arena.alloc<double>(ctx->n);
+        ctx->y_corr = ctx->arena.alloc<double>(ctx->n);
         FB_HIP(hipStreamSynchronize(st));
     } catch (...) {
         (void)hipStreamSynchronize(st);
@@ -320,9 +321,19 @@ int fmmbem_get_stats(const fmmbem_ctx_t *ctx, fmmbem_stats *o)
 
 void fmmbem_destroy(fmmbem_ctx_t *ctx)
 {
+    destroy_context(ctx, true);
+}
+
+}  // extern "C"
+
+namespace fmmbem {
+
+void destroy_context(fmmbem_ctx *ctx, bool sync_device)
+{
     if (!ctx)
         return;
-    (void)hipDeviceSynchronize();
+    if (sync_device)
+        (void)hipDeviceSynchronize();
     for (auto &pd : ctx->timing.pending) {
         (void)hipEventDestroy(pd.a);
         (void)hipEventDestroy(pd.b);
@@ -337,12 +348,15 @@ void fmmbem_destroy(fmmbem_ctx_t *ctx)
         (void)hipEventDestroy(ctx->ev_join);
     if (ctx->ev_h_s)
         (void)hipEventDestroy(ctx->ev_h_s);
-    if (ctx->hcol_s)
-        (void)hipHostFree(ctx->hcol_s);
+    pinned_put(ctx->hcol_s, ctx->hcol_s_src);
     if (ctx->side)
         (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }
+
+}  // namespace fmmbem
+
+extern "C" {
 
 int fmmbem_set_timing(fmmbem_ctx_t *ctx, int enabled)
 {

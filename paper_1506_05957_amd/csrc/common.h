@@ -135,6 +135,42 @@ struct DevAlloc {
     }
 };
 
+// Pinned, device-mapped host memory (the Hessenberg columns): hipHostMalloc,
+// or the provider installed for the calling thread when there is one (the
+// request loop keeps its own, because hipHostFree waits for the whole device
+// while other requests run).  The provider is recorded with the buffer, so it
+// goes back the same way from any thread.
+struct PinnedProvider {
+    void *(*get)(size_t bytes, void *user);
+    void (*put)(void *p, void *user);
+    void *user;
+};
+extern thread_local const PinnedProvider *t_pinned;
+inline double *pinned_get(size_t bytes, const PinnedProvider **src)
+{
+    *src = t_pinned;
+    void *p = nullptr;
+    if (t_pinned) {
+        p = t_pinned->get(bytes, t_pinned->user);
+        if (!p)
+            throw Error(FMMBEM_ENOMEM, "pinned host allocation failed");
+    } else {
+        hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocMapped);
+        if (e != hipSuccess)
+            throw Error(FMMBEM_ENOMEM, std::string("hipHostMalloc failed: ") + hipGetErrorString(e));
+    }
+    return static_cast<double *>(p);
+}
+inline void pinned_put(void *p, const PinnedProvider *src)
+{
+    if (!p)
+        return;
+    if (src)
+        src->put(p, src->user);
+    else
+        (void)hipHostFree(p);
+}
+
 // Device buffers owned by a context; freed in reverse order on destruction.
 struct DevArena {
     DevAlloc al;
@@ -329,6 +365,7 @@ struct KrylovWork {
     // kernels directly: h1[0..k], |w|^2 at k + 1, h2 at m + 2 + j, |b|^2 at
     // 2 (m + 2); the least-squares solution y (host-written) after it
     double *hcol = nullptr;      // host view, [hcol_len(m)]
+    const PinnedProvider *hcol_src = nullptr;
     double *hcol_dev = nullptr;  // the same memory, device view
     hipEvent_t ev_h = nullptr;   // the column of the last step is complete
     bool owned = true;           // V ... hcol, ev_h belong to this workspace
@@ -360,6 +397,7 @@ struct fmmbem_ctx {
     void *L = nullptr;         // same
     double *y_near = nullptr;  // [n] sorted order (P2P + far field, in kernel units)
     double *y_far = nullptr;   // [n]
+    double *y_corr = nullptr;  // [n] sorted order: the correction's product S x of the current mat-vec
     fmmbem::Timing timing;
     fmmbem::KrylovWork *kw = nullptr;
     fmmbem::NearMatrix nearm;
@@ -378,6 +416,7 @@ struct fmmbem_ctx {
     // Hessenberg column of fmmbem_solve_ctx_static (pinned, device-mapped,
     // made at build for restarts up to FMMBEM_STATIC_MAX_RESTART) and its event
     double *hcol_s = nullptr, *hcol_s_dev = nullptr;
+    const fmmbem::PinnedProvider *hcol_s_src = nullptr;
     hipEvent_t ev_h_s = nullptr;
 };
 
@@ -464,6 +503,10 @@ int run_solve(fmmbem_ctx *ctx, const double *b, double tol, const fmmbem_schedul
 // x[0..n) = 0 by a kernel (no memset node in a caller's capture)
 void fill_zero(double *x, int64_t n, hipStream_t st);
 void free_krylov(fmmbem_ctx *ctx);
+// fmmbem_destroy; without sync_device the caller has synchronised every
+// stream that used the context (the request loop, which must not drain the
+// device while other requests run)
+void destroy_context(fmmbem_ctx *ctx, bool sync_device);
 // allocate the context's Krylov workspace for GMRES(m) now (a solve would on
 // its first call)
 void reserve_krylov(fmmbem_ctx *ctx, int m);

@@ -1320,11 +1320,14 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_
 // The combine of a mat-vec for sorted target i: y[perm i] = pref (near +
 // far + sum_e S_ie x_e) over the correction entries e of row i, plus x / 2
 // for the second-kind operator; yf holds the far field of the target.
+// With ycorr the correction's product S x is already there (k_corr_spmv, by
+// sorted target) and the entries are not visited again.
 struct CombineArgs {
     const int32_t *perm, *cptr, *ccol;
     const double *cval, *x, *ynear;
     double pref;
     double *y;
+    const double *ycorr;
 };
 
 template <int KIND>
@@ -1333,9 +1336,16 @@ __device__ inline void combine_target(const CombineArgs &A, int64_t i, const dou
     const int64_t o = A.perm[i];
     if constexpr (KIND != FMMBEM_STOKES_SL) {
         double acc = A.ynear[i] + yf[0];
-        for (int e = A.cptr[i]; e < A.cptr[i + 1]; ++e)
-            acc += A.cval[e] * A.x[A.ccol[e]];
+        if (A.ycorr)
+            acc += A.ycorr[i];
+        else
+            for (int e = A.cptr[i]; e < A.cptr[i + 1]; ++e)
+                acc += A.cval[e] * A.x[A.ccol[e]];
         A.y[o] = KIND == FMMBEM_LAPLACE_DL ? 0.5 * A.x[o] + A.pref * acc : A.pref * acc;
+    } else if (A.ycorr) {
+        A.y[3 * o] = A.pref * ((A.ynear[3 * i] + yf[0]) + A.ycorr[3 * i]);
+        A.y[3 * o + 1] = A.pref * ((A.ynear[3 * i + 1] + yf[1]) + A.ycorr[3 * i + 1]);
+        A.y[3 * o + 2] = A.pref * ((A.ynear[3 * i + 2] + yf[2]) + A.ycorr[3 * i + 2]);
     } else {
         double a0 = A.ynear[3 * i] + yf[0], a1 = A.ynear[3 * i + 1] + yf[1], a2 = A.ynear[3 * i + 2] + yf[2];
         for (int e = A.cptr[i]; e < A.cptr[i + 1]; ++e) {
@@ -1350,6 +1360,49 @@ __device__ inline void combine_target(const CombineArgs &A, int64_t i, const dou
         A.y[3 * o + 1] = A.pref * a1;
         A.y[3 * o + 2] = A.pref * a2;
     }
+}
+
+// The correction's product yc = S x by sorted target (S: the near-singular
+// and self corrections, CSR by sorted target, columns in caller order; 1 or
+// 3 x 3 values per entry).  Sixteen lanes per row take its entries in turn;
+// the lanes' sums are joined by a fixed butterfly, so the result does not
+// depend on the launch.  Launched where the far-field stream would otherwise
+// wait for the near field, so that the combine reads one value per component.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_corr_spmv(int64_t nt, const int32_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                   const double *__restrict__ x, double *__restrict__ yc)
+{
+    const int64_t i = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int l = threadIdx.x & 15;
+    double a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        a[q] = 0.0;
+    if (i < nt) {
+        const int c1 = ptr[i + 1];
+        for (int e = ptr[i] + l; e < c1; e += 16) {
+            const int64_t jo = col[e];
+            if constexpr (NQ == 1) {
+                a[0] += val[e] * x[jo];
+            } else {
+                const double *v = val + 9 * (int64_t)e;
+                const double t0 = x[3 * jo], t1 = x[3 * jo + 1], t2 = x[3 * jo + 2];
+                a[0] += (v[0] * t0 + v[1] * t1) + v[2] * t2;
+                a[1] += (v[3] * t0 + v[4] * t1) + v[5] * t2;
+                a[2] += (v[6] * t0 + v[7] * t1) + v[8] * t2;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            a[q] += __shfl_xor(a[q], off, 16);
+    if (l == 0 && i < nt)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            yc[NQ * i + q] = a[q];
 }
 
 // combine_target for one channel with the target's inputs already read:
@@ -1742,8 +1795,8 @@ __global__ __launch_bounds__(256) void k_down_leaf(int p, int ncs, int opd, cons
     R x0, y0, z0;
     target_rel<R>(ic, nt, s, cb, tc, tc32, x0, y0, z0);
     const int64_t o0 = ca.perm[ic];
-    const double yn0 = ca.ynear[ic];
-    const int c00 = ca.cptr[ic], c01 = ca.cptr[ic + 1];
+    const double yn0 = ca.ycorr ? ca.ynear[ic] + ca.ycorr[ic] : ca.ynear[ic];
+    const int c00 = ca.ycorr ? 0 : ca.cptr[ic], c01 = ca.ycorr ? 0 : ca.cptr[ic + 1];
     const double xo0 = KIND == FMMBEM_LAPLACE_DL ? ca.x[o0] : 0.0;
     R *own = reinterpret_cast<R *>(smem_raw);  // [nch][D]
     R *ts = own + nch * D;                     // [nch - 1][D][D]: chain[c + 1] into chain[c], input-major
@@ -1934,6 +1987,8 @@ void up_pass(fmmbem_ctx *ctx, int p, hipStream_t st)
                 k_p2m<R, NCH, 4><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
             else if (p <= 8)
                 k_p2m<R, NCH, 8><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
+            else if (NCH == 1 && p <= 12)  // one channel: the column sweep still fits (160 VGPRs in FP64)
+                k_p2m<R, NCH, 12><<<T.nleaf, 256, shm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, src, M);
             else
                 k_p2m_tile<R, NCH><<<T.nleaf, 256, p2m_tile_shm<R, NCH>(p), st>>>(p, ncs, T.leaves, T.box_i, T.box_r,
                                                                                 side, src, M);
@@ -1971,6 +2026,17 @@ void up_pass(fmmbem_ctx *ctx, int p, hipStream_t st)
 // charges that the near-field launch wrote before it; st joins the side stream before L2P,
 // which combines far and near field into y.  Without a far field: y_far = 0,
 // join and combine.
+// the correction's product into ctx->y_corr on st (see k_corr_spmv)
+template <int KIND>
+void corr_spmv(fmmbem_ctx *ctx, const CombineArgs &ca, hipStream_t st)
+{
+    if (!ca.ycorr)
+        return;
+    constexpr int NQ = KIND == FMMBEM_STOKES_SL ? 3 : 1;
+    k_corr_spmv<NQ><<<grid_for(ctx->nt, 16), 256, 0, st>>>(ctx->nt, ca.cptr, ca.ccol, ca.cval, ca.x, ctx->y_corr);
+    FB_HIP(hipGetLastError());
+}
+
 template <typename R, int KIND>
 void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bool have_up)
 {
@@ -2053,6 +2119,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         if constexpr (NCH == 1) {
             const size_t dshm = down_leaf_shm<R>(p, std::max(1, T.nlevels - std::max(P.lmin_tgt, 0)));
             if (dshm > 0) {
+                corr_spmv<KIND>(ctx, ca, st);  // while the near field may still run
                 FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // the combine needs the near field
                 k_down_leaf<R, KIND><<<T.nleaf, 256, dshm, st>>>(p, ncs, P.op_dim, l2l_op, P.leaf_rec, T.box_r,
                                                                  side, nt, G.tc, G.tc32, L, ca);
@@ -2071,6 +2138,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                     p, ncs, P.op_dim, l2l_op, P.tiles, t0, P.level_list, T.box_i, T.box_r, L, L);
                 FB_HIP(hipGetLastError());
             }
+            corr_spmv<KIND>(ctx, ca, st);  // while the near field may still run
             FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // L2P combines with the near field
             constexpr int NQS = KIND == FMMBEM_STOKES_SL ? 3 + 12 : 1;
             k_l2p<R, KIND><<<T.nleaf, 64, sizeof(cplx<R>) * NQS * ncoef(p), st>>>(
@@ -2082,6 +2150,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         hipEvent_t ev4;
         stage_begin(ctx, SO + 4, st, &ev4);
         fill_zero(ctx->y_far, ctx->n, st);
+        corr_spmv<KIND>(ctx, ca, st);
         FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         k_combine<KIND><<<grid_for(nt, 64), 64, 0, st>>>(nt, ca, ctx->y_far);
         FB_HIP(hipGetLastError());
@@ -2223,7 +2292,8 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
     const double pref = kind == FMMBEM_STOKES_SL   ? -1.0 / (8.0 * M_PI * ctx->prm.mu)
                         : kind == FMMBEM_LAPLACE_DL ? -1.0 / (4.0 * M_PI)
                                                     : 1.0 / (4.0 * M_PI);
-    const CombineArgs ca{ctx->tree.perm, C.ptr, C.col_orig, C.val, x, ctx->y_near, pref, y};
+    const CombineArgs ca{ctx->tree.perm, C.ptr, C.col_orig, C.val, x, ctx->y_near, pref, y,
+                         C.nnz > 0 ? ctx->y_corr : nullptr};
     far_dispatch(ctx, p, prec, ca, st, have_up);  // ends with the join and the combine
     ctx->near_pending = false;
 }

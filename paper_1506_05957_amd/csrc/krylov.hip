@@ -50,9 +50,8 @@ __device__ double block_total(double s, double *__restrict__ sh)
 
 // x - sum_{j < nv} c[j] V_j[i] in the order j = 0, 1, ...; the loads of
 // AXPY_UNROLL vectors are issued together so that their latencies overlap.
-// With c2, the coefficient is c[j] + c2[j].
 __device__ inline double sub_combination(double x, const double *__restrict__ V, int64_t ldv, int nv, int64_t i,
-                                         const double *__restrict__ c, const double *__restrict__ c2)
+                                         const double *__restrict__ c)
 {
     int j = 0;
     for (; j + AXPY_UNROLL <= nv; j += AXPY_UNROLL) {
@@ -62,33 +61,24 @@ __device__ inline double sub_combination(double x, const double *__restrict__ V,
             v[u] = V[(int64_t)(j + u) * ldv + i];
 #pragma unroll
         for (int u = 0; u < AXPY_UNROLL; ++u)
-            x -= (c2 ? c[j + u] + c2[j + u] : c[j + u]) * v[u];
+            x -= c[j + u] * v[u];
     }
     for (; j < nv; ++j)
-        x -= (c2 ? c[j] + c2[j] : c[j]) * V[(int64_t)j * ldv + i];
+        x -= c[j] * V[(int64_t)j * ldv + i];
     return x;
 }
 
 // Classical Gram-Schmidt dots: block (b, g) takes row block b and the vectors
-// j = g CGS_JG .. + CGS_JG - 1 and writes part[j][b] = V_j . w' over its rows,
-// where w' = w - sum_{j < nv} h1[j] V_j when the first pass's partials hpart
-// are given (h1 summed from them, the update recomputed per block and not
-// stored) and w' = w otherwise.  Dynamic LDS: nv doubles.
+// j = g CGS_JG .. + CGS_JG - 1 and writes part[j][b] = V_j . w over its rows.
 constexpr int CGS_JG = 8;
 __global__ __launch_bounds__(DOT_BLOCK) void k_cgs_dots(int64_t n, int rpt, const double *__restrict__ V, int64_t ldv,
-                                                         int nv, const double *__restrict__ hpart,
-                                                         const double *__restrict__ w, double *__restrict__ part,
-                                                         int nb)
+                                                         int nv, const double *__restrict__ w,
+                                                         double *__restrict__ part, int nb)
 {
-    extern __shared__ double hs[];  // [nv] first-pass coefficients
     __shared__ double sh[CGS_JG][DOT_NWV];
     const int b = blockIdx.x, j0 = blockIdx.y * CGS_JG;
     const int nj = min(CGS_JG, nv - j0);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (hpart) {
-        block_sums(hpart, nb, nv, hs);
-        __syncthreads();
-    }
     double s[CGS_JG];
 #pragma unroll
     for (int jj = 0; jj < CGS_JG; ++jj)
@@ -98,9 +88,7 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_cgs_dots(int64_t n, int rpt, cons
         const int64_t i = base + (int64_t)k * DOT_BLOCK;
         if (i >= n)
             break;
-        double x = w[i];
-        if (hpart)
-            x = sub_combination(x, V, ldv, nv, i, hs, nullptr);
+        const double x = w[i];
         double v[CGS_JG];
 #pragma unroll
         for (int jj = 0; jj < CGS_JG; ++jj)
@@ -127,10 +115,29 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_cgs_dots(int64_t n, int rpt, cons
     }
 }
 
-// h1, h2 summed from the two passes' partials; w -= sum_{j<nv} (h1[j] + h2[j])
-// V_j, and the partial of |w|^2 of this row block into partn[b].  Block 0
-// also writes h1 to hout[0..nv) and h2 to hout[off2..off2 + nv) for the host.
-// Dynamic LDS: 2 nv doubles.
+// w -= sum_{j<nv} h1[j] V_j, h1 summed from the first pass's partials (every
+// block sums them in the same order).  Dynamic LDS: nv doubles.
+__global__ __launch_bounds__(DOT_BLOCK) void k_sub_first(int64_t n, int rpt, const double *__restrict__ V, int64_t ldv,
+                                                          int nv, const double *__restrict__ part1, int nb,
+                                                          double *__restrict__ w)
+{
+    extern __shared__ double hs[];  // [nv]
+    block_sums(part1, nb, nv, hs);
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * rpt * DOT_BLOCK + threadIdx.x;
+    for (int k = 0; k < rpt; ++k) {
+        const int64_t i = base + (int64_t)k * DOT_BLOCK;
+        if (i >= n)
+            break;
+        w[i] = sub_combination(w[i], V, ldv, nv, i, hs);
+    }
+}
+
+// h1, h2 summed from the two passes' partials; w -= sum_{j<nv} h2[j] V_j (h1
+// was taken off by k_sub_first before the second pass), and the partial of
+// |w|^2 of this row block into partn[b].  Block 0 also writes h1 to
+// hout[0..nv) and h2 to hout[off2..off2 + nv) for the host.  Dynamic LDS:
+// 2 nv doubles.
 __global__ __launch_bounds__(DOT_BLOCK) void k_update_norm(int64_t n, int rpt, const double *__restrict__ V,
                                                             int64_t ldv, int nv, const double *__restrict__ part1,
                                                             const double *__restrict__ part2, int nb,
@@ -154,7 +161,7 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_update_norm(int64_t n, int rpt, c
         const int64_t i = base + (int64_t)k * DOT_BLOCK;
         if (i >= n)
             break;
-        const double x = sub_combination(w[i], V, ldv, nv, i, hs, hs + nv);
+        const double x = sub_combination(w[i], V, ldv, nv, i, hs + nv);
         w[i] = x;
         s += x * x;
     }
@@ -237,8 +244,7 @@ void release_work(KrylovWork *kw)
 {
     if (kw->owned) {
         kw->arena.release();
-        if (kw->hcol)
-            (void)hipHostFree(kw->hcol);
+        pinned_put(kw->hcol, kw->hcol_src);
         if (kw->ev_h)
             (void)hipEventDestroy(kw->ev_h);
     }
@@ -268,7 +274,7 @@ KrylovWork *get_work(fmmbem_ctx *ctx, int m)
         kw->part2 = kw->arena.alloc<double>((size_t)(m + 1) * kw->nb);
         kw->partn = kw->arena.alloc<double>(kw->nb);
         kw->y = kw->arena.alloc<double>(m + 1);
-        FB_HIP(hipHostMalloc((void **)&kw->hcol, sizeof(double) * hcol_len(m), hipHostMallocMapped));
+        kw->hcol = pinned_get(sizeof(double) * hcol_len(m), &kw->hcol_src);
         std::fill(kw->hcol, kw->hcol + hcol_len(m), 0.0);
         FB_HIP(hipHostGetDevicePointer((void **)&kw->hcol_dev, kw->hcol, 0));
         FB_HIP(hipEventCreateWithFlags(&kw->ev_h, hipEventDisableTiming));
@@ -280,14 +286,11 @@ KrylovWork *get_work(fmmbem_ctx *ctx, int m)
     return kw;
 }
 
-// part[j][b] = V_j . w over row block b, j < nv; with hpart (the first
-// pass's partials), w' = w - sum_j h1[j] V_j in place of w
-void cgs_dots(KrylovWork *kw, const double *V, int nv, const double *w, double *part, hipStream_t st,
-              const double *hpart = nullptr)
+// part[j][b] = V_j . w over row block b, j < nv
+void cgs_dots(KrylovWork *kw, const double *V, int nv, const double *w, double *part, hipStream_t st)
 {
     dim3 grid(kw->nb, (nv + CGS_JG - 1) / CGS_JG);
-    const size_t shm = hpart ? sizeof(double) * nv : 0;
-    k_cgs_dots<<<grid, DOT_BLOCK, shm, st>>>(kw->n, kw->rpt, V, kw->n, nv, hpart, w, part, kw->nb);
+    k_cgs_dots<<<grid, DOT_BLOCK, 0, st>>>(kw->n, kw->rpt, V, kw->n, nv, w, part, kw->nb);
     FB_HIP(hipGetLastError());
 }
 
@@ -450,8 +453,12 @@ void GmresState::enqueue_step()
     ++matvecs;
     hipEvent_t ev;
     stage_begin(ctx, 10, st, &ev);
+    // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2 (below, with |w|^2)
     cgs_dots(kw, kw->V, k + 1, kw->w, kw->part1, st);
-    cgs_dots(kw, kw->V, k + 1, kw->w, kw->part2, st, kw->part1);
+    k_sub_first<<<kw->nb, DOT_BLOCK, sizeof(double) * (k + 1), st>>>(n, kw->rpt, kw->V, n, k + 1, kw->part1,
+                                                                      kw->nb, kw->w);
+    FB_HIP(hipGetLastError());
+    cgs_dots(kw, kw->V, k + 1, kw->w, kw->part2, st);
     // h1[0..k], |w|^2 at k + 1 and h2[0..k] at m + 2 go straight to the host column
     k_update_norm<<<kw->nb, DOT_BLOCK, 2 * sizeof(double) * (k + 1), st>>>(
         n, kw->rpt, kw->V, n, k + 1, kw->part1, kw->part2, kw->nb, kw->w, kw->partn, kw->hcol_dev, m + 2);

@@ -24,6 +24,7 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <vector>
 
 #include "common.h"
 
@@ -81,11 +82,98 @@ int64_t context_bytes(const fmmbem_ctx *ctx)
     return ctx->arena.bytes + (ctx->kw ? ctx->kw->arena.bytes : 0);
 }
 
+// Memory of the requests' contexts.  hipFree and hipHostFree wait for the
+// whole device, which would drain every other request's work each time one
+// ends; so blocks that a finished request gives back are kept, by size class,
+// and handed to later requests, and go back to HIP only when the server is
+// destroyed (or, for device memory, when an allocation fails: then every
+// cached block is freed and the allocation tried once more).
+struct BlockPool {
+    bool pinned = false;
+    std::mutex mu;
+    std::multimap<size_t, void *> cached;
+    std::map<void *, size_t> cls;  // every block made, with its size class
+
+    static size_t size_class(size_t b)
+    {
+        if (b <= ((size_t)64 << 10)) {
+            size_t c = 256;
+            while (c < b)
+                c <<= 1;
+            return c;
+        }
+        const size_t g = (size_t)1 << 20;
+        return (b + g - 1) / g * g;
+    }
+    void *make(size_t c)
+    {
+        void *p = nullptr;
+        if (pinned)
+            return hipHostMalloc(&p, c, hipHostMallocMapped) == hipSuccess ? p : nullptr;
+        return hipMalloc(&p, c) == hipSuccess ? p : nullptr;
+    }
+    void drop(void *p)
+    {
+        if (pinned)
+            (void)hipHostFree(p);
+        else
+            (void)hipFree(p);
+    }
+    void *get(size_t b)
+    {
+        const size_t c = size_class(b);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = cached.find(c);
+            if (it != cached.end()) {
+                void *p = it->second;
+                cached.erase(it);
+                return p;
+            }
+        }
+        void *p = make(c);
+        if (!p && !pinned) {
+            trim();
+            p = make(c);
+        }
+        if (p) {
+            std::lock_guard<std::mutex> lk(mu);
+            cls[p] = c;
+        }
+        return p;
+    }
+    void put(void *p)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cls.find(p);
+        if (it != cls.end())
+            cached.emplace(it->second, p);
+    }
+    void trim()
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &kv : cached) {
+            drop(kv.second);
+            cls.erase(kv.second);
+        }
+        cached.clear();
+    }
+    ~BlockPool()
+    {
+        for (auto &kv : cls)
+            drop(kv.first);
+    }
+    static void *get_cb(size_t b, void *u) { return static_cast<BlockPool *>(u)->get(b); }
+    static void put_cb(void *p, void *u) { static_cast<BlockPool *>(u)->put(p); }
+};
+
 }  // namespace
 
 struct fmmbem_server {
     fmmbem_server_params prm{};
     int device = 0;
+    BlockPool dev_pool, host_pool;  // declared first: released after every context
+    PinnedProvider pinned{BlockPool::get_cb, BlockPool::put_cb, nullptr};
     std::vector<hipStream_t> streams;
     hipStream_t build_stream = nullptr;
     std::mutex mu;
@@ -148,7 +236,11 @@ struct fmmbem_server {
         r->gm.reset();
         if (r->ctx) {
             r->info.device_bytes = context_bytes(r->ctx);
-            fmmbem_destroy(r->ctx);
+            // only this request's streams are waited for, not the device
+            (void)hipStreamSynchronize(streams[r->stream]);
+            if (r->ctx->side)
+                (void)hipStreamSynchronize(r->ctx->side);
+            destroy_context(r->ctx, false);
             r->ctx = nullptr;
         }
         r->d_b = r->d_x = nullptr;  // held by the context's arena
@@ -166,6 +258,7 @@ struct fmmbem_server {
     void build_loop()
     {
         (void)hipSetDevice(device);
+        t_pinned = &pinned;
         while (true) {
             Request *r;
             {
@@ -237,6 +330,7 @@ struct fmmbem_server {
     void loop()
     {
         (void)hipSetDevice(device);
+        t_pinned = &pinned;
         int rr = 0;
         while (true) {
             std::vector<Request *> fresh;
@@ -314,6 +408,8 @@ int fmmbem_server_create(const fmmbem_server_params *p, fmmbem_server_t **out)
             throw Error(FMMBEM_EINVAL, "server params out of range");
         }
         FB_HIP(hipGetDevice(&s->device));
+        s->host_pool.pinned = true;
+        s->pinned.user = &s->host_pool;
         for (int i = 0; i < s->prm.n_streams; ++i) {
             hipStream_t st;
             FB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -355,6 +451,11 @@ int fmmbem_submit(fmmbem_server_t *srv, const fmmbem_mesh *mesh, const double *b
         fmmbem_params_default(&r->prm);
         if (params)
             r->prm = *params;
+        if (!r->prm.alloc) {  // the server's own cache of device blocks
+            r->prm.alloc = BlockPool::get_cb;
+            r->prm.free = BlockPool::put_cb;
+            r->prm.alloc_user = &srv->dev_pool;
+        }
         if (r->sched.p_init > r->prm.p_max)
             r->prm.p_max = std::min(r->sched.p_init, FMMBEM_P_MAX);
         r->est_bytes = estimate_bytes(mesh->n_triangles, kernel, r->prm, r->sched);
