@@ -8,8 +8,9 @@ Gauss points, 393216 unknowns.  Stokes single layer, mu = 1, boundary data
 u = (1, 0, 0) at every centroid; GMRES(50) to a relative residual of 1e-6.
 A step is one relaxed solve: p from 16 down to p_min = 4 by the residual
 (Eq. 17/19), FP32 P2P/expansions once eps_k >= 1e-5, FP64 Arnoldi, Givens and
-true residuals, N_CRIT 128; `value` = such solves per second with the inputs
-resident in device memory.  Beside it: the fixed p = 16 FP64 solve (N_CRIT
+true residuals, N_CRIT 128, M2L by rotation from p = 8 (the direct product
+below); `value` = such solves per second with the inputs resident in device
+memory.  Beside it: the fixed p = 16 FP64 solve (N_CRIT
 256, the fastest for fixed p), p50 and max over the samples, the event-timed
 roofline of the P2P and M2L kernels inside the timed solves, and the oracle's
 CPU rate from a bounded row sample.
@@ -50,6 +51,10 @@ TOL = 1e-6
 STAGE_KERNEL = {
     "stokes": {"p2p_fp32": "k_p2p<float, 1>", "p2p_fp64": "k_p2p<double, 1>",
                "m2l_fp32": "k_m2l_mfma<float, 4, 1|4>", "m2l_fp64": "k_m2l_stored<4>|k_m2l_valu<double, 4, 2>"},
+    # M2L by rotation from p = 8 (the direct kernels below it)
+    "stokes_rot": {"p2p_fp32": "k_p2p<float, 1>", "p2p_fp64": "k_p2p<double, 1>",
+                   "m2l_fp32": "k_m2l_rot<float, 4, 2|4> (p >= 8), k_m2l_mfma<float, 4, 1|4> (p < 8)",
+                   "m2l_fp64": "k_m2l_rot<double, 4, 2>"},
     "laplace": {"p2p_fp32": "k_p2p<float, 0>", "p2p_fp64": "k_p2p<double, 0>",
                 "m2l_fp32": "k_m2l_mfma<float, 1, 1|4>", "m2l_fp64": "k_m2l_valu<double, 1, 8>"},
 }
@@ -70,6 +75,8 @@ def summary_ms(ts):
         out["max"] = float(a.max())
     return out
 
+
+M2L_MODES = {"fly": 0, "stored": 1, "rot": 2}  # params.m2l_stored
 
 # source regions the HBM counter records were taken on: file, first marker, end marker
 COUNTED_SOURCES = {
@@ -177,7 +184,7 @@ def cells_headline(args, fb, syn, torch, dev):
 
     t0 = time.perf_counter()
     ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=args.ncrit_relaxed, p_max=16,
-                                                             m2l_stored=int(args.m2l == "stored")))
+                                                             m2l_stored=M2L_MODES[args.m2l]))
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     stats = fb.fmmbem_get_stats(ctx)
@@ -215,7 +222,7 @@ def cells_headline(args, fb, syn, torch, dev):
            "stats": stats, "build_s": t_build, "mesh": m, "u": u, "x_relaxed": x_relaxed}
 
     workload = "stokes_64rbc"
-    names = STAGE_KERNEL["stokes"]
+    names = STAGE_KERNEL["stokes_rot" if args.m2l == "rot" else "stokes"]
     rl = {}
     for s in stages:
         peak = PEAK_FP32_VALU if s.endswith("fp32") else PEAK_FP64_VALU
@@ -232,7 +239,7 @@ def cells_headline(args, fb, syn, torch, dev):
 
     # relaxed on the fixed schedule's tree (N_CRIT 256), for a same-tree factor
     ctx2 = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=args.ncrit_fixed, p_max=16,
-                                                              m2l_stored=int(args.m2l == "stored")))
+                                                              m2l_stored=M2L_MODES[args.m2l]))
     fb.fmmbem_solve_ctx(ctx2, u, TOL, fixed, x)  # warm-up
     t_fix, r_fix = timed_solves(fb, torch, ctx2, u, x, fixed, args.fixed_reps)
     out["fixed"] = {"solve_ms": summary_ms(t_fix), **rep_summary(r_fix), "ncrit": args.ncrit_fixed}
@@ -616,8 +623,9 @@ def main():
     ap.add_argument("--ncrit-relaxed", type=int, default=128)
     ap.add_argument("--ncrit-fixed", type=int, default=256)
     ap.add_argument("--fixed-reps", type=int, default=5, help="fixed-p solves of the 64-cell case (>= 5)")
-    ap.add_argument("--m2l", choices=("stored", "fly"), default="stored",
-                    help="FP64 M2L operators of the 64-cell case: stored at build or generated per mat-vec")
+    ap.add_argument("--m2l", choices=tuple(M2L_MODES), default="rot",
+                    help="M2L of the 64-cell case: FP64 operators stored at build, generated per mat-vec, "
+                         "or by rotation from p = 8")
     ap.add_argument("--cmp-reps", type=int, default=20, help="solves per schedule of the secondary workloads")
     ap.add_argument("--matvec-reps", type=int, default=100, help="event-timed mat-vecs per order")
     ap.add_argument("--cpu-rows", type=int, default=4096, help="rows of the oracle's sampled mat-vec")
@@ -694,7 +702,7 @@ def main():
         "config": {"workload": "stokes_sl_64rbc_131072panels_uniform_flow_relaxed16to4_mixed_tol1e-6",
                    "panels": stats["n_panels"], "unknowns": stats["n_unknowns"], "sources": stats["n_sources"],
                    "cells": 64, "panels_per_cell": 2048, "scene_seed": 0, "mu": 1.0, "theta": 0.5,
-                   "ncrit": args.ncrit_relaxed, "restart": 50, "near_field": "on the fly", "m2l_fp64": args.m2l},
+                   "ncrit": args.ncrit_relaxed, "restart": 50, "near_field": "on the fly", "m2l": args.m2l},
         "solve_ms": {"relaxed_mixed": rel["solve_ms"], "fixed_p16_fp64": fixed["solve_ms"] if fixed else None},
         "speedup_relaxed_vs_fixed": fixed["solve_ms"]["p50"] / rel["solve_ms"]["p50"] if fixed else None,
         "relaxed_mixed": {k: v for k, v in rel.items() if k != "solve_ms"},

@@ -106,7 +106,15 @@ typedef struct {
      * call.  Memory: 8 D^2 bytes per translation, D = 2 ncoef(p_max) rounded
      * up to 16 rows (a sphere of 32768 panels at N_CRIT 64, p_max = 12: 2541
      * translations, 718 MB); see fmmbem_stats.n_translations and
-     * m2l_op_bytes.  0 (default): generated on the fly. */
+     * m2l_op_bytes.  0 (default): generated on the fly.
+     * 2: M2L by rotation at p >= 8 in both precisions: per translation
+     * direction, the real forms of the rotation taking the direction to +z
+     * and back (every degree <= p_max, FP64 and FP32) are built at build and
+     * stored; each pair's multipole expansion is rotated, translated along
+     * the axis, and its local expansion rotated back, O(p^3) per pair
+     * instead of O(p^4).  Below p = 8 as with 0.  Memory: 24 T bytes per
+     * direction, T = sum over n <= p_max of 64 ceil(2 (n + 1) / 16)
+     * ceil(2 (n + 1) / 4) (p_max = 16: 9664 values, 232 KB). */
     int32_t m2l_stored;
     /* Quadrature of Sec. 2.3, fixed by the method as built (0 = default;
      * any other value gives FMMBEM_EINVAL):
@@ -184,7 +192,7 @@ typedef struct {
     int64_t device_bytes;        /* device memory held by the context */
     int64_t near_entries;        /* panel pairs of the stored near field (0 unless near_stored) */
     int64_t n_translations;      /* distinct M2L translations (offset and box sizes) */
-    int64_t m2l_op_bytes;        /* stored FP64 M2L operators (0 unless m2l_stored) */
+    int64_t m2l_op_bytes;        /* stored M2L operators or rotations (0 unless m2l_stored) */
 } fmmbem_stats;
 
 /* Defaults described above. */

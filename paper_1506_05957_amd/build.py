@@ -21,6 +21,7 @@ ARCH = "gfx950"
 
 SOURCES = [
     ("rules.cpp", []),
+    ("rotations.cpp", []),
     ("tree.hip", ["-ffp-contract=off"]),
     ("near.hip", ["-ffp-contract=off"]),
     ("translations.hip", []),

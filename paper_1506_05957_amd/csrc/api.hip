@@ -146,7 +146,7 @@ static void validate_params(const fmmbem_params *p)
     FB_REQUIRE(p->p_max >= 1 && p->p_max <= FMMBEM_P_MAX, FMMBEM_EINVAL, "p_max must be in [1, 20]");
     FB_REQUIRE(p->mu > 0.0 && std::isfinite(p->mu), FMMBEM_EINVAL, "mu must be positive");
     FB_REQUIRE(p->near_stored == 0 || p->near_stored == 1, FMMBEM_EINVAL, "near_stored must be 0 or 1");
-    FB_REQUIRE(p->m2l_stored == 0 || p->m2l_stored == 1, FMMBEM_EINVAL, "m2l_stored must be 0 or 1");
+    FB_REQUIRE(p->m2l_stored >= 0 && p->m2l_stored <= 2, FMMBEM_EINVAL, "m2l_stored must be 0, 1 or 2");
     FB_REQUIRE(p->quad_far == 0 || p->quad_far == 4, FMMBEM_EINVAL, "quad_far: only the 4-point rule is built");
     FB_REQUIRE(p->quad_near == 0 || p->quad_near == 25, FMMBEM_EINVAL, "quad_near: only the 25-point rule is built");
     FB_REQUIRE(p->near_factor == 0.0 || p->near_factor == 2.0, FMMBEM_EINVAL,
@@ -191,7 +191,7 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         build_translations(ctx, st);
         if (prm.near_stored)
             build_near_matrix(ctx, st);
-        if (prm.m2l_stored)
+        if (prm.m2l_stored == 1)
             build_m2l_operators(ctx, st);
         const int ncs = ncoef(prm.p_max);
         ctx->charges = ctx->arena.alloc<double>((size_t)(kernel == FMMBEM_LAPLACE_SL ? 4 : 8) * ctx->nsrc);
@@ -314,7 +314,7 @@ int fmmbem_get_stats(const fmmbem_ctx_t *ctx, fmmbem_stats *o)
     o->device_bytes = ctx->arena.bytes + (ctx->kw ? ctx->kw->arena.bytes : 0);
     o->near_entries = ctx->nearm.entries;
     o->n_translations = ctx->m2l.n_trans;
-    o->m2l_op_bytes = ctx->m2l.ops_bytes;
+    o->m2l_op_bytes = ctx->m2l.ops_bytes + ctx->m2l.rot_bytes;
     return FMMBEM_OK;
     API_END
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -324,7 +325,26 @@ struct M2LPlan {
     double *ops64 = nullptr;
     int ops_nrt = 0, ops_k4 = 0;
     int64_t ops_bytes = 0;
+    // M2L by rotation (m2l_stored = 2, rotations.cpp): per direction (an
+    // integer offset reduced by its gcd) the folded forward and backward
+    // rotations of every degree <= p_max in matrix-core lane order (rot_per
+    // values per direction and kind), FP64 and FP32.  The chunks are taken in
+    // the order of their directions, so that the chunks sharing a direction's
+    // tables run together on one XCD; per position in that order: rot_hdr =
+    // {direction, eT | eS << 8, columns, 0} and rot_dist = |D| 2^-e (in units
+    // of the larger half-size), per column rot_cols = {source box x channels
+    // + channel, pair x channels + channel} ({-1, -1} past the chunk), and for
+    // Stokes per pair rot_gc = c_S - c_T
+    int n_dirs = 0;
+    int64_t rot_per = 0, rot_bytes = 0;
+    int4 *rot_hdr = nullptr;
+    int2 *rot_cols = nullptr;
+    double *rot_dist = nullptr, *rot_gc = nullptr;
+    double *rot64_f = nullptr, *rot64_b = nullptr;
+    float *rot32_f = nullptr, *rot32_b = nullptr;
 };
+// orders from which the rotation M2L replaces the direct one (m2l_stored = 2)
+constexpr int ROT_MIN_P = 8;
 
 // The regular near field stored as a block-sparse matrix (nearfield.hip): per
 // P2P unit (targets [tb, te) of one leaf), one dense block per source leaf of
@@ -520,6 +540,11 @@ void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev);
 void stage_end(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t ev, double flops = 0.0);
 // rules (rules.cpp): Gauss-Legendre by Golub-Welsch, near rule tables
 void gauss_legendre_gw(int n, double *x, double *w);
+// rotation tables of the M2L by rotation (rotations.cpp): values per
+// direction and kind at order p, and the tables of the given integer directions
+int64_t rot_tile_values(int p);
+void rotation_tables(const std::vector<std::array<int64_t, 3>> &dirs, int p, std::vector<double> &fwd,
+                     std::vector<double> &back);
 void near_rule_table(int n1d, double *bary, double *w);
 void set_last_error(const std::string &m);
 inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }

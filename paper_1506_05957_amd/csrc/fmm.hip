@@ -1134,6 +1134,311 @@ __global__ __launch_bounds__(256, 3) void k_m2l_stored(int p, int ncs, int nrt_s
     }
 }
 
+// M2L by rotation: the translation of Sec. 2.5 in three O(p^3) steps per box
+// pair instead of one O(p^4) product.  The multipole expansion is rotated so
+// that the translation vector lies along +z (per degree n, a real
+// 2 (n + 1) x 2 (n + 1) matrix of the direction, built on the host), translated
+// along z, where order l couples only with order -l through the axis values
+// I_j^0(d z) = j! / d^(j + 1), and the local expansion is rotated back.  The
+// rotations depend only on the direction of the key, so keys of one direction
+// share them.
+//
+// Block = chunk (pairs x channels of one key, at most 64 columns), taken in
+// groups of 16 NT columns held in LDS as one [2 nc + 2][16 NT + 1] array (the
+// two rows past the last degree are zero; the odd row stride keeps a wave's
+// 64 rows of one column, as staged, on distinct banks, and leaves every
+// matrix-core operand read an immediate offset from a per-lane base).  Each
+// stage works in place: a wave owns whole degrees (whole orders in the axial
+// stage), assigned longest first to the least loaded wave, so its writes
+// follow only its own reads; the at most two rows past a degree that a 4-deep
+// step reads meet zero operator entries.  Every operator value of a degree is
+// read before its products.  Column tiles past the chunk are skipped.
+// Scalings: the source's 2^(-eS n) when the rotated multipole is stored, the
+// target's (-1)^k 2^(-eT (k + 1)) and the order's signs when the translated
+// local expansion is stored.
+constexpr int ROT_KA = 6;  // 4-deep steps of an order in the axial stage
+
+__device__ __forceinline__ double scale2(double x, int e) { return ldexp(x, e); }
+__device__ __forceinline__ float scale2(float x, int e) { return ldexpf(x, e); }
+
+// degrees (or orders) of this wave: items n = hi .. 0, cost(n), assigned in
+// that order to the least loaded of the four waves (lowest index on ties)
+template <typename F> __device__ __forceinline__ uint32_t rot_owned(int hi, int w, F cost)
+{
+    int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    uint32_t mask = 0;
+    for (int n = hi; n >= 0; --n) {
+        const int c = cost(n);
+        int wm = 0, mv = c0;
+        if (c1 < mv) { wm = 1; mv = c1; }
+        if (c2 < mv) { wm = 2; mv = c2; }
+        if (c3 < mv) { wm = 3; mv = c3; }
+        c0 += wm == 0 ? c : 0;
+        c1 += wm == 1 ? c : 0;
+        c2 += wm == 2 ? c : 0;
+        c3 += wm == 3 ? c : 0;
+        if (wm == w)
+            mask |= 1u << n;
+    }
+    return mask;
+}
+
+__device__ __forceinline__ int rot_degree_cost(int n)
+{
+    const int S = 2 * (n + 1);
+    return ((S + 15) >> 4) * ((S + 3) >> 2);
+}
+
+// rotate degree n in place: X_n <- A_n X_n (A_n from the direction's table T,
+// lane order) on column tiles ct < nct, the result scaled by 2^es.  RTC row
+// tiles and at most KMC 4-deep steps (the degree's class): every operator
+// value of the degree is read first, with addresses clamped to its tiles and
+// no guard, so that each product waits only for its own value
+template <typename R, int NT, int RTC, int KMC>
+__device__ __forceinline__ void rot_degree(int n, const R *__restrict__ T, R *X, int lane, int nct, int es)
+{
+    typedef typename Acc4<R>::type acc_t;
+    constexpr int LD = 16 * NT + 1;
+    const int li = lane & 15, lk = lane >> 4;
+    int off = 0;
+    for (int j = 0; j < n; ++j)
+        off += rot_degree_cost(j);
+    const int S = 2 * (n + 1), k4 = (S + 3) >> 2, base = n * (n + 1);
+    R a[KMC][RTC];
+#pragma unroll
+    for (int kt = 0; kt < KMC; ++kt)
+#pragma unroll
+        for (int rt = 0; rt < RTC; ++rt)
+            a[kt][rt] = T[((int64_t)off + rt * k4 + min(kt, k4 - 1)) * 64 + lane];
+    acc_t acc[RTC][NT];
+#pragma unroll
+    for (int rt = 0; rt < RTC; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+            acc[rt][ct] = acc_t{0, 0, 0, 0};
+    const R *Xl = X + (base + lk) * LD + li;
+#pragma unroll
+    for (int kt = 0; kt < KMC; ++kt) {
+        if (kt < k4) {
+            R b[NT];
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct)
+                b[ct] = Xl[4 * kt * LD + 16 * ct];
+#pragma unroll
+            for (int rt = 0; rt < RTC; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+                    if (ct < nct)
+                        acc[rt][ct] = mfma_16x16x4(a[kt][rt], b[ct], acc[rt][ct]);
+        }
+    }
+    R *Xo = X + base * LD + li;
+#pragma unroll
+    for (int rt = 0; rt < RTC; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * rt + (sizeof(R) == 8 ? 4 * v + lk : 4 * lk + v);
+            if (row < S)
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+                    if (ct < nct)
+                        Xo[row * LD + 16 * ct] = scale2(acc[rt][ct][v], es);
+        }
+}
+
+// rotate the degrees of mask in place, the result of degree n scaled by 2^(e n)
+template <typename R, int NT>
+__device__ __forceinline__ void rot_degrees(uint32_t mask, const R *__restrict__ T, R *X, int lane, int nct, int e)
+{
+    for (uint32_t mk = mask; mk;) {
+        const int n = 31 - __builtin_clz(mk);
+        mk &= ~(1u << n);
+        if (n <= 7)
+            rot_degree<R, NT, 1, 4>(n, T, X, lane, nct, e * n);
+        else if (n <= 15)
+            rot_degree<R, NT, 2, 8>(n, T, X, lane, nct, e * n);
+        else
+            rot_degree<R, NT, 3, 11>(n, T, X, lane, nct, e * n);
+    }
+}
+
+// translate the orders l of mask along z in place: for k = l .. p,
+//   L'_k^l = (-1)^(k + l) 2^(-eT (k + 1)) sum_{n = l .. p} g_{n + k} conj(M'_n^l),
+// g_j = j! / d^(j + 1) (M' already scaled by 2^(-eS n))
+template <typename R, int NT>
+__device__ __forceinline__ void rot_axial(uint32_t mask, int p, const R *g, R *X, int lane, int nct, int eT)
+{
+    typedef typename Acc4<R>::type acc_t;
+    constexpr int LD = 16 * NT + 1;
+    const int li = lane & 15, lk = lane >> 4;
+    for (uint32_t mk = mask; mk;) {
+        const int l = 31 - __builtin_clz(mk);
+        mk &= ~(1u << l);
+        const int c = p + 1 - l, nrt = (c + 15) >> 4, k4 = (c + 3) >> 2;
+        acc_t acc[2][2][NT];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+                    acc[rt][ri][ct] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int kt = 0; kt < ROT_KA; ++kt) {
+            if (kt >= k4)
+                break;
+            const int nn = l + 4 * kt + lk;
+            const bool nv = nn <= p;
+            const int ncl = nv ? nn : p;
+            const R *Xr = X + (ncl * (ncl + 1) + 2 * l) * LD + li;
+            R b[2][NT];
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+                for (int ct = 0; ct < NT; ++ct)
+                    b[ri][ct] = Xr[ri * LD + 16 * ct];
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                if (rt < nrt) {
+                    const int ko = l + 16 * rt + li;
+                    const bool ok = nv && ko <= p;
+                    const R gv = g[ok ? ko + nn : 0];
+                    const R a = ok ? gv : R(0);
+#pragma unroll
+                    for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+                        for (int ct = 0; ct < NT; ++ct)
+                            if (ct < nct)
+                                acc[rt][ri][ct] = mfma_16x16x4(a, b[ri][ct], acc[rt][ri][ct]);
+                }
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            if (rt >= nrt)
+                break;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ko = l + 16 * rt + (sizeof(R) == 8 ? 4 * v + lk : 4 * lk + v);
+                if (ko <= p) {
+                    const R sc = scale2(((ko + l) & 1) ? R(-1) : R(1), -eT * (ko + 1));
+                    R *Xo = X + (ko * (ko + 1) + 2 * l) * LD + li;
+#pragma unroll
+                    for (int ct = 0; ct < NT; ++ct) {
+                        if (ct < nct) {
+                            Xo[16 * ct] = sc * acc[rt][0][ct][v];
+                            Xo[LD + 16 * ct] = -sc * acc[rt][1][ct][v];
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename R, int NCH, int NT>
+__global__ __launch_bounds__(256, 2) void k_m2l_rot(int p, int ncs, int n_chunks, int per_xcd,
+                                                 const int4 *__restrict__ hdr, const double *__restrict__ dist,
+                                                 const int2 *__restrict__ cols, const double *__restrict__ gcs,
+                                                 int64_t rot_per, const R *__restrict__ rotf,
+                                                 const R *__restrict__ rotb, const cplx<R> *__restrict__ M,
+                                                 cplx<R> *__restrict__ Y)
+{
+    constexpr int CW = 16 * NT, LD = CW + 1, CPW = CW / 4;
+    // Stokes: column w + 4 i of a group is channel w (groups start at a
+    // multiple of 4), so wave 3 writes out the fourth channel of every pair
+    // and moves its centre from c_S to c_T there, from the pair's first three
+    // channels: Y_3 + (c_S - c_T) . (Y_0, Y_1, Y_2)
+    constexpr bool FIXC = NCH == 4;
+    static_assert(!FIXC || CW % 4 == 0, "groups hold whole pairs");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    // consecutive positions of the order (one direction) on one XCD
+    const int s = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    if (s >= n_chunks)
+        return;
+    const int nc = ncoef(p), Dp = 2 * nc;
+    R *g = reinterpret_cast<R *>(smem_raw);  // [2 p + 2]
+    R *gc = g + 2 * p + 2;                   // [CW / 4][3] (Stokes)
+    R *X = gc + (FIXC ? 3 * CPW : 0);        // [Dp + 2][LD]
+    const int4 h = hdr[s];
+    const int dir = h.x, eT = h.y & 255, eS = h.y >> 8, ncol = h.z;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const uint32_t dmask = rot_owned(p, w, rot_degree_cost);
+    const uint32_t amask = rot_owned(p, w, [p](int l) {
+        const int cl = p + 1 - l;
+        return ((cl + 15) >> 4) * ((cl + 3) >> 2);
+    });
+    if (threadIdx.x == 0) {
+        const double d = dist[s], id = 1.0 / d;
+        double v = id;
+        for (int j = 0; j <= 2 * p; ++j) {
+            g[j] = (R)v;
+            v *= (j + 1) * id;
+        }
+    }
+    for (int t = threadIdx.x; t < 2 * LD; t += blockDim.x)
+        X[Dp * LD + t] = R(0);
+    const R *Tf = rotf + (int64_t)dir * rot_per, *Tb = rotb + (int64_t)dir * rot_per;
+    const R *Mr = reinterpret_cast<const R *>(M);
+    R *Yr = reinterpret_cast<R *>(Y);
+    const int2 *cs = cols + (int64_t)s * M2L_CHUNK;
+    for (int c0 = 0; c0 < ncol; c0 += CW) {
+        const int nct = min(NT, (ncol - c0 + 15) >> 4);
+        // wave w stages (and writes out) columns w, w + 4, ... of the group
+        int2 cc[CPW];
+#pragma unroll
+        for (int i = 0; i < CPW; ++i)
+            cc[i] = cs[c0 + w + 4 * i];
+        __syncthreads();  // the previous group written out
+        if (FIXC && w == 3 && lane < 3 * CPW && c0 + 4 * (lane / 3) < ncol)
+            gc[lane] = (R)gcs[((int64_t)s * (M2L_CHUNK / 4) + (c0 >> 2)) * 3 + lane];
+        for (int r0 = 0; r0 < Dp; r0 += 64) {
+            const int row = r0 + lane, rc = min(row, Dp - 1);
+            R v[CPW];
+#pragma unroll
+            for (int i = 0; i < CPW; ++i)
+                v[i] = Mr[2 * (int64_t)(cc[i].x < 0 ? 0 : cc[i].x) * ncs + rc];
+            if (row < Dp)
+#pragma unroll
+                for (int i = 0; i < CPW; ++i)
+                    X[row * LD + w + 4 * i] = cc[i].x >= 0 ? v[i] : R(0);
+        }
+        __syncthreads();
+        rot_degrees<R, NT>(dmask, Tf, X, lane, nct, -eS);
+        __syncthreads();
+        rot_axial<R, NT>(amask, p, g, X, lane, nct, eT);
+        __syncthreads();
+        rot_degrees<R, NT>(dmask, Tb, X, lane, nct, 0);
+        __syncthreads();
+        for (int r0 = 0; r0 < Dp; r0 += 64) {
+            const int row = r0 + lane;
+            if (row < Dp) {
+                const R *Xw = X + row * LD + w;
+                if (FIXC && w == 3) {
+#pragma unroll
+                    for (int i = 0; i < CPW; ++i)
+                        if (cc[i].y >= 0)
+                            Yr[2 * (int64_t)cc[i].y * nc + row] = Xw[4 * i] + gc[3 * i] * Xw[4 * i - 3] +
+                                                                  gc[3 * i + 1] * Xw[4 * i - 2] +
+                                                                  gc[3 * i + 2] * Xw[4 * i - 1];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < CPW; ++i)
+                        if (cc[i].y >= 0)
+                            Yr[2 * (int64_t)cc[i].y * nc + row] = Xw[4 * i];
+                }
+            }
+        }
+    }
+}
+
+// LDS of k_m2l_rot
+template <typename R, int NCH> size_t m2l_rot_shm(int p, int nt)
+{
+    return sizeof(R) * ((2 * (size_t)p + 2) + (NCH == 4 ? 12 * (size_t)nt : 0) +
+                        (2 * (size_t)ncoef(p) + 2) * (16 * (size_t)nt + 1));
+}
+
 template <typename R> size_t m2l_mfma_shm(int p)
 {
     const int q = 2 * p, Kp = (2 * ncoef(p) + 3) & ~3;
@@ -2037,6 +2342,33 @@ void corr_spmv(fmmbem_ctx *ctx, const CombineArgs &ca, hipStream_t st)
     FB_HIP(hipGetLastError());
 }
 
+// the widest column group within the LDS budget (FP64: 32 or 16 columns,
+// two blocks on a CU; FP32: 64 or 32 columns, three)
+template <typename R, int NCH>
+void launch_m2l_rot(fmmbem_ctx *ctx, int p, const cplx<R> *M, cplx<R> *Y, hipStream_t st)
+{
+    const M2LPlan &P = ctx->m2l;
+    const int ncs = ncoef(ctx->prm.p_max);
+    const int per = (P.n_chunks + 7) / 8;
+    constexpr int NTW = sizeof(R) == 8 ? 2 : 4;
+    constexpr size_t budget = sizeof(R) == 8 ? 80 * 1024 : 48 * 1024;
+    const R *rf, *rb;
+    if constexpr (sizeof(R) == 8) {
+        rf = P.rot64_f;
+        rb = P.rot64_b;
+    } else {
+        rf = P.rot32_f;
+        rb = P.rot32_b;
+    }
+    FB_REQUIRE(p <= 20, FMMBEM_EINVAL, "rotation M2L beyond its order limit");
+    if (m2l_rot_shm<R, NCH>(p, NTW) <= budget)
+        k_m2l_rot<R, NCH, NTW><<<8 * per, 256, m2l_rot_shm<R, NCH>(p, NTW), st>>>(
+            p, ncs, P.n_chunks, per, P.rot_hdr, P.rot_dist, P.rot_cols, P.rot_gc, P.rot_per, rf, rb, M, Y);
+    else
+        k_m2l_rot<R, NCH, NTW / 2><<<8 * per, 256, m2l_rot_shm<R, NCH>(p, NTW / 2), st>>>(
+            p, ncs, P.n_chunks, per, P.rot_hdr, P.rot_dist, P.rot_cols, P.rot_gc, P.rot_per, rf, rb, M, Y);
+}
+
 template <typename R, int KIND>
 void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bool have_up)
 {
@@ -2062,6 +2394,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         else
             l2l_op = P.l2l32;
         const size_t op_shm = sizeof(R) * 16 * std::max<size_t>(2 * (size_t)ncoef(p), 3 * 64);
+        const bool rot = P.rot64_f && p >= ROT_MIN_P;
         const int row_chunks = (2 * ncoef(p) + 63) / 64;
 
         stage_begin(ctx, SO + 1, st, &ev);
@@ -2072,7 +2405,9 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
             else
                 table = P.table32;
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
-            if constexpr (sizeof(R) == 4) {
+            if (rot) {
+                launch_m2l_rot<R, NCH>(ctx, p, M, Y, st);
+            } else if constexpr (sizeof(R) == 4) {
                 // one wave per 16-row tile up to four tiles (the low orders of the
                 // relaxed iterations: no wave idles, one tile's accumulators per
                 // wave), else four waves of up to four tiles each
@@ -2096,17 +2431,21 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
             }
             FB_HIP(hipGetLastError());
         }
-        // the method's count: the complex O(p^4) translation of Sec. 2.5,
-        // 4 (p + 1)^3 (p + 2) flops per box pair and channel (the kernels
-        // apply it as a real (2 nc) x (2 nc) operator, 8 nc^2 flops)
+        // flops per box pair and channel: the direct path counts the
+        // method's complex O(p^4) translation of Sec. 2.5, 4 (p + 1)^3 (p + 2)
+        // (its kernels apply it as a real (2 nc) x (2 nc) operator, 8 nc^2
+        // flops); the rotation path what it applies, two real rotations of
+        // 8 (n + 1)^2 flops per degree and the axial step of 4 (p + 1 - l)^2
+        // per order: 20 sum_{m <= p + 1} m^2
         const double q1 = p + 1.0;
-        stage_end(ctx, SO + 1, st, ev, 4.0 * q1 * q1 * q1 * (p + 2.0) * NCH * (double)T.n_m2l);
+        const double fl = rot ? 20.0 * q1 * (p + 2.0) * (2.0 * p + 3.0) / 6.0 : 4.0 * q1 * q1 * q1 * (p + 2.0);
+        stage_end(ctx, SO + 1, st, ev, fl * NCH * (double)T.n_m2l);
 
         // the downward pass: the per-target sum of the M2L terms, then L2L and L2P
         stage_begin(ctx, SO + 3, st, &ev);
         {
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
-            if constexpr (NCH == 4)
+            if (NCH == 4 && !rot)  // the rotation M2L moves the fourth channel's centre itself
                 k_m2l_reduce<R, NCH, true><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             else
                 k_m2l_reduce<R, NCH, false><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);

@@ -12,6 +12,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <numeric>
 #include <vector>
 
 #include "common.h"
@@ -110,6 +112,31 @@ __global__ void k_translation_tables(int nu, const uint64_t *__restrict__ ukey, 
             }
         }
     }
+}
+
+// per position s of the rotation order (chunk order[s]) and column: the
+// column's source box x channels + channel and pair x channels + channel
+// ({-1, -1} past the chunk); for Stokes per pair c_S - c_T
+__global__ void k_rot_columns(int nchk, int nch, const int32_t *__restrict__ order,
+                              const int32_t *__restrict__ chunk_begin, const int32_t *__restrict__ pair_sorted,
+                              const int32_t *__restrict__ pairs, const double *__restrict__ box_r,
+                              int2 *__restrict__ cols, double *__restrict__ gc)
+{
+    const int s = blockIdx.x, col = threadIdx.x;
+    if (s >= nchk || col >= M2L_CHUNK)
+        return;
+    const int c = order[s], pb = chunk_begin[c], np = chunk_begin[c + 1] - pb;
+    const int pl = col / nch, ch = col - pl * nch;
+    int2 v = int2{-1, -1};
+    if (pl < np) {
+        const int pr = pair_sorted[pb + pl];
+        v = int2{pairs[2 * pr + 1] * nch + ch, pr * nch + ch};
+        if (gc && ch == 0)
+            for (int d = 0; d < 3; ++d)
+                gc[((int64_t)s * (M2L_CHUNK / 4) + pl) * 3 + d] =
+                    box_r[5 * (int64_t)pairs[2 * pr + 1] + d] - box_r[5 * (int64_t)pairs[2 * pr] + d];
+    }
+    cols[(int64_t)s * M2L_CHUNK + col] = v;
 }
 
 // octant digit of every box (root: 0)
@@ -404,6 +431,72 @@ void build_translations(fmmbem_ctx *ctx, hipStream_t st)
         FB_HIP(hipMemcpyAsync(P.chunk_begin, cbeg.data(), sizeof(int32_t) * cbeg.size(), hipMemcpyHostToDevice, st));
         FB_HIP(hipMemcpyAsync(P.chunk_trans, cu.data(), sizeof(int32_t) * cu.size(), hipMemcpyHostToDevice, st));
         FB_HIP(hipMemcpyAsync(P.trans_key, ukeys.data(), sizeof(uint64_t) * ukeys.size(), hipMemcpyHostToDevice, st));
+        if (ctx->prm.m2l_stored == 2) {
+            // directions (integer offsets reduced by their gcd) and distances
+            std::map<std::array<int64_t, 3>, int> dir_id;
+            std::vector<std::array<int64_t, 3>> dirs;
+            std::vector<int32_t> tdir(ukeys.size());
+            std::vector<double> tdist(ukeys.size());
+            for (size_t u = 0; u < ukeys.size(); ++u) {
+                const uint64_t k = ukeys[u];
+                const int eT = (int)((k >> 48) & 63), eS = (int)((k >> 54) & 63), e = std::max(eT, eS);
+                std::array<int64_t, 3> D;
+                for (int d = 0; d < 3; ++d)
+                    D[d] = (int64_t)((k >> (16 * d)) & 0xffff) - KEY_BIAS;
+                const int64_t g = std::gcd(std::gcd(std::llabs(D[0]), std::llabs(D[1])), std::llabs(D[2]));
+                std::array<int64_t, 3> r = {D[0] / g, D[1] / g, D[2] / g};
+                auto it = dir_id.find(r);
+                if (it == dir_id.end()) {
+                    it = dir_id.emplace(r, (int)dirs.size()).first;
+                    dirs.push_back(r);
+                }
+                tdir[u] = it->second;
+                const double vx = std::ldexp((double)D[0], -e), vy = std::ldexp((double)D[1], -e),
+                             vz = std::ldexp((double)D[2], -e);
+                tdist[u] = std::sqrt(vx * vx + vy * vy + vz * vz);
+            }
+            std::vector<double> fwd, back;
+            rotation_tables(dirs, ctx->prm.p_max, fwd, back);
+            P.n_dirs = (int)dirs.size();
+            P.rot_per = rot_tile_values(ctx->prm.p_max);
+            std::vector<float> f32(fwd.begin(), fwd.end()), b32(back.begin(), back.end());
+            std::vector<int32_t> order(cu.size());
+            std::iota(order.begin(), order.end(), 0);
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int32_t a, int32_t b) { return tdir[cu[a]] < tdir[cu[b]]; });
+            const int nchk = (int)order.size();
+            std::vector<int4> hdr(nchk);
+            std::vector<double> hdist(nchk);
+            for (int s = 0; s < nchk; ++s) {
+                const int c = order[s], u = cu[c];
+                const uint64_t k = ukeys[u];
+                hdr[s] = int4{tdir[u], (int)((k >> 48) & 63) | (int)((k >> 54) & 63) << 8,
+                              (cbeg[c + 1] - cbeg[c]) * ctx->nch, 0};
+                hdist[s] = tdist[u];
+            }
+            P.rot_hdr = ctx->arena.alloc<int4>(nchk);
+            P.rot_dist = ctx->arena.alloc<double>(nchk);
+            P.rot_cols = ctx->arena.alloc<int2>((size_t)nchk * M2L_CHUNK);
+            if (ctx->nch == 4)
+                P.rot_gc = ctx->arena.alloc<double>((size_t)nchk * 3 * (M2L_CHUNK / 4));
+            int32_t *dorder = tmp.alloc<int32_t>(nchk);
+            FB_HIP(hipMemcpyAsync(P.rot_hdr, hdr.data(), sizeof(int4) * nchk, hipMemcpyHostToDevice, st));
+            FB_HIP(hipMemcpyAsync(P.rot_dist, hdist.data(), sizeof(double) * nchk, hipMemcpyHostToDevice, st));
+            FB_HIP(hipMemcpyAsync(dorder, order.data(), sizeof(int32_t) * nchk, hipMemcpyHostToDevice, st));
+            k_rot_columns<<<nchk, M2L_CHUNK, 0, st>>>(nchk, ctx->nch, dorder, P.chunk_begin, P.pair_sorted, T.m2l_pairs,
+                                                      T.box_r, P.rot_cols, P.rot_gc);
+            FB_HIP(hipGetLastError());
+            P.rot64_f = ctx->arena.alloc<double>(fwd.size());
+            P.rot64_b = ctx->arena.alloc<double>(back.size());
+            P.rot32_f = ctx->arena.alloc<float>(f32.size());
+            P.rot32_b = ctx->arena.alloc<float>(b32.size());
+            P.rot_bytes = (int64_t)(fwd.size() + back.size()) * (8 + 4);
+            FB_HIP(hipMemcpyAsync(P.rot64_f, fwd.data(), sizeof(double) * fwd.size(), hipMemcpyHostToDevice, st));
+            FB_HIP(hipMemcpyAsync(P.rot64_b, back.data(), sizeof(double) * back.size(), hipMemcpyHostToDevice, st));
+            FB_HIP(hipMemcpyAsync(P.rot32_f, f32.data(), sizeof(float) * f32.size(), hipMemcpyHostToDevice, st));
+            FB_HIP(hipMemcpyAsync(P.rot32_b, b32.data(), sizeof(float) * b32.size(), hipMemcpyHostToDevice, st));
+            FB_HIP(hipStreamSynchronize(st));  // the host vectors go out of scope
+        }
         const int64_t fq = (int64_t)(P.q + 1) * (P.q + 1);
         P.table64 = ctx->arena.alloc<cplx<double>>(fq * P.n_trans);
         P.table32 = ctx->arena.alloc<cplx<float>>(fq * P.n_trans);

@@ -72,7 +72,7 @@ def test_build_rejects_bad_params(fb):
     tri = np.array([[0, 1, 2]], dtype=np.int32)
     for prm in (fb.params(theta=0.0), fb.params(theta=1.5), fb.params(ncrit=0), fb.params(p_max=21),
                 fb.params(p_max=0), fb.params(mu=-1.0), fb.params(near_stored=2),
-                fb.params(m2l_stored=2)):
+                fb.params(m2l_stored=3)):
         rc, h = _build_rc(fb, xyz, tri, prm=prm)
         assert rc == fb.EINVAL
 

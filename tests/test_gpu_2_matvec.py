@@ -171,3 +171,53 @@ def test_stored_m2l_operators_match_generated(orc, kernel, name, p_max):
     assert rel_l2(yb, yr) <= 1e-6 and max_rel(yb, yr) <= 1e-5
     fb.fmmbem_destroy(a)
     fb.fmmbem_destroy(b)
+
+
+@pytest.mark.parametrize("kernel,name,p_max", [(0, "sphere8192", 16), (1, "cells8x512", 16), (2, "sphere2048", 12),
+                                               (1, "cells8x512", 20)])
+def test_rotation_m2l_matches_direct(orc, kernel, name, p_max):
+    """M2L by rotation (m2l_stored = 2; p >= 8) against the direct O(p^4)
+    translation generated on every call: the same product up to rounding in
+    FP64 at p_max and below it, within FP32 rounding in FP32 (the direct FP32
+    path stops at p = 14), unchanged below p = 8; against the oracle the
+    rotation path keeps <= 1e-6 at p_max (FP64) and 2e-6 at min(p_max, 14) (FP32)."""
+    from paper_1506_05957_amd import fmmbem as fb
+    announce(f"rotation vs direct M2L kernel={kernel} {name} p_max={p_max}")
+    m = MESHES[name]()
+    prm = dict(ncrit=64, p_max=p_max)
+    a = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(**prm))
+    b = fb.fmmbem_build(m.xyz, m.tri, kernel, fb.params(**prm, m2l_stored=2))
+    sb = fb.fmmbem_get_stats(b)
+    assert sb["n_translations"] == fb.fmmbem_get_stats(a)["n_translations"] > 0
+    assert sb["m2l_op_bytes"] > 0
+    n = m.n_panels * (3 if kernel == 1 else 1)
+    x = syn.random_vector(n, 37)
+    for p in sorted({p_max, 16, 12, 9, 8}, reverse=True):
+        if p > p_max:
+            continue
+        ya = matvec(fb, a, p, fb.FP64, x)
+        yb = matvec(fb, b, p, fb.FP64, x)
+        e = rel_l2(yb, ya)
+        announce(f"  FP64 p={p}: rel diff {e:.1e}")
+        assert e <= 1e-12
+    for p in (8, 12, 14):
+        if p > p_max:
+            continue
+        ya = matvec(fb, a, p, fb.FP64, x)
+        y32a = matvec(fb, a, p, fb.FP32, x)
+        y32b = matvec(fb, b, p, fb.FP32, x)
+        ea, eb = rel_l2(y32a, ya), rel_l2(y32b, ya)
+        announce(f"  FP32 p={p}: direct {ea:.1e} rotation {eb:.1e}")
+        assert eb <= max(2.0 * ea, 2e-6)
+    for p in (7, 4):
+        assert np.array_equal(matvec(fb, a, p, fb.FP64, x), matvec(fb, b, p, fb.FP64, x))
+        assert np.array_equal(matvec(fb, a, p, fb.FP32, x), matvec(fb, b, p, fb.FP32, x))
+    yr = orc.matvec(kernel, m.xyz, m.tri, x)
+    yb = matvec(fb, b, p_max, fb.FP64, x)
+    assert rel_l2(yb, yr) <= 1e-6 and max_rel(yb, yr) <= 1e-5
+    p32 = min(p_max, 14)  # FP32 expansions stop at p = 14
+    e32 = rel_l2(matvec(fb, b, p32, fb.FP32, x), yr)
+    announce(f"  FP32 p={p32} against the oracle: {e32:.1e}")
+    assert e32 <= 2e-6
+    fb.fmmbem_destroy(a)
+    fb.fmmbem_destroy(b)
