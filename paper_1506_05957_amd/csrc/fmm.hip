@@ -1162,21 +1162,26 @@ __device__ __forceinline__ double scale2(double x, int e) { return ldexp(x, e); 
 __device__ __forceinline__ float scale2(float x, int e) { return ldexpf(x, e); }
 
 // degrees (or orders) of this wave: items n = hi .. 0, cost(n), assigned in
-// that order to the least loaded of the four waves (lowest index on ties)
-template <typename F> __device__ __forceinline__ uint32_t rot_owned(int hi, int w, F cost)
+// that order to the least loaded of the NW waves (lowest index on ties)
+template <int NW, typename F> __device__ __forceinline__ uint32_t rot_owned(int hi, int w, F cost)
 {
-    int c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    int ld[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j)
+        ld[j] = 0;
     uint32_t mask = 0;
     for (int n = hi; n >= 0; --n) {
         const int c = cost(n);
-        int wm = 0, mv = c0;
-        if (c1 < mv) { wm = 1; mv = c1; }
-        if (c2 < mv) { wm = 2; mv = c2; }
-        if (c3 < mv) { wm = 3; mv = c3; }
-        c0 += wm == 0 ? c : 0;
-        c1 += wm == 1 ? c : 0;
-        c2 += wm == 2 ? c : 0;
-        c3 += wm == 3 ? c : 0;
+        int wm = 0, mv = ld[0];
+#pragma unroll
+        for (int j = 1; j < NW; ++j)
+            if (ld[j] < mv) {
+                wm = j;
+                mv = ld[j];
+            }
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+            ld[j] += wm == j ? c : 0;
         if (wm == w)
             mask |= 1u << n;
     }
@@ -1336,21 +1341,21 @@ __device__ __forceinline__ void rot_axial(uint32_t mask, int p, const R *g, R *X
     }
 }
 
-template <typename R, int NCH, int NT>
-__global__ __launch_bounds__(256, 2) void k_m2l_rot(int p, int ncs, int n_chunks, int per_xcd,
+template <typename R, int NCH, int NT, int NW>
+__global__ __launch_bounds__(64 * NW, NW / 2) void k_m2l_rot(int p, int ncs, int n_chunks, int per_xcd,
                                                  const int4 *__restrict__ hdr, const double *__restrict__ dist,
                                                  const int2 *__restrict__ cols, const double *__restrict__ gcs,
                                                  int64_t rot_per, const R *__restrict__ rotf,
                                                  const R *__restrict__ rotb, const cplx<R> *__restrict__ M,
                                                  cplx<R> *__restrict__ Y)
 {
-    constexpr int CW = 16 * NT, LD = CW + 1, CPW = CW / 4;
-    // Stokes: column w + 4 i of a group is channel w (groups start at a
-    // multiple of 4), so wave 3 writes out the fourth channel of every pair
-    // and moves its centre from c_S to c_T there, from the pair's first three
-    // channels: Y_3 + (c_S - c_T) . (Y_0, Y_1, Y_2)
+    constexpr int CW = 16 * NT, LD = CW + 1, CPW = CW / NW;
+    // Stokes: column w + NW i of a group is channel w mod 4 (groups start at a
+    // multiple of 4), so the waves w = 3 mod 4 write out the fourth channel of
+    // every pair and move its centre from c_S to c_T there, from the pair's
+    // first three channels: Y_3 + (c_S - c_T) . (Y_0, Y_1, Y_2)
     constexpr bool FIXC = NCH == 4;
-    static_assert(!FIXC || CW % 4 == 0, "groups hold whole pairs");
+    static_assert(NW % 4 == 0 && CW % NW == 0, "groups hold whole pairs, whole columns per wave");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // consecutive positions of the order (one direction) on one XCD
     const int s = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
@@ -1359,12 +1364,12 @@ __global__ __launch_bounds__(256, 2) void k_m2l_rot(int p, int ncs, int n_chunks
     const int nc = ncoef(p), Dp = 2 * nc;
     R *g = reinterpret_cast<R *>(smem_raw);  // [2 p + 2]
     R *gc = g + 2 * p + 2;                   // [CW / 4][3] (Stokes)
-    R *X = gc + (FIXC ? 3 * CPW : 0);        // [Dp + 2][LD]
+    R *X = gc + (FIXC ? 3 * (CW / 4) : 0);   // [Dp + 2][LD]
     const int4 h = hdr[s];
     const int dir = h.x, eT = h.y & 255, eS = h.y >> 8, ncol = h.z;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const uint32_t dmask = rot_owned(p, w, rot_degree_cost);
-    const uint32_t amask = rot_owned(p, w, [p](int l) {
+    const uint32_t dmask = rot_owned<NW>(p, w, rot_degree_cost);
+    const uint32_t amask = rot_owned<NW>(p, w, [p](int l) {
         const int cl = p + 1 - l;
         return ((cl + 15) >> 4) * ((cl + 3) >> 2);
     });
@@ -1384,13 +1389,13 @@ __global__ __launch_bounds__(256, 2) void k_m2l_rot(int p, int ncs, int n_chunks
     const int2 *cs = cols + (int64_t)s * M2L_CHUNK;
     for (int c0 = 0; c0 < ncol; c0 += CW) {
         const int nct = min(NT, (ncol - c0 + 15) >> 4);
-        // wave w stages (and writes out) columns w, w + 4, ... of the group
+        // wave w stages (and writes out) columns w, w + NW, ... of the group
         int2 cc[CPW];
 #pragma unroll
         for (int i = 0; i < CPW; ++i)
-            cc[i] = cs[c0 + w + 4 * i];
+            cc[i] = cs[c0 + w + NW * i];
         __syncthreads();  // the previous group written out
-        if (FIXC && w == 3 && lane < 3 * CPW && c0 + 4 * (lane / 3) < ncol)
+        if (FIXC && w == NW - 1 && lane < 3 * (CW / 4) && c0 + 4 * (lane / 3) < ncol)
             gc[lane] = (R)gcs[((int64_t)s * (M2L_CHUNK / 4) + (c0 >> 2)) * 3 + lane];
         for (int r0 = 0; r0 < Dp; r0 += 64) {
             const int row = r0 + lane, rc = min(row, Dp - 1);
@@ -1401,7 +1406,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_rot(int p, int ncs, int n_chunks
             if (row < Dp)
 #pragma unroll
                 for (int i = 0; i < CPW; ++i)
-                    X[row * LD + w + 4 * i] = cc[i].x >= 0 ? v[i] : R(0);
+                    X[row * LD + w + NW * i] = cc[i].x >= 0 ? v[i] : R(0);
         }
         __syncthreads();
         rot_degrees<R, NT>(dmask, Tf, X, lane, nct, -eS);
@@ -1414,18 +1419,19 @@ __global__ __launch_bounds__(256, 2) void k_m2l_rot(int p, int ncs, int n_chunks
             const int row = r0 + lane;
             if (row < Dp) {
                 const R *Xw = X + row * LD + w;
-                if (FIXC && w == 3) {
+                if (FIXC && (w & 3) == 3) {
 #pragma unroll
-                    for (int i = 0; i < CPW; ++i)
+                    for (int i = 0; i < CPW; ++i) {
+                        const R *gq = gc + 3 * ((w + NW * i) >> 2);
                         if (cc[i].y >= 0)
-                            Yr[2 * (int64_t)cc[i].y * nc + row] = Xw[4 * i] + gc[3 * i] * Xw[4 * i - 3] +
-                                                                  gc[3 * i + 1] * Xw[4 * i - 2] +
-                                                                  gc[3 * i + 2] * Xw[4 * i - 1];
+                            Yr[2 * (int64_t)cc[i].y * nc + row] = Xw[NW * i] + gq[0] * Xw[NW * i - 3] +
+                                                                  gq[1] * Xw[NW * i - 2] + gq[2] * Xw[NW * i - 1];
+                    }
                 } else {
 #pragma unroll
                     for (int i = 0; i < CPW; ++i)
                         if (cc[i].y >= 0)
-                            Yr[2 * (int64_t)cc[i].y * nc + row] = Xw[4 * i];
+                            Yr[2 * (int64_t)cc[i].y * nc + row] = Xw[NW * i];
                 }
             }
         }
@@ -2342,15 +2348,16 @@ void corr_spmv(fmmbem_ctx *ctx, const CombineArgs &ca, hipStream_t st)
     FB_HIP(hipGetLastError());
 }
 
-// the widest column group within the LDS budget (FP64: 32 or 16 columns,
-// two blocks on a CU; FP32: 64 or 32 columns, three)
+// the widest column group within the LDS budget (FP64: 32 or 16 columns, two
+// blocks on a CU; FP32: 64 or 32 columns, at least three); four waves: blocks
+// of eight waves (fewer, larger blocks per CU) measured slower in FP32
 template <typename R, int NCH>
 void launch_m2l_rot(fmmbem_ctx *ctx, int p, const cplx<R> *M, cplx<R> *Y, hipStream_t st)
 {
     const M2LPlan &P = ctx->m2l;
     const int ncs = ncoef(ctx->prm.p_max);
     const int per = (P.n_chunks + 7) / 8;
-    constexpr int NTW = sizeof(R) == 8 ? 2 : 4;
+    constexpr int NTW = sizeof(R) == 8 ? 2 : 4, NW = 4;
     constexpr size_t budget = sizeof(R) == 8 ? 80 * 1024 : 48 * 1024;
     const R *rf, *rb;
     if constexpr (sizeof(R) == 8) {
@@ -2362,10 +2369,10 @@ void launch_m2l_rot(fmmbem_ctx *ctx, int p, const cplx<R> *M, cplx<R> *Y, hipStr
     }
     FB_REQUIRE(p <= 20, FMMBEM_EINVAL, "rotation M2L beyond its order limit");
     if (m2l_rot_shm<R, NCH>(p, NTW) <= budget)
-        k_m2l_rot<R, NCH, NTW><<<8 * per, 256, m2l_rot_shm<R, NCH>(p, NTW), st>>>(
+        k_m2l_rot<R, NCH, NTW, NW><<<8 * per, 64 * NW, m2l_rot_shm<R, NCH>(p, NTW), st>>>(
             p, ncs, P.n_chunks, per, P.rot_hdr, P.rot_dist, P.rot_cols, P.rot_gc, P.rot_per, rf, rb, M, Y);
     else
-        k_m2l_rot<R, NCH, NTW / 2><<<8 * per, 256, m2l_rot_shm<R, NCH>(p, NTW / 2), st>>>(
+        k_m2l_rot<R, NCH, NTW / 2, NW><<<8 * per, 64 * NW, m2l_rot_shm<R, NCH>(p, NTW / 2), st>>>(
             p, ncs, P.n_chunks, per, P.rot_hdr, P.rot_dist, P.rot_cols, P.rot_gc, P.rot_per, rf, rb, M, Y);
 }
 
