@@ -1397,16 +1397,26 @@ __global__ __launch_bounds__(64 * NW, NW / 2) void k_m2l_rot(int p, int ncs, int
         __syncthreads();  // the previous group written out
         if (FIXC && w == NW - 1 && lane < 3 * (CW / 4) && c0 + 4 * (lane / 3) < ncol)
             gc[lane] = (R)gcs[((int64_t)s * (M2L_CHUNK / 4) + (c0 >> 2)) * 3 + lane];
-        for (int r0 = 0; r0 < Dp; r0 += 64) {
-            const int row = r0 + lane, rc = min(row, Dp - 1);
-            R v[CPW];
+        // RB 64-row blocks of every column of the wave in flight together (at
+        // most 32 reads: a wave holds at most 63 outstanding)
+        constexpr int RB = CPW >= 32 ? 1 : 32 / CPW;
+        for (int r0 = 0; r0 < Dp; r0 += 64 * RB) {
+            R v[RB][CPW];
 #pragma unroll
-            for (int i = 0; i < CPW; ++i)
-                v[i] = Mr[2 * (int64_t)(cc[i].x < 0 ? 0 : cc[i].x) * ncs + rc];
-            if (row < Dp)
+            for (int h = 0; h < RB; ++h) {
+                const int rc = min(r0 + 64 * h + lane, Dp - 1);
 #pragma unroll
                 for (int i = 0; i < CPW; ++i)
-                    X[row * LD + w + NW * i] = cc[i].x >= 0 ? v[i] : R(0);
+                    v[h][i] = Mr[2 * (int64_t)(cc[i].x < 0 ? 0 : cc[i].x) * ncs + rc];
+            }
+#pragma unroll
+            for (int h = 0; h < RB; ++h) {
+                const int row = r0 + 64 * h + lane;
+                if (row < Dp)
+#pragma unroll
+                    for (int i = 0; i < CPW; ++i)
+                        X[row * LD + w + NW * i] = cc[i].x >= 0 ? v[h][i] : R(0);
+            }
         }
         __syncthreads();
         rot_degrees<R, NT>(dmask, Tf, X, lane, nct, -eS);
