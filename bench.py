@@ -353,13 +353,13 @@ def cpu_baseline(args, fb, syn, head, sphere_mesh, sphere_x):
 def laplace_sphere_32768(args, fb, syn, torch, dev):
     """Laplace single layer, 32768-panel sphere, Y_l^m data (l = 0..4):
     relaxed mixed (12 -> 3), relaxed FP64 and fixed p = 12 FP64 solves with
-    the stored near field and stored FP64 M2L operators; per-order mat-vec
-    times; the roofline of the stored-operator M2L and near-field product."""
+    the stored near field and the rotation M2L (from p = 8); per-order mat-vec
+    times; the rooflines of the FP64 M2L and of the near-field product."""
     m = syn.sphere(6)
     nt = m.n_panels
     orders = syn.ylm_orders(0)
     rhs = [torch.tensor(syn.ylm_rhs(m, l, mm), device=dev) for l, mm in orders]
-    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE, fb.params(ncrit=64, p_max=12, near_stored=1, m2l_stored=1))
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE, fb.params(ncrit=64, p_max=12, near_stored=1, m2l_stored=2))
     stats = fb.fmmbem_get_stats(ctx)
     x = torch.empty(nt, dtype=torch.float64, device=dev)
     scheds = {"relaxed_mixed": fb.schedule(fb.LAPLACE, rule=fb.RELAX_BF, p_init=12, p_min=3, mixed=1),
@@ -369,7 +369,7 @@ def laplace_sphere_32768(args, fb, syn, torch, dev):
         for b in rhs:
             fb.fmmbem_solve_ctx(ctx, b, TOL, s, x)
     out = {"workload": "laplace_sl_sphere32768_ylm_tol1e-6", "panels": nt, "ncrit": 64,
-           "near_field": "stored", "m2l_fp64": "stored", "rhs": [f"Y_{l}^{mm}" for l, mm in orders]}
+           "near_field": "stored", "m2l": "rot", "rhs": [f"Y_{l}^{mm}" for l, mm in orders]}
     fb.fmmbem_set_timing_stages(ctx, ["p2p_fp32", "m2l_fp64"])
     fb.fmmbem_get_timing(ctx, reset=True)
     for name, s in scheds.items():
@@ -384,19 +384,14 @@ def laplace_sphere_32768(args, fb, syn, torch, dev):
             out[name]["p_history_last"] = [int(v) for v in reps[-1]["p_hist"]]
     fb.fmmbem_set_timing(ctx, False)
     out["speedup_relaxed_vs_fixed"] = out["fixed_p12_fp64"]["solve_ms"]["p50"] / out["relaxed_mixed"]["solve_ms"]["p50"]
-    # HBM rooflines of the two dominant kernels, event-timed inside the relaxed solves
+    # rooflines of the two dominant kernels, event-timed inside the relaxed
+    # solves: the FP64 rotation M2L (p = 12) against the matrix-core peak with
+    # the flops it applies, the near-field product against HBM
     rl = {}
-    t_ms, n, _ = stage["m2l_fp64"]
-    if n:
-        nc = 91
-        nbytes = stats["m2l_op_bytes"] + stats["n_boxes"] * 2 * nc * 8 + stats["n_m2l"] * 2 * nc * 8
-        avg = t_ms / 1e3 / n
-        rl["m2l_fp64"] = {"bound": "hbm", "kernel": "k_m2l_stored<1>", "achieved": nbytes / avg / 1e9,
-                          "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": nbytes / avg / PEAK_HBM,
-                          "traffic": kernel_traffic("k_m2l_stored<1>", "laplace_sphere32768"),
-                          "avg_launch_us": avg * 1e6, "launches": n, "bytes_per_launch": nbytes,
-                          "fp64_tflops_method_count": stage["m2l_fp64"][2] / n / avg / 1e12,
-                          "frac_of_fp64_method_count": stage["m2l_fp64"][2] / n / avg / PEAK_FP64_VALU}
+    r = alu_roofline(stage["m2l_fp64"], "m2l_fp64", "k_m2l_rot<double, 1, 2, 4>", "laplace_sphere32768",
+                     PEAK_FP64_VALU, "mfma")
+    if r:
+        rl["m2l_fp64"] = r
     t_ms, n, _ = stage["p2p_fp32"]
     if n:
         nbytes = stats["near_entries"] * 4 + 3 * 8 * nt
@@ -495,7 +490,7 @@ def laplace_second_kind(args, fb, syn, torch, dev):
     fb.fmmbem_matvec(sl, 12, fb.FP64, g, b)
     torch.cuda.synchronize()
     fb.fmmbem_destroy(sl)
-    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE_DL, fb.params(ncrit=64, p_max=12, near_stored=1, m2l_stored=1))
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE_DL, fb.params(ncrit=64, p_max=12, near_stored=1, m2l_stored=2))
     x = torch.empty_like(b)
     out = {"workload": f"laplace_dl_2nd_kind_sphere{m.n_panels}_exterior_neumann_Y21_tol1e-6",
            "panels": m.n_panels}
@@ -590,8 +585,8 @@ def serving(args, fb, syn):
 # ------------------------------------------------------------------ N_CRIT sweep
 def ncrit_sweep(args, fb, syn, torch, dev):
     """Solve time against N_CRIT for both schedules on the Laplace 32768-panel
-    sphere (on-the-fly near field) and the 64-cell Stokes case (stored FP64
-    M2L operators, as the headline)."""
+    sphere (on-the-fly near field) and the 64-cell Stokes case (with the
+    headline's M2L, --m2l)."""
     out = {"laplace_sphere32768": {}, "stokes_64rbc": {}}
     m = syn.sphere(6)
     b = torch.tensor(syn.ylm_rhs(m, 3, 0), device=dev)
@@ -611,7 +606,7 @@ def ncrit_sweep(args, fb, syn, torch, dev):
     u = torch.tensor(np.tile([1.0, 0.0, 0.0], m.n_panels), device=dev)
     x = torch.empty_like(u)
     for nc in (48, 64, 96, 128, 192, 256, 384):
-        ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=nc, p_max=16, m2l_stored=1))
+        ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=nc, p_max=16, m2l_stored=M2L_MODES[args.m2l]))
         row = {}
         for name, s in (("relaxed_mixed", fb.schedule(fb.STOKES, p_init=16, p_min=4)),
                         ("fixed_p16_fp64", fb.schedule(fb.STOKES, rule=fb.FIXED, p_init=16, p_min=16, mixed=0))):

@@ -41,16 +41,18 @@ def matvec(fb, ctx, p, prec, x):
     return yd.cpu().numpy()
 
 
-@pytest.mark.parametrize("stored", [0, 1])
-def test_laplace_sphere_32768(orc, stored):
+@pytest.mark.parametrize("near_stored,m2l_stored", [(0, 0), (1, 1), (1, 2)])
+def test_laplace_sphere_32768(orc, near_stored, m2l_stored):
     """The 32768-panel sphere, five Y_l^m right-hand sides, relaxed mixed
-    solves at tol 1e-6; stored = 1 is the benchmark's configuration (near field
-    and FP64 M2L operators stored at build)."""
+    solves at tol 1e-6; (1, 2) is the benchmark's configuration (near field
+    stored at build, M2L by rotation from p = 8); (1, 1) stores the direct FP64
+    M2L operators instead."""
     from paper_1506_05957_amd import fmmbem as fb
-    announce(f"full size: Laplace sphere 32768, Y_l^m, relaxed 12 -> 3 mixed, stored={stored}")
+    announce(f"full size: Laplace sphere 32768, Y_l^m, relaxed 12 -> 3 mixed, near_stored={near_stored} "
+             f"m2l_stored={m2l_stored}")
     m = syn.sphere(6)
     ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE,
-                          fb.params(ncrit=64, p_max=12, near_stored=stored, m2l_stored=stored))
+                          fb.params(ncrit=64, p_max=12, near_stored=near_stored, m2l_stored=m2l_stored))
     rows = sampled_rows(m.n_panels, 256, 0)
     x = syn.random_vector(m.n_panels, 3)
     yr = orc.matvec(orc.LAPLACE, m.xyz, m.tri, x, rows=rows)
@@ -102,20 +104,22 @@ def test_stokes_sphere_8192_drag(orc):
     fb.fmmbem_destroy(ctx)
 
 
-@pytest.mark.parametrize("ncrit", [128, 256])
-def test_stokes_64_cells(orc, ncrit):
+@pytest.mark.parametrize("ncrit,m2l_stored", [(128, 2), (256, 2), (128, 0)])
+def test_stokes_64_cells(orc, ncrit, m2l_stored):
     """64 red blood cells x 2048 panels (131072 panels, 393216 unknowns), the
     relaxed mixed schedule (16 -> 4, the benchmark's headline) and fixed
-    p = 16 in FP64, at each N_CRIT the benchmark uses: both converge to a true
+    p = 16 in FP64, at each N_CRIT the benchmark uses with its M2L by rotation
+    (m2l_stored = 2), and with the direct M2L: both converge to a true
     residual <= 1e-6, the oracle's residual b - A x on 4096 sampled rows is
     <= 5e-6 of b there, and the force on every cell agrees between the two
     schedules (the normal field that the single layer nearly annihilates
     carries no force)."""
     from paper_1506_05957_amd import fmmbem as fb
-    announce(f"full size: 64 red blood cells x 2048 panels, N_CRIT {ncrit}, relaxed and fixed")
+    announce(f"full size: 64 red blood cells x 2048 panels, N_CRIT {ncrit}, m2l_stored {m2l_stored}, "
+             f"relaxed and fixed")
     m = syn.rbc_scene(64, 4, 0)
     assert m.n_panels == 131072
-    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=ncrit, p_max=16))
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=ncrit, p_max=16, m2l_stored=m2l_stored))
     st = fb.fmmbem_get_stats(ctx)
     announce(f"  stats: {st}")
     u = np.tile([1.0, 0.0, 0.0], m.n_panels)
