@@ -345,6 +345,9 @@ struct M2LPlan {
 };
 // orders from which the rotation M2L replaces the direct one (m2l_stored = 2)
 constexpr int ROT_MIN_P = 8;
+// orders up to which L2P (where the downward pass is not fused) evaluates the
+// far field without waiting for the near field, and a combine joins the two
+constexpr int L2P_FAR_MAX_P = 7;
 
 // The regular near field stored as a block-sparse matrix (nearfield.hip): per
 // P2P unit (targets [tb, te) of one leaf), one dense block per source leaf of

@@ -1795,12 +1795,16 @@ __device__ __forceinline__ void target_rel(int64_t i, int64_t nt, double s, cons
 
 // L2P: one block per leaf, one thread per target, which also combines the
 // target's far field with its near field (joined before the launch).
-template <typename R, int KIND>
+// With FAR (the low orders, where the near field takes longer than the far
+// chain) the far field of every target goes to yfar in sorted order and a
+// separate combine joins it with the near field, so that L2P itself does not
+// wait for the near field; otherwise L2P combines.
+template <typename R, int KIND, bool FAR>
 __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__restrict__ leaves,
                                             const int32_t *__restrict__ box_i, const double *__restrict__ box_r,
                                             double side, int64_t nt, const double *__restrict__ tc,
                                             const float *__restrict__ tc32, const cplx<R> *__restrict__ L,
-                                            CombineArgs ca)
+                                            CombineArgs ca, double *__restrict__ yfar)
 {
     constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     constexpr int NCH = STOKES ? 4 : 1;
@@ -1864,7 +1868,10 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
         });
         if constexpr (!STOKES) {
             const double yf = (double)pot[0] / s;
-            combine_target<KIND>(ca, i, &yf);
+            if constexpr (FAR)
+                yfar[i] = yf;
+            else
+                combine_target<KIND>(ca, i, &yf);
         } else {
             const double is = 1.0 / s, is2 = is * is;
             const double xr[3] = {(double)x * s, (double)y * s, (double)z * s};  // x - c
@@ -1876,7 +1883,12 @@ __global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__res
                 u += (double)grd[9 + dir] * is2;
                 yf[dir] = u;
             }
-            combine_target<KIND>(ca, i, yf);
+            if constexpr (FAR) {
+                for (int dir = 0; dir < 3; ++dir)
+                    yfar[3 * i + dir] = yf[dir];
+            } else {
+                combine_target<KIND>(ca, i, yf);
+            }
         }
     }
 }
@@ -2495,10 +2507,20 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 FB_HIP(hipGetLastError());
             }
             corr_spmv<KIND>(ctx, ca, st);  // while the near field may still run
-            FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // L2P combines with the near field
             constexpr int NQS = KIND == FMMBEM_STOKES_SL ? 3 + 12 : 1;
-            k_l2p<R, KIND><<<T.nleaf, 64, sizeof(cplx<R>) * NQS * ncoef(p), st>>>(
-                p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc, G.tc32, L, ca);
+            const size_t lshm = sizeof(cplx<R>) * NQS * ncoef(p);
+            if (p <= L2P_FAR_MAX_P) {
+                // the far field while the near field may still run, then the combine
+                k_l2p<R, KIND, true><<<T.nleaf, 64, lshm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc,
+                                                                G.tc32, L, ca, ctx->y_far);
+                FB_HIP(hipGetLastError());
+                FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
+                k_combine<KIND><<<grid_for(nt, 64), 64, 0, st>>>(nt, ca, ctx->y_far);
+            } else {
+                FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // L2P combines with the near field
+                k_l2p<R, KIND, false><<<T.nleaf, 64, lshm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc,
+                                                                 G.tc32, L, ca, nullptr);
+            }
             FB_HIP(hipGetLastError());
         }
         stage_end(ctx, SO + 3, st, ev);
