@@ -367,7 +367,10 @@ __global__ __launch_bounds__(256) void k_p2m_tile(int p, int ncs, const int32_t 
     const double s = ldexp(side, -(lv + 1));
     const double *c = box_r + 5 * (int64_t)b;
     const R is = (R)(1.0 / s);
-    const int m = threadIdx.x % nm, sl = threadIdx.x / nm;
+    // s fastest: a wave holds a few neighbouring orders m, whose diagonal and
+    // column recurrences run about as many steps as each other (with m
+    // fastest every wave would run the longest diagonal and the longest column)
+    const int sl = threadIdx.x % ts, m = threadIdx.x / ts;
     R ar[ITEMS], ai[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
@@ -376,7 +379,7 @@ __global__ __launch_bounds__(256) void k_p2m_tile(int p, int ncs, const int32_t 
     for (int64_t t0 = s0; t0 < s1; t0 += ts) {
         const int cnt = (int)std::min<int64_t>(ts, s1 - t0);
         __syncthreads();  // the previous tile has been read
-        if (sl < cnt) {
+        if (sl < cnt && m < nm) {
             const S sv = src[t0 + sl];
             R x, y, z;  // relative to the leaf centre
             if constexpr (sizeof(R) == 8) {
@@ -1560,8 +1563,9 @@ __global__ __launch_bounds__(256) void k_m2l_valu(int p, int ncs, int q_tab, con
     }
 }
 
-// Pass 2: L(T) = sum of Y over T's pairs (CSR order), all boxes; thread =
-// (pair slice, output), slices summed in a fixed order.  With FIXC (Stokes
+// Pass 2: L(T) = sum of Y over T's pairs (CSR order), all boxes; block =
+// (box, chunk of 256 outputs), thread = (pair slice, output), slices summed
+// in a fixed order.  With FIXC (Stokes
 // after k_m2l_mfma) the fourth channel of each pair also changes centre from
 // c_S to c_T: Y_3 + (c_S - c_T) . (Y_0, Y_1, Y_2).
 template <typename R, int NCH, bool FIXC>
@@ -1574,7 +1578,8 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_
     const int nc = ncoef(p), no = NCH * nc;
     const int e0 = ptr[T], e1 = ptr[T + 1];
     const double *cT = box_r + 5 * (int64_t)T;
-    for (int o0 = 0; o0 < no; o0 += blockDim.x) {
+    {
+        const int o0 = blockIdx.y * (int)blockDim.x;  // this block's outputs: o0 .. o0 + span - 1
         const int span = min((int)blockDim.x, no - o0);
         const int sl = threadIdx.x / span, t = o0 + threadIdx.x % span;
         const int nsl_here = max(1, (int)blockDim.x / span);
@@ -1793,103 +1798,179 @@ __device__ __forceinline__ void target_rel(int64_t i, int64_t nt, double s, cons
     }
 }
 
-// L2P: one block per leaf, one thread per target, which also combines the
-// target's far field with its near field (joined before the launch).
-// With FAR (the low orders, where the near field takes longer than the far
-// chain) the far field of every target goes to yfar in sorted order and a
-// separate combine joins it with the near field, so that L2P itself does not
-// wait for the near field; otherwise L2P combines.
+// L2P: one block per leaf; lane t of every wave takes targets t, t + 64, ...
+// and the four waves split the columns m of the regular harmonics (wave w
+// takes m = 4 b + w for even b and 4 b + 3 - w for odd b, near equal shares
+// of the (n, m) pairs), each running the diagonal recurrence to its own
+// columns.  The waves' partial sums are added in wave order through LDS and
+// wave 0 combines the target's far field with its near field (joined before
+// the launch).  With FAR (the low orders, where the near field takes longer
+// than the far chain) the far field of every target goes to yfar in sorted
+// order and a separate combine joins it with the near field, so that L2P
+// itself does not wait for the near field; otherwise L2P combines.
+// Stokes needs the gradients of the four local expansions as well: the
+// gradient of sum L_n^m R_n^m is the expansion of order p - 1 with
+//   d/dz: L_{j+1}^k,  d/dx: (L_{j+1}^{k-1} - L_{j+1}^{k+1}) / 2,
+//   d/dy: (i/2) (L_{j+1}^{k-1} + L_{j+1}^{k+1}),
+// formed at each (j, k) from the three neighbours of degree j + 1
+// (L_{j+1}^{-1} = -conj(L_{j+1}^1)).  The leaf's expansions sit in LDS
+// channel-fastest, so that one coefficient's reads share one base address.
+// Dynamic LDS: l2p_shm.
+constexpr int L2P_WAVES = 4;
+
+template <typename R, int KIND> constexpr int l2p_nacc()
+{
+    return KIND == FMMBEM_STOKES_SL ? 3 + 12 : 1;
+}
+
+template <typename R, int KIND> size_t l2p_shm(int p)
+{
+    constexpr int NCH = KIND == FMMBEM_STOKES_SL ? 4 : 1;
+    return sizeof(cplx<R>) * NCH * (size_t)ncoef(p) + sizeof(R) * (L2P_WAVES - 1) * l2p_nacc<R, KIND>() * 64;
+}
+
 template <typename R, int KIND, bool FAR>
-__global__ __launch_bounds__(64) void k_l2p(int p, int ncs, const int32_t *__restrict__ leaves,
-                                            const int32_t *__restrict__ box_i, const double *__restrict__ box_r,
-                                            double side, int64_t nt, const double *__restrict__ tc,
-                                            const float *__restrict__ tc32, const cplx<R> *__restrict__ L,
-                                            CombineArgs ca, double *__restrict__ yfar)
+__global__ __launch_bounds__(64 * L2P_WAVES, 3) void k_l2p(int p, int ncs, const int32_t *__restrict__ leaves,
+                                                        const int32_t *__restrict__ box_i,
+                                                        const double *__restrict__ box_r, double side, int64_t nt,
+                                                        const double *__restrict__ tc,
+                                                        const float *__restrict__ tc32,
+                                                        const cplx<R> *__restrict__ L, CombineArgs ca,
+                                                        double *__restrict__ yfar)
 {
     constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     constexpr int NCH = STOKES ? 4 : 1;
-    constexpr int NV = STOKES ? 3 : 1;        // potentials evaluated
-    constexpr int NG = STOKES ? 12 : 0;       // gradients evaluated (channel x direction)
-    // the expansions of the order at hand only (l2p_shm): sized for p, not
-    // for the largest order, so that many leaves' blocks share a CU
+    constexpr int NV = STOKES ? 3 : 1;  // potentials evaluated
+    constexpr int NA = l2p_nacc<R, KIND>();  // potentials, then gradients (channel x direction)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int nc = ncoef(p);
-    cplx<R> *V = reinterpret_cast<cplx<R> *>(smem_raw);  // [NV][nc]
-    cplx<R> *G = V + NV * nc;                              // [NG][nc] (gradients: order p - 1)
+    cplx<R> *E = reinterpret_cast<cplx<R> *>(smem_raw);                   // [nc][NCH]
+    R *red = reinterpret_cast<R *>(smem_raw + sizeof(cplx<R>) * NCH * nc);  // [L2P_WAVES - 1][NA][64]
     const int b = leaves[blockIdx.x];
     const int lv = box_i[6 * b], tb = box_i[6 * b + 1], te = box_i[6 * b + 2];
     const double s = ldexp(side, -(lv + 1));
     const double *c = box_r + 5 * (int64_t)b;
     const cplx<R> *Lb = L + (int64_t)b * NCH * ncs;
-    for (int t = threadIdx.x; t < nc; t += blockDim.x)
-        for (int a = 0; a < NV; ++a)
-            V[a * nc + t] = Lb[a * ncs + t];
-    if constexpr (STOKES) {
-        // gradient expansions (order p-1): dz: L_{j+1}^k; dx: (L_{j+1}^{k-1} - L_{j+1}^{k+1}) / 2;
-        // dy: (i/2) (L_{j+1}^{k-1} + L_{j+1}^{k+1})
-        const int ncg = ncoef(p - 1);
-        for (int t = threadIdx.x; t < ncg; t += blockDim.x) {
-            int j, k;
-            idx_to_nm(t, j, k);
-            for (int ch = 0; ch < 4; ++ch) {
-                const cplx<R> *E = Lb + ch * ncs;
-                cplx<R> a = load_full(E, j + 1, k - 1), bb = load_full(E, j + 1, k + 1 <= j + 1 ? k + 1 : j + 1);
-                if (k + 1 > j + 1)
-                    bb = cplx<R>{0, 0};
-                cplx<R> cz = load_full(E, j + 1, k);
-                G[(3 * ch + 0) * nc + t] = cplx<R>{R(0.5) * (a.re - bb.re), R(0.5) * (a.im - bb.im)};
-                G[(3 * ch + 1) * nc + t] = cplx<R>{-R(0.5) * (a.im + bb.im), R(0.5) * (a.re + bb.re)};
-                G[(3 * ch + 2) * nc + t] = cz;
-            }
-        }
+    for (int t = threadIdx.x; t < NCH * nc; t += blockDim.x) {
+        const int ch = t / nc, id = t - ch * nc;
+        E[id * NCH + ch] = Lb[(int64_t)ch * ncs + id];
     }
     __syncthreads();
-    for (int i = tb + threadIdx.x; i < te; i += blockDim.x) {
-        R x, y, z;
-        target_rel<R>(i, nt, s, c, tc, tc32, x, y, z);
-        R pot[NV], grd[NG > 0 ? NG : 1];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    for (int i0 = tb; i0 < te; i0 += 64) {
+        const int i = i0 + lane;
+        const bool live = i < te;
+        R x = 0, y = 0, z = 0;
+        if (live)
+            target_rel<R>(i, nt, s, c, tc, tc32, x, y, z);
+        R acc[NA];
 #pragma unroll
-        for (int a = 0; a < NV; ++a)
-            pot[a] = 0;
+        for (int a = 0; a < NA; ++a)
+            acc[a] = 0;
+        const R r2 = x * x + y * y + z * z;
+        R dre = 1, dim = 0;  // R_md^md
+        int md = 0;
+        for (int bk = 0;; ++bk) {
+            const int m = 4 * bk + ((bk & 1) ? L2P_WAVES - 1 - w : w);
+            if (m > p)
+                break;
+            for (; md < m; ++md) {
+                const R g = -inv_int<R>(2 * (md + 1));
+                const R ar = g * (x * dre - y * dim), ai = g * (x * dim + y * dre);
+                dre = ar;
+                dim = ai;
+            }
+            const R wgt = m == 0 ? R(1) : R(2);
+            R cr = dre, ci = dim, pr = 0, pi = 0;
+            for (int n = m; n <= p; ++n) {
+                if (n > m) {
+                    const R g = inv_int<R>((n - m) * (n + m));
+                    const R az = R(2 * n - 1) * z;
+                    const R nr = (az * cr - r2 * pr) * g, ni = (az * ci - r2 * pi) * g;
+                    pr = cr;
+                    pi = ci;
+                    cr = nr;
+                    ci = ni;
+                }
+                const R wr = wgt * cr, wi = wgt * ci;
+                const cplx<R> *e0 = E + cidx(n, m) * NCH;
+                cplx<R> v[NV];
 #pragma unroll
-        for (int a = 0; a < (NG > 0 ? NG : 1); ++a)
-            grd[a] = 0;
-        sweep_regular<R>(p, x, y, z, [&](int id, int n, R wr, R wi) {
+                for (int a = 0; a < NV; ++a)
+                    v[a] = e0[a];
+                if constexpr (STOKES) {
+                    if (n < p) {
+                        // (n + 1, m - 1 .. m + 1); at m = 0 the first is folded from the third
+                        const cplx<R> *e1 = E + cidx(n + 1, m) * NCH;
+                        cplx<R> ea[4], ez[4], eb[4];
 #pragma unroll
-            for (int a = 0; a < NV; ++a)
-                pot[a] += V[a * nc + id].re * wr + V[a * nc + id].im * wi;
-            if constexpr (STOKES) {
-                if (n < p) {
+                        for (int ch = 0; ch < 4; ++ch) {
+                            ea[ch] = e1[ch - NCH];
+                            ez[ch] = e1[ch];
+                            eb[ch] = e1[ch + NCH];
+                        }
+                        const R hr = R(0.5) * wr, hi = R(0.5) * wi;
 #pragma unroll
-                    for (int g = 0; g < NG; ++g)
-                        grd[g] += G[g * nc + id].re * wr + G[g * nc + id].im * wi;
+                        for (int ch = 0; ch < 4; ++ch) {
+                            const R are = m == 0 ? -eb[ch].re : ea[ch].re, aim = m == 0 ? eb[ch].im : ea[ch].im;
+                            const R dr = are - eb[ch].re, di = aim - eb[ch].im;
+                            const R sr = are + eb[ch].re, si = aim + eb[ch].im;
+                            R *g = acc + NV + 3 * ch;
+                            g[0] += dr * hr;
+                            g[0] += di * hi;
+                            g[1] += sr * hi;
+                            g[1] -= si * hr;
+                            g[2] += ez[ch].re * wr;
+                            g[2] += ez[ch].im * wi;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < NV; ++a) {
+                    acc[a] += v[a].re * wr;
+                    acc[a] += v[a].im * wi;
                 }
             }
-        });
-        if constexpr (!STOKES) {
-            const double yf = (double)pot[0] / s;
-            if constexpr (FAR)
-                yfar[i] = yf;
-            else
-                combine_target<KIND>(ca, i, &yf);
-        } else {
-            const double is = 1.0 / s, is2 = is * is;
-            const double xr[3] = {(double)x * s, (double)y * s, (double)z * s};  // x - c
-            double yf[3];
-            for (int dir = 0; dir < 3; ++dir) {
-                double u = (double)pot[dir] * is;
-                for (int a = 0; a < 3; ++a)
-                    u -= xr[a] * (double)grd[3 * a + dir] * is2;
-                u += (double)grd[9 + dir] * is2;
-                yf[dir] = u;
-            }
-            if constexpr (FAR) {
-                for (int dir = 0; dir < 3; ++dir)
-                    yfar[3 * i + dir] = yf[dir];
+        }
+        // the waves' partial sums, added in wave order
+        if (w > 0) {
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+                red[((w - 1) * NA + a) * 64 + lane] = acc[a];
+        }
+        __syncthreads();
+        if (w == 0 && live) {
+#pragma unroll
+            for (int v = 0; v < L2P_WAVES - 1; ++v)
+#pragma unroll
+                for (int a = 0; a < NA; ++a)
+                    acc[a] += red[(v * NA + a) * 64 + lane];
+            if constexpr (!STOKES) {
+                const double yf = (double)acc[0] / s;
+                if constexpr (FAR)
+                    yfar[i] = yf;
+                else
+                    combine_target<KIND>(ca, i, &yf);
             } else {
-                combine_target<KIND>(ca, i, yf);
+                const double is = 1.0 / s, is2 = is * is;
+                const double xr[3] = {(double)x * s, (double)y * s, (double)z * s};  // x - c
+                double yf[3];
+                for (int dir = 0; dir < 3; ++dir) {
+                    double u = (double)acc[dir] * is;
+                    for (int a = 0; a < 3; ++a)
+                        u -= xr[a] * (double)acc[NV + 3 * a + dir] * is2;
+                    u += (double)acc[NV + 9 + dir] * is2;
+                    yf[dir] = u;
+                }
+                if constexpr (FAR) {
+                    for (int dir = 0; dir < 3; ++dir)
+                        yfar[3 * i + dir] = yf[dir];
+                } else {
+                    combine_target<KIND>(ca, i, yf);
+                }
             }
         }
+        __syncthreads();  // red is rewritten by the next targets
     }
 }
 
@@ -1932,12 +2013,13 @@ __device__ __forceinline__ void p2p_phase(const Src<R, vec_src<KIND>()> *__restr
         const R r2 = dx * dx + dy * dy + dz * dz;
         R rinv;
         if constexpr (sizeof(R) == 8) {
-            // hardware estimate refined by two Newton steps (r2 is finite and > 0
-            // for every pair the result keeps; the self pair is masked below)
+            // hardware estimate (documented to 2^29 ulp, a relative error of
+            // 2^-23) refined by one Newton step y (3/2 - r2 y^2 / 2), which
+            // squares the relative error (times 3/2): about 2^-45 (r2 is
+            // finite and > 0 for every pair the result keeps; the self pair
+            // is masked below)
             double y = __builtin_amdgcn_rsq(r2);
-            const double h = 0.5 * r2;
-            y = y * (1.5 - h * y * y);
-            y = y * (1.5 - h * y * y);
+            y = y * (1.5 - (0.5 * r2) * (y * y));
             rinv = y;
         } else {
             rinv = __builtin_amdgcn_rsqf(r2);
@@ -2475,9 +2557,9 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         {
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
             if (NCH == 4 && !rot)  // the rotation M2L moves the fourth channel's centre itself
-                k_m2l_reduce<R, NCH, true><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
+                k_m2l_reduce<R, NCH, true><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             else
-                k_m2l_reduce<R, NCH, false><<<T.nbox, 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
+                k_m2l_reduce<R, NCH, false><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             FB_HIP(hipGetLastError());
         }
         // one channel at the low orders: L2L down each leaf's chain of
@@ -2507,18 +2589,17 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 FB_HIP(hipGetLastError());
             }
             corr_spmv<KIND>(ctx, ca, st);  // while the near field may still run
-            constexpr int NQS = KIND == FMMBEM_STOKES_SL ? 3 + 12 : 1;
-            const size_t lshm = sizeof(cplx<R>) * NQS * ncoef(p);
+            const size_t lshm = l2p_shm<R, KIND>(p);
             if (p <= L2P_FAR_MAX_P) {
                 // the far field while the near field may still run, then the combine
-                k_l2p<R, KIND, true><<<T.nleaf, 64, lshm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc,
+                k_l2p<R, KIND, true><<<T.nleaf, 64 * L2P_WAVES, lshm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc,
                                                                 G.tc32, L, ca, ctx->y_far);
                 FB_HIP(hipGetLastError());
                 FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
                 k_combine<KIND><<<grid_for(nt, 64), 64, 0, st>>>(nt, ca, ctx->y_far);
             } else {
                 FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // L2P combines with the near field
-                k_l2p<R, KIND, false><<<T.nleaf, 64, lshm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc,
+                k_l2p<R, KIND, false><<<T.nleaf, 64 * L2P_WAVES, lshm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc,
                                                                  G.tc32, L, ca, nullptr);
             }
             FB_HIP(hipGetLastError());
