@@ -13,6 +13,9 @@ thread_local const PinnedProvider *t_pinned = nullptr;
 
 void set_last_error(const std::string &m) { g_last_error = m; }
 
+// stage clocks only measure time: no system-scope fence when they complete
+constexpr unsigned TIMING_EVENT_FLAGS = hipEventDefault | hipEventDisableSystemFence;
+
 void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev)
 {
     *ev = nullptr;
@@ -21,7 +24,7 @@ void stage_begin(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t *ev)
     Timing &T = ctx->timing;
     if (T.pool.empty()) {
         hipEvent_t e;
-        FB_HIP(hipEventCreate(&e));
+        FB_HIP(hipEventCreateWithFlags(&e, TIMING_EVENT_FLAGS));
         T.pool.push_back(e);
     }
     *ev = T.pool.back();
@@ -50,7 +53,7 @@ void stage_end(fmmbem_ctx *ctx, int stage, hipStream_t st, hipEvent_t ev, double
     Timing &T = ctx->timing;
     if (T.pool.empty()) {
         hipEvent_t e;
-        FB_HIP(hipEventCreate(&e));
+        FB_HIP(hipEventCreateWithFlags(&e, TIMING_EVENT_FLAGS));
         T.pool.push_back(e);
     }
     hipEvent_t e2 = T.pool.back();

@@ -424,11 +424,14 @@ struct fmmbem_ctx {
     fmmbem::Timing timing;
     fmmbem::KrylovWork *kw = nullptr;
     fmmbem::NearMatrix nearm;
-    // P2P runs on a stream of its own, concurrently with the far-field chain
-    // (fork after the charges, join before the combine)
+    // The near field and the far-field chain of a mat-vec run concurrently on
+    // two streams: the near field on the side stream (fork after the charges,
+    // join before the combine), or, where it is the longer of the two
+    // (near_on_main), the near field on the main stream right after the
+    // charges and the far chain on the side stream, joined before the combine
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    bool near_pending = false;  // a near field launched on the side stream that no stream has joined yet
+    bool side_pending = false;  // work on the side stream that the main stream has not joined yet (ev_join marks its end)
     // charges already launched for this input and precision ahead of the
     // mat-vec that will use them, with the upward pass of order spec_up_p
     // (-1: none; see prefetch_charges)
@@ -436,6 +439,7 @@ struct fmmbem_ctx {
     int spec_prec = -1;
     int spec_up_p = -1;
     bool spec_near = false;  // the near field of those charges already launched
+    bool spec_swap = false;  // the prefetched mat-vec runs its near field on the main stream (near_on_main)
     // Hessenberg column of fmmbem_solve_ctx_static (pinned, device-mapped,
     // made at build for restarts up to FMMBEM_STATIC_MAX_RESTART) and its event
     double *hcol_s = nullptr, *hcol_s_dev = nullptr;
@@ -511,10 +515,19 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
 // next run_matvec with the same x and prec uses them and starts the near field
 // from them), then optionally the upward pass (P2M, M2M) of order p_up, whose
 // multipoles that run_matvec uses when its order is <= p_up
-void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st, const NormIn &nz = NormIn{});
+// (near_main: the mat-vec will run its near field on the main stream st and
+// its upward pass and far chain on the side stream)
+void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st, const NormIn &nz = NormIn{},
+                      bool near_main = false);
 void prefetch_up(fmmbem_ctx *ctx, int prec, int p_up, hipStream_t st);
-// launch the near field of the prefetched charges on the side stream now
-void prefetch_side_near(fmmbem_ctx *ctx);
+// launch the near field of the prefetched charges now (on the side stream, or
+// on st for near_main)
+void prefetch_near(fmmbem_ctx *ctx, hipStream_t st);
+// whether a mat-vec of order p and precision prec runs its near field on the
+// main stream and its far chain on the side stream: FP32 Stokes with the
+// near field on the fly at the orders where its L2P evaluates the far field
+// alone (the near field is then the longer branch)
+bool near_on_main(const fmmbem_ctx *ctx, int p, int prec);
 // stored near field (nearfield.hip): assemble at build; one product on
 // stream st of the input in sorted order (nearm.xs, written by the charges)
 void build_near_matrix(fmmbem_ctx *ctx, hipStream_t st);

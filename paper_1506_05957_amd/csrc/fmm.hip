@@ -2309,7 +2309,7 @@ void launch_charges(fmmbem_ctx *ctx, const double *x, hipStream_t st, const Norm
     const int64_t nt = ctx->nt, ns = ctx->nsrc;
     Src<R, VS> *src = static_cast<Src<R, VS> *>(ctx->charges);
     hipEvent_t ev;
-    if (ctx->near_pending)  // the charges buffer may still be read by an earlier P2P
+    if (ctx->side_pending)  // the charges buffer may still be read on the side stream (P2P, or P2M)
         FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
 
     stage_begin(ctx, SO + 4, st, &ev);
@@ -2322,11 +2322,13 @@ void launch_charges(fmmbem_ctx *ctx, const double *x, hipStream_t st, const Norm
     FB_HIP(hipEventRecord(ctx->ev_fork, st));
 }
 
-// the near field (P2P, or the stored near-field product) on the side stream
-// once the charges marked by ev_fork are written; ev_join marks its end
+// the near field (P2P, or the stored near-field product) on stream ns: on the
+// side stream once the charges marked by ev_fork are written (ev_join marks
+// its end), or on the stream of the charges themselves
 template <typename R, int KIND>
-void launch_side_near(fmmbem_ctx *ctx)
+void launch_near(fmmbem_ctx *ctx, hipStream_t ns)
 {
+    const bool on_side = ns == ctx->side;
     constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     constexpr bool VS = vec_src<KIND>();
     constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
@@ -2337,30 +2339,33 @@ void launch_side_near(fmmbem_ctx *ctx)
     hipEvent_t ev;
     // a wait on an event that has completed costs the host next to nothing,
     // one on a pending event about as much as several kernel launches
-    FB_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-    stage_begin(ctx, SO + 0, ctx->side, &ev);
+    if (on_side)
+        FB_HIP(hipStreamWaitEvent(ns, ctx->ev_fork, 0));
+    stage_begin(ctx, SO + 0, ns, &ev);
     if (ctx->nearm.v64) {
         // stored near field: 2 flops per matrix entry
-        launch_near_stored(ctx, sizeof(R) == 8 ? FMMBEM_FP64 : FMMBEM_FP32, ctx->side);
-        stage_end(ctx, SO + 0, ctx->side, ev, 2.0 * (STOKES ? 9.0 : 1.0) * (double)ctx->nearm.entries);
+        launch_near_stored(ctx, sizeof(R) == 8 ? FMMBEM_FP64 : FMMBEM_FP32, ns);
+        stage_end(ctx, SO + 0, ns, ev, 2.0 * (STOKES ? 9.0 : 1.0) * (double)ctx->nearm.entries);
     } else {
         if (T.n_unit > 0) {
-            k_p2p<R, KIND><<<8 * T.p2p_xcd.max_count(), 64 * P2P_WAVES, 0, ctx->side>>>(
+            k_p2p<R, KIND><<<8 * T.p2p_xcd.max_count(), 64 * P2P_WAVES, 0, ns>>>(
                 T.p2p_xcd, T.p2p_unit, T.p2p_chunk, T.p2p_choff, nt, G.tc, G.tc32, src, T.p2p_dst, T.p2p_part,
                 ctx->y_near);
             FB_HIP(hipGetLastError());
             if (T.n_split > 0) {
                 constexpr int NQ = STOKES ? 3 : 1;
-                k_p2p_pieces<NQ><<<T.n_split, 256, 0, ctx->side>>>(T.p2p_split, T.p2p_part, ctx->y_near);
+                k_p2p_pieces<NQ><<<T.n_split, 256, 0, ns>>>(T.p2p_split, T.p2p_part, ctx->y_near);
                 FB_HIP(hipGetLastError());
             }
         }
         // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
         const double fl = STOKES ? 30.0 : KIND == FMMBEM_LAPLACE_DL ? 18.0 : 12.0;
-        stage_end(ctx, SO + 0, ctx->side, ev, fl * (double)(T.p2p_interactions - 4 * nt));
+        stage_end(ctx, SO + 0, ns, ev, fl * (double)(T.p2p_interactions - 4 * nt));
     }
-    FB_HIP(hipEventRecord(ctx->ev_join, ctx->side));
-    ctx->near_pending = true;
+    if (on_side) {
+        FB_HIP(hipEventRecord(ctx->ev_join, ns));
+        ctx->side_pending = true;
+    }
 }
 
 // The upward pass of order p on st: P2M of every leaf, then M2M level by level
@@ -2481,8 +2486,10 @@ void launch_m2l_rot(fmmbem_ctx *ctx, int p, const cplx<R> *M, cplx<R> *Y, hipStr
 }
 
 template <typename R, int KIND>
-void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bool have_up)
+void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bool have_up, bool swap)
 {
+    // the chain runs on fs: the main stream st, or with swap (near field on
+    // st) the side stream, whose far field the combine on st joins
     constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
     constexpr int NCH = STOKES ? 4 : 1;
     constexpr int SO = sizeof(R) == 8 ? 0 : 5;  // stage offset of this precision
@@ -2494,10 +2501,13 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
     cplx<R> *M = static_cast<cplx<R> *>(ctx->M);
     cplx<R> *L = static_cast<cplx<R> *>(ctx->L);
     hipEvent_t ev;
+    const hipStream_t fs = swap ? ctx->side : st;
 
     if (T.n_m2l > 0) {
+        if (swap && !have_up)
+            FB_HIP(hipStreamWaitEvent(fs, ctx->ev_fork, 0));  // the charges
         if (!have_up)
-            up_pass<R, KIND>(ctx, p, st);
+            up_pass<R, KIND>(ctx, p, fs);
         const M2LPlan &P = ctx->m2l;
         const R *l2l_op;
         if constexpr (sizeof(R) == 8)
@@ -2508,7 +2518,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         const bool rot = P.rot64_f && p >= ROT_MIN_P;
         const int row_chunks = (2 * ncoef(p) + 63) / 64;
 
-        stage_begin(ctx, SO + 1, st, &ev);
+        stage_begin(ctx, SO + 1, fs, &ev);
         {
             const cplx<R> *table;
             if constexpr (sizeof(R) == 8)
@@ -2517,7 +2527,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 table = P.table32;
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
             if (rot) {
-                launch_m2l_rot<R, NCH>(ctx, p, M, Y, st);
+                launch_m2l_rot<R, NCH>(ctx, p, M, Y, fs);
             } else if constexpr (sizeof(R) == 4) {
                 // one wave per 16-row tile up to four tiles (the low orders of the
                 // relaxed iterations: no wave idles, one tile's accumulators per
@@ -2525,19 +2535,19 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 const int nrt = (2 * ncoef(p) + 15) / 16;
                 FB_REQUIRE(nrt <= 16, FMMBEM_EINVAL, "FP32 M2L beyond its order limit");
                 if (nrt <= 4)
-                    k_m2l_mfma<R, NCH, 1><<<P.n_chunks, 64 * nrt, m2l_mfma_shm<R>(p), st>>>(
+                    k_m2l_mfma<R, NCH, 1><<<P.n_chunks, 64 * nrt, m2l_mfma_shm<R>(p), fs>>>(
                         p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
                 else
-                    k_m2l_mfma<R, NCH, 4><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), st>>>(
+                    k_m2l_mfma<R, NCH, 4><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), fs>>>(
                         p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
             } else if (P.ops64) {
-                k_m2l_stored<NCH><<<P.n_chunks, 256, 0, st>>>(p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin,
+                k_m2l_stored<NCH><<<P.n_chunks, 256, 0, fs>>>(p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin,
                                                                P.chunk_trans, P.pair_sorted, T.m2l_pairs, P.ops64,
                                                                M, Y);
             } else {
                 constexpr int PB = NCH == 1 ? 8 : 2;
                 const size_t shm = sizeof(cplx<R>) * (size_t)(2 * p + 1) * (2 * p + 1);
-                k_m2l_valu<R, NCH, PB><<<P.n_chunks, 256, shm, st>>>(
+                k_m2l_valu<R, NCH, PB><<<P.n_chunks, 256, shm, fs>>>(
                     p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
             }
             FB_HIP(hipGetLastError());
@@ -2550,16 +2560,16 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         // per order: 20 sum_{m <= p + 1} m^2
         const double q1 = p + 1.0;
         const double fl = rot ? 20.0 * q1 * (p + 2.0) * (2.0 * p + 3.0) / 6.0 : 4.0 * q1 * q1 * q1 * (p + 2.0);
-        stage_end(ctx, SO + 1, st, ev, fl * NCH * (double)T.n_m2l);
+        stage_end(ctx, SO + 1, fs, ev, fl * NCH * (double)T.n_m2l);
 
         // the downward pass: the per-target sum of the M2L terms, then L2L and L2P
-        stage_begin(ctx, SO + 3, st, &ev);
+        stage_begin(ctx, SO + 3, fs, &ev);
         {
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
             if (NCH == 4 && !rot)  // the rotation M2L moves the fourth channel's centre itself
-                k_m2l_reduce<R, NCH, true><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
+                k_m2l_reduce<R, NCH, true><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             else
-                k_m2l_reduce<R, NCH, false><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, st>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
+                k_m2l_reduce<R, NCH, false><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             FB_HIP(hipGetLastError());
         }
         // one channel at the low orders: L2L down each leaf's chain of
@@ -2567,6 +2577,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         // block per leaf, where the chain and its operators fit in LDS
         bool fused = false;
         if constexpr (NCH == 1) {
+            FB_REQUIRE(!swap, FMMBEM_EINTERNAL, "one channel keeps the near field on the side stream");
             const size_t dshm = down_leaf_shm<R>(p, std::max(1, T.nlevels - std::max(P.lmin_tgt, 0)));
             if (dshm > 0) {
                 corr_spmv<KIND>(ctx, ca, st);  // while the near field may still run
@@ -2584,28 +2595,35 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 const int t0 = P.tile_begin[l], ntile = P.tile_begin[l + 1] - t0;
                 if (ntile == 0)
                     continue;
-                k_octant_apply<R, NCH, true><<<dim3(ntile, row_chunks), 256, op_shm, st>>>(
+                k_octant_apply<R, NCH, true><<<dim3(ntile, row_chunks), 256, op_shm, fs>>>(
                     p, ncs, P.op_dim, l2l_op, P.tiles, t0, P.level_list, T.box_i, T.box_r, L, L);
                 FB_HIP(hipGetLastError());
             }
-            corr_spmv<KIND>(ctx, ca, st);  // while the near field may still run
+            corr_spmv<KIND>(ctx, ca, fs);  // while the near field may still run
             const size_t lshm = l2p_shm<R, KIND>(p);
-            if (p <= L2P_FAR_MAX_P) {
+            if (swap || p <= L2P_FAR_MAX_P) {
                 // the far field while the near field may still run, then the combine
-                k_l2p<R, KIND, true><<<T.nleaf, 64 * L2P_WAVES, lshm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc,
-                                                                G.tc32, L, ca, ctx->y_far);
+                k_l2p<R, KIND, true><<<T.nleaf, 64 * L2P_WAVES, lshm, fs>>>(p, ncs, T.leaves, T.box_i, T.box_r, side,
+                                                                           nt, G.tc, G.tc32, L, ca, ctx->y_far);
                 FB_HIP(hipGetLastError());
+                if (swap) {  // the far field ends the side stream's work; the combine on st joins it
+                    stage_end(ctx, SO + 3, fs, ev);
+                    ev = nullptr;
+                    FB_HIP(hipEventRecord(ctx->ev_join, fs));
+                    ctx->side_pending = true;
+                }
                 FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
                 k_combine<KIND><<<grid_for(nt, 64), 64, 0, st>>>(nt, ca, ctx->y_far);
             } else {
                 FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // L2P combines with the near field
-                k_l2p<R, KIND, false><<<T.nleaf, 64 * L2P_WAVES, lshm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side, nt, G.tc,
-                                                                 G.tc32, L, ca, nullptr);
+                k_l2p<R, KIND, false><<<T.nleaf, 64 * L2P_WAVES, lshm, st>>>(p, ncs, T.leaves, T.box_i, T.box_r, side,
+                                                                            nt, G.tc, G.tc32, L, ca, nullptr);
             }
             FB_HIP(hipGetLastError());
         }
-        stage_end(ctx, SO + 3, st, ev);
+        stage_end(ctx, SO + 3, fs, ev);
     } else {
+        FB_REQUIRE(!swap, FMMBEM_EINTERNAL, "no far field to run on the side stream");
         hipEvent_t ev4;
         stage_begin(ctx, SO + 4, st, &ev4);
         fill_zero(ctx->y_far, ctx->n, st);
@@ -2617,23 +2635,23 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
     }
 }
 
-void far_dispatch(fmmbem_ctx *ctx, int p, int prec, const CombineArgs &ca, hipStream_t st, bool have_up)
+void far_dispatch(fmmbem_ctx *ctx, int p, int prec, const CombineArgs &ca, hipStream_t st, bool have_up, bool swap)
 {
     const int kind = ctx->kernel;
     if (prec == FMMBEM_FP64) {
         if (kind == FMMBEM_STOKES_SL)
-            far_chain<double, FMMBEM_STOKES_SL>(ctx, p, ca, st, have_up);
+            far_chain<double, FMMBEM_STOKES_SL>(ctx, p, ca, st, have_up, swap);
         else if (kind == FMMBEM_LAPLACE_DL)
-            far_chain<double, FMMBEM_LAPLACE_DL>(ctx, p, ca, st, have_up);
+            far_chain<double, FMMBEM_LAPLACE_DL>(ctx, p, ca, st, have_up, swap);
         else
-            far_chain<double, FMMBEM_LAPLACE_SL>(ctx, p, ca, st, have_up);
+            far_chain<double, FMMBEM_LAPLACE_SL>(ctx, p, ca, st, have_up, swap);
     } else {
         if (kind == FMMBEM_STOKES_SL)
-            far_chain<float, FMMBEM_STOKES_SL>(ctx, p, ca, st, have_up);
+            far_chain<float, FMMBEM_STOKES_SL>(ctx, p, ca, st, have_up, swap);
         else if (kind == FMMBEM_LAPLACE_DL)
-            far_chain<float, FMMBEM_LAPLACE_DL>(ctx, p, ca, st, have_up);
+            far_chain<float, FMMBEM_LAPLACE_DL>(ctx, p, ca, st, have_up, swap);
         else
-            far_chain<float, FMMBEM_LAPLACE_SL>(ctx, p, ca, st, have_up);
+            far_chain<float, FMMBEM_LAPLACE_SL>(ctx, p, ca, st, have_up, swap);
     }
 }
 
@@ -2677,41 +2695,48 @@ void charges_dispatch(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st
     }
 }
 
-void side_near_dispatch(fmmbem_ctx *ctx, int prec)
+void near_dispatch(fmmbem_ctx *ctx, int prec, hipStream_t ns)
 {
     const int kind = ctx->kernel;
     if (prec == FMMBEM_FP64) {
         if (kind == FMMBEM_STOKES_SL)
-            launch_side_near<double, FMMBEM_STOKES_SL>(ctx);
+            launch_near<double, FMMBEM_STOKES_SL>(ctx, ns);
         else if (kind == FMMBEM_LAPLACE_DL)
-            launch_side_near<double, FMMBEM_LAPLACE_DL>(ctx);
+            launch_near<double, FMMBEM_LAPLACE_DL>(ctx, ns);
         else
-            launch_side_near<double, FMMBEM_LAPLACE_SL>(ctx);
+            launch_near<double, FMMBEM_LAPLACE_SL>(ctx, ns);
     } else {
         if (kind == FMMBEM_STOKES_SL)
-            launch_side_near<float, FMMBEM_STOKES_SL>(ctx);
+            launch_near<float, FMMBEM_STOKES_SL>(ctx, ns);
         else if (kind == FMMBEM_LAPLACE_DL)
-            launch_side_near<float, FMMBEM_LAPLACE_DL>(ctx);
+            launch_near<float, FMMBEM_LAPLACE_DL>(ctx, ns);
         else
-            launch_side_near<float, FMMBEM_LAPLACE_SL>(ctx);
+            launch_near<float, FMMBEM_LAPLACE_SL>(ctx, ns);
     }
 }
 
 }  // namespace
 
-void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st, const NormIn &nz)
+bool near_on_main(const fmmbem_ctx *ctx, int p, int prec)
+{
+    return ctx->kernel == FMMBEM_STOKES_SL && !ctx->prm.near_stored && prec == FMMBEM_FP32 && p <= L2P_FAR_MAX_P &&
+           ctx->tree.n_m2l > 0 && ctx->tree.n_unit > 0;
+}
+
+void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st, const NormIn &nz, bool near_main)
 {
     charges_dispatch(ctx, prec, x, st, nz);
     ctx->spec_x = x;
     ctx->spec_prec = prec;
     ctx->spec_up_p = -1;
     ctx->spec_near = false;
+    ctx->spec_swap = near_main && ctx->kernel == FMMBEM_STOKES_SL && !ctx->prm.near_stored && ctx->tree.n_m2l > 0;
 }
 
-void prefetch_side_near(fmmbem_ctx *ctx)
+void prefetch_near(fmmbem_ctx *ctx, hipStream_t st)
 {
     FB_REQUIRE(ctx->spec_x != nullptr, FMMBEM_EINTERNAL, "near field prefetched without the charges");
-    side_near_dispatch(ctx, ctx->spec_prec);
+    near_dispatch(ctx, ctx->spec_prec, ctx->spec_swap ? st : ctx->side);
     ctx->spec_near = true;
 }
 
@@ -2722,7 +2747,14 @@ void prefetch_up(fmmbem_ctx *ctx, int prec, int p_up, hipStream_t st)
     FB_REQUIRE(p_up >= 1 && p_up <= ctx->prm.p_max && (prec == FMMBEM_FP64 || p_up <= P_MAX_FP32),
                FMMBEM_EINVAL, "upward pass order out of range");
     if (ctx->tree.n_m2l > 0) {
-        up_dispatch(ctx, p_up, prec, st);
+        if (ctx->spec_swap) {  // on the side stream, where the far chain will follow it
+            FB_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+            up_dispatch(ctx, p_up, prec, ctx->side);
+            FB_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+            ctx->side_pending = true;
+        } else {
+            up_dispatch(ctx, p_up, prec, st);
+        }
         ctx->spec_up_p = p_up;
     }
 }
@@ -2736,16 +2768,19 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
     const bool have_charges = ctx->spec_x == x && ctx->spec_prec == prec;
     const bool have_up = have_charges && ctx->spec_up_p >= p;
     const bool have_near = have_charges && ctx->spec_near;
+    // the order of the streams: as prefetched, else chosen here
+    const bool swap = have_charges ? ctx->spec_swap : near_on_main(ctx, p, prec);
     ctx->spec_x = nullptr;
     ctx->spec_prec = -1;
     ctx->spec_up_p = -1;
     ctx->spec_near = false;
+    ctx->spec_swap = false;
     if (!have_charges)
-        charges_dispatch(ctx, prec, x, st);
+        charges_dispatch(ctx, prec, x, st);  // (joins the side stream first if it still runs)
     else
         (void)hipEventQuery(ctx->ev_fork);  // refresh its state: usually complete by now
     if (!have_near)
-        side_near_dispatch(ctx, prec);
+        near_dispatch(ctx, prec, swap ? st : ctx->side);
     // stored near field: its blocks already hold the corrections of their pairs
     const Correction &C = ctx->prm.near_stored ? ctx->nearm.rest : ctx->corr;
     const double pref = kind == FMMBEM_STOKES_SL   ? -1.0 / (8.0 * M_PI * ctx->prm.mu)
@@ -2753,8 +2788,8 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
                                                     : 1.0 / (4.0 * M_PI);
     const CombineArgs ca{ctx->tree.perm, C.ptr, C.col_orig, C.val, x, ctx->y_near, pref, y,
                          C.nnz > 0 ? ctx->y_corr : nullptr};
-    far_dispatch(ctx, p, prec, ca, st, have_up);  // ends with the join and the combine
-    ctx->near_pending = false;
+    far_dispatch(ctx, p, prec, ca, st, have_up, swap);  // ends with the join and the combine on st
+    ctx->side_pending = false;
 }
 
 void build_m2l_operators(fmmbem_ctx *ctx, hipStream_t st)

@@ -379,27 +379,29 @@ GmresState::~GmresState()
 {
     // a solve left early (an error, or b = 0) may still have a prefetched
     // mat-vec in flight: let it end before the context is used again
-    if (ctx->spec_x || ctx->near_pending) {
-        if (ctx->near_pending)
+    if (ctx->spec_x || ctx->side_pending) {
+        if (ctx->side_pending)
             (void)hipStreamWaitEvent(st, ctx->ev_join, 0);
         (void)hipStreamSynchronize(st);
         ctx->spec_x = nullptr;
         ctx->spec_prec = ctx->spec_up_p = -1;
         ctx->spec_near = false;
-        ctx->near_pending = false;
+        ctx->spec_swap = false;
+        ctx->side_pending = false;
     }
 }
 
 // wait for the prefetched charges, upward pass and near field, and drop them
 void GmresState::drain_prefetch()
 {
-    if (ctx->near_pending)
+    if (ctx->side_pending)
         FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
     FB_HIP(hipStreamSynchronize(st));
     ctx->spec_x = nullptr;
     ctx->spec_prec = ctx->spec_up_p = -1;
     ctx->spec_near = false;
-    ctx->near_pending = false;
+    ctx->spec_swap = false;
+    ctx->side_pending = false;
 }
 
 void GmresState::record(int p, int prec, double r)
@@ -475,6 +477,7 @@ void GmresState::enqueue_step()
     // this one) and at most two above the order at the extrapolated residual;
     // a mat-vec of a higher order than the prefetched pass runs its own.
     int pre_prec = -1, p_up = 0;
+    bool pre_swap = false;
     if (bnorm_known && k + 1 < m && it + 1 < s.max_iter) {
         const double ratio = rho_prev2 > 0.0 ? std::min(1.0, rho_prev / rho_prev2) : 0.01;
         const double rho_next = rho_prev * ratio;
@@ -484,6 +487,7 @@ void GmresState::enqueue_step()
             p_up = std::min(cur.p, nx.p + 2);
             if (pre_prec == FMMBEM_FP32)
                 p_up = std::min(p_up, P_MAX_FP32);
+            pre_swap = near_on_main(ctx, nx.p, pre_prec);
         }
     }
     if (pre_prec < 0) {
@@ -494,16 +498,22 @@ void GmresState::enqueue_step()
     if (pre_prec >= 0) {
         // v_{k+1} = w / |w| (and |w|^2 into the host column) is written
         // by these charges
-        prefetch_charges(ctx, pre_prec, vn, st, NormIn{kw->w, kw->partn, kw->nb, kw->hcol_dev + (k + 1)});
+        prefetch_charges(ctx, pre_prec, vn, st, NormIn{kw->w, kw->partn, kw->nb, kw->hcol_dev + (k + 1)},
+                         pre_swap);
     }
     FB_HIP(hipEventRecord(ev_h, st));
-    if (pre_prec >= 0) {
+    if (pre_prec >= 0 && pre_swap) {
+        // the near field right behind the charges on this stream, the
+        // upward pass on the side stream
+        prefetch_near(ctx, st);
+        prefetch_up(ctx, pre_prec, p_up, st);
+    } else if (pre_prec >= 0) {
         prefetch_up(ctx, pre_prec, p_up, st);
         // the near field after the launches the GPU needs first: its fork
         // waits on the pending charges (several launches' worth of host
         // time, which the host would spend waiting anyway), and the product
         // is done sooner than when forked after the host's wait
-        prefetch_side_near(ctx);
+        prefetch_near(ctx, st);
     }
 }
 
