@@ -133,6 +133,68 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_sub_first(int64_t n, int rpt, con
     }
 }
 
+// The first update and the second pass of CGS2 in one: w -= sum_{j<nv} h1[j]
+// V_j (h1 summed from the first pass's partials, as in k_sub_first), then
+// part2[j][b] = V_j . w over row block b, j < nv <= 8 NVC.  A row's vectors
+// are read for the update and right after for the dots (the second read
+// comes from L2); a thread keeps the partial dots of every vector over its
+// rows, and the block adds them up (shuffle tree per wave, then the waves in
+// order).  Dynamic LDS: nv doubles.
+template <int NVC>
+__global__ __launch_bounds__(DOT_BLOCK) void k_sub_dots(int64_t n, int rpt, const double *__restrict__ V, int64_t ldv,
+                                                         int nv, const double *__restrict__ part1, int nb,
+                                                         double *__restrict__ w, double *__restrict__ part2)
+{
+    extern __shared__ double hs[];  // [nv]
+    __shared__ double sh[CGS_JG][DOT_NWV];
+    block_sums(part1, nb, nv, hs);
+    __syncthreads();
+    double s[CGS_JG * NVC];
+#pragma unroll
+    for (int q = 0; q < CGS_JG * NVC; ++q)
+        s[q] = 0.0;
+    const int64_t base = (int64_t)blockIdx.x * rpt * DOT_BLOCK + threadIdx.x;
+    for (int k = 0; k < rpt; ++k) {
+        const int64_t i = base + (int64_t)k * DOT_BLOCK;
+        if (i >= n)
+            break;
+        const double x = sub_combination(w[i], V, ldv, nv, i, hs);
+        w[i] = x;
+#pragma unroll
+        for (int c = 0; c < NVC; ++c) {
+            double v[CGS_JG];
+#pragma unroll
+            for (int u = 0; u < CGS_JG; ++u)  // clamped, unguarded reads; the extra ones zeroed
+                v[u] = V[(int64_t)min(CGS_JG * c + u, nv - 1) * ldv + i];
+#pragma unroll
+            for (int u = 0; u < CGS_JG; ++u)
+                s[CGS_JG * c + u] += (CGS_JG * c + u < nv ? v[u] : 0.0) * x;
+        }
+    }
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < NVC; ++c) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int u = 0; u < CGS_JG; ++u)
+                s[CGS_JG * c + u] += __shfl_down(s[CGS_JG * c + u], off, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int u = 0; u < CGS_JG; ++u)
+                sh[u][wv] = s[CGS_JG * c + u];
+        __syncthreads();
+        const int j = CGS_JG * c + (int)threadIdx.x;
+        if ((int)threadIdx.x < CGS_JG && j < nv) {
+            double t = 0.0;
+            for (int q = 0; q < DOT_NWV; ++q)
+                t += sh[threadIdx.x][q];
+            part2[(int64_t)j * nb + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
 // h1, h2 summed from the two passes' partials; w -= sum_{j<nv} h2[j] V_j (h1
 // was taken off by k_sub_first before the second pass), and the partial of
 // |w|^2 of this row block into partn[b].  Block 0 also writes h1 to
@@ -291,6 +353,28 @@ void cgs_dots(KrylovWork *kw, const double *V, int nv, const double *w, double *
 {
     dim3 grid(kw->nb, (nv + CGS_JG - 1) / CGS_JG);
     k_cgs_dots<<<grid, DOT_BLOCK, 0, st>>>(kw->n, kw->rpt, V, kw->n, nv, w, part, kw->nb);
+    FB_HIP(hipGetLastError());
+}
+
+// w -= V h1 and part2 = V^T w (h1 from part1), for the nv vectors of V
+void sub_dots(KrylovWork *kw, int nv, hipStream_t st)
+{
+    const size_t shm = sizeof(double) * nv;
+    const int64_t n = kw->n;
+    switch ((nv + CGS_JG - 1) / CGS_JG) {
+    case 1: k_sub_dots<1><<<kw->nb, DOT_BLOCK, shm, st>>>(n, kw->rpt, kw->V, n, nv, kw->part1, kw->nb, kw->w, kw->part2); break;
+    case 2: k_sub_dots<2><<<kw->nb, DOT_BLOCK, shm, st>>>(n, kw->rpt, kw->V, n, nv, kw->part1, kw->nb, kw->w, kw->part2); break;
+    case 3: k_sub_dots<3><<<kw->nb, DOT_BLOCK, shm, st>>>(n, kw->rpt, kw->V, n, nv, kw->part1, kw->nb, kw->w, kw->part2); break;
+    case 4: k_sub_dots<4><<<kw->nb, DOT_BLOCK, shm, st>>>(n, kw->rpt, kw->V, n, nv, kw->part1, kw->nb, kw->w, kw->part2); break;
+    case 5: k_sub_dots<5><<<kw->nb, DOT_BLOCK, shm, st>>>(n, kw->rpt, kw->V, n, nv, kw->part1, kw->nb, kw->w, kw->part2); break;
+    case 6: k_sub_dots<6><<<kw->nb, DOT_BLOCK, shm, st>>>(n, kw->rpt, kw->V, n, nv, kw->part1, kw->nb, kw->w, kw->part2); break;
+    case 7: k_sub_dots<7><<<kw->nb, DOT_BLOCK, shm, st>>>(n, kw->rpt, kw->V, n, nv, kw->part1, kw->nb, kw->w, kw->part2); break;
+    default:  // more vectors than the fused kernel keeps: the update, then the dots
+        k_sub_first<<<kw->nb, DOT_BLOCK, shm, st>>>(n, kw->rpt, kw->V, n, nv, kw->part1, kw->nb, kw->w);
+        FB_HIP(hipGetLastError());
+        cgs_dots(kw, kw->V, nv, kw->w, kw->part2, st);
+        return;
+    }
     FB_HIP(hipGetLastError());
 }
 
@@ -457,10 +541,7 @@ void GmresState::enqueue_step()
     stage_begin(ctx, 10, st, &ev);
     // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2 (below, with |w|^2)
     cgs_dots(kw, kw->V, k + 1, kw->w, kw->part1, st);
-    k_sub_first<<<kw->nb, DOT_BLOCK, sizeof(double) * (k + 1), st>>>(n, kw->rpt, kw->V, n, k + 1, kw->part1,
-                                                                      kw->nb, kw->w);
-    FB_HIP(hipGetLastError());
-    cgs_dots(kw, kw->V, k + 1, kw->w, kw->part2, st);
+    sub_dots(kw, k + 1, st);
     // h1[0..k], |w|^2 at k + 1 and h2[0..k] at m + 2 go straight to the host column
     k_update_norm<<<kw->nb, DOT_BLOCK, 2 * sizeof(double) * (k + 1), st>>>(
         n, kw->rpt, kw->V, n, k + 1, kw->part1, kw->part2, kw->nb, kw->w, kw->partn, kw->hcol_dev, m + 2);
