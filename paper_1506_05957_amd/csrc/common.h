@@ -432,6 +432,7 @@ struct fmmbem_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool side_pending = false;  // work on the side stream that the main stream has not joined yet (ev_join marks its end)
+    bool corr_on_near = false;  // the correction product of the pending near field runs behind it on the side stream
     // charges already launched for this input and precision ahead of the
     // mat-vec that will use them, with the upward pass of order spec_up_p
     // (-1: none; see prefetch_charges)

@@ -2326,7 +2326,7 @@ void launch_charges(fmmbem_ctx *ctx, const double *x, hipStream_t st, const Norm
 // side stream once the charges marked by ev_fork are written (ev_join marks
 // its end), or on the stream of the charges themselves
 template <typename R, int KIND>
-void launch_near(fmmbem_ctx *ctx, hipStream_t ns)
+void launch_near(fmmbem_ctx *ctx, hipStream_t ns, const double *x)
 {
     const bool on_side = ns == ctx->side;
     constexpr bool STOKES = KIND == FMMBEM_STOKES_SL;
@@ -2361,6 +2361,15 @@ void launch_near(fmmbem_ctx *ctx, hipStream_t ns)
         // source-target pairs actually evaluated: all P2P pairs minus the 4 self points of each target
         const double fl = STOKES ? 30.0 : KIND == FMMBEM_LAPLACE_DL ? 18.0 : 12.0;
         stage_end(ctx, SO + 0, ns, ev, fl * (double)(T.p2p_interactions - 4 * nt));
+    }
+    // on the side stream the correction product S x follows the near field
+    // there, off the far chain (which is then the longer branch)
+    const Correction &C = ctx->prm.near_stored ? ctx->nearm.rest : ctx->corr;
+    ctx->corr_on_near = on_side && C.nnz > 0;
+    if (ctx->corr_on_near) {
+        constexpr int NQ = STOKES ? 3 : 1;
+        k_corr_spmv<NQ><<<grid_for(nt, 16), 256, 0, ns>>>(nt, C.ptr, C.col_orig, C.val, x, ctx->y_corr);
+        FB_HIP(hipGetLastError());
     }
     if (on_side) {
         FB_HIP(hipEventRecord(ctx->ev_join, ns));
@@ -2450,7 +2459,7 @@ void up_pass(fmmbem_ctx *ctx, int p, hipStream_t st)
 template <int KIND>
 void corr_spmv(fmmbem_ctx *ctx, const CombineArgs &ca, hipStream_t st)
 {
-    if (!ca.ycorr)
+    if (!ca.ycorr || ctx->corr_on_near)  // none, or already behind the near field
         return;
     constexpr int NQ = KIND == FMMBEM_STOKES_SL ? 3 : 1;
     k_corr_spmv<NQ><<<grid_for(ctx->nt, 16), 256, 0, st>>>(ctx->nt, ca.cptr, ca.ccol, ca.cval, ca.x, ctx->y_corr);
@@ -2695,23 +2704,23 @@ void charges_dispatch(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st
     }
 }
 
-void near_dispatch(fmmbem_ctx *ctx, int prec, hipStream_t ns)
+void near_dispatch(fmmbem_ctx *ctx, int prec, hipStream_t ns, const double *x)
 {
     const int kind = ctx->kernel;
     if (prec == FMMBEM_FP64) {
         if (kind == FMMBEM_STOKES_SL)
-            launch_near<double, FMMBEM_STOKES_SL>(ctx, ns);
+            launch_near<double, FMMBEM_STOKES_SL>(ctx, ns, x);
         else if (kind == FMMBEM_LAPLACE_DL)
-            launch_near<double, FMMBEM_LAPLACE_DL>(ctx, ns);
+            launch_near<double, FMMBEM_LAPLACE_DL>(ctx, ns, x);
         else
-            launch_near<double, FMMBEM_LAPLACE_SL>(ctx, ns);
+            launch_near<double, FMMBEM_LAPLACE_SL>(ctx, ns, x);
     } else {
         if (kind == FMMBEM_STOKES_SL)
-            launch_near<float, FMMBEM_STOKES_SL>(ctx, ns);
+            launch_near<float, FMMBEM_STOKES_SL>(ctx, ns, x);
         else if (kind == FMMBEM_LAPLACE_DL)
-            launch_near<float, FMMBEM_LAPLACE_DL>(ctx, ns);
+            launch_near<float, FMMBEM_LAPLACE_DL>(ctx, ns, x);
         else
-            launch_near<float, FMMBEM_LAPLACE_SL>(ctx, ns);
+            launch_near<float, FMMBEM_LAPLACE_SL>(ctx, ns, x);
     }
 }
 
@@ -2736,7 +2745,7 @@ void prefetch_charges(fmmbem_ctx *ctx, int prec, const double *x, hipStream_t st
 void prefetch_near(fmmbem_ctx *ctx, hipStream_t st)
 {
     FB_REQUIRE(ctx->spec_x != nullptr, FMMBEM_EINTERNAL, "near field prefetched without the charges");
-    near_dispatch(ctx, ctx->spec_prec, ctx->spec_swap ? st : ctx->side);
+    near_dispatch(ctx, ctx->spec_prec, ctx->spec_swap ? st : ctx->side, ctx->spec_x);
     ctx->spec_near = true;
 }
 
@@ -2780,7 +2789,7 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
     else
         (void)hipEventQuery(ctx->ev_fork);  // refresh its state: usually complete by now
     if (!have_near)
-        near_dispatch(ctx, prec, swap ? st : ctx->side);
+        near_dispatch(ctx, prec, swap ? st : ctx->side, x);
     // stored near field: its blocks already hold the corrections of their pairs
     const Correction &C = ctx->prm.near_stored ? ctx->nearm.rest : ctx->corr;
     const double pref = kind == FMMBEM_STOKES_SL   ? -1.0 / (8.0 * M_PI * ctx->prm.mu)
@@ -2790,6 +2799,7 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
                          C.nnz > 0 ? ctx->y_corr : nullptr};
     far_dispatch(ctx, p, prec, ca, st, have_up, swap);  // ends with the join and the combine on st
     ctx->side_pending = false;
+    ctx->corr_on_near = false;
 }
 
 void build_m2l_operators(fmmbem_ctx *ctx, hipStream_t st)
