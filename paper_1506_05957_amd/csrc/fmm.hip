@@ -614,147 +614,11 @@ __global__ __launch_bounds__(256) void k_p2m_dipole(int p, int ncs, const int32_
 // and in the scaled expansions
 //   M2M: M_n^m(P) += sum_{j <= n} 2^-j sum_mm conj(R_{n-j}^{m-mm}(delta)) M_j^mm(C)
 //   L2L: L_j^k(C) += 2^-(j+1) sum_{n >= j} sum_m L_n^m(P) conj(R_{n-j}^{m-k}(delta))
-// are fixed real linear maps of the stored coefficients, one per octant.  A
-// block takes a tile of boxes of one level and one octant (16 columns: boxes
-// x channels) and a chunk of 64 output rows: the input coefficients sit in
-// LDS, lane r streams operator row r (coalesced over rows) and skips the
-// inputs that the triangular structure zeroes.  M2M writes per-child terms that k_m2m_sum adds
-// up per parent in child order; L2L adds into the child.  Stokes: the fourth
-// channel changes centre with the first three (M2M: + d . Z, L2L: - d . Z,
-// d = c_C - c_P).
-template <typename R, int NCH, bool L2L>
-__global__ __launch_bounds__(256) void k_octant_apply(int p, int ncs, int D, const R *__restrict__ ops,
-                                                      const int4 *__restrict__ tiles, int tile0,
-                                                      const int32_t *__restrict__ list,
-                                                      const int32_t *__restrict__ box_i,
-                                                      const double *__restrict__ box_r, const cplx<R> *__restrict__ X,
-                                                      cplx<R> *__restrict__ Y)
-{
-    // block = (tile, chunk of 64 rows); lane = row, the 4 waves split the
-    // inputs k (wave w takes k = w, w + 4, ...) and are summed in wave order
-    constexpr int NCOL = 16, NW = 4;
-    constexpr int BPT = NCOL / NCH;  // boxes per tile
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *xs = reinterpret_cast<R *>(smem_raw);    // [Dp][NCOL], then
-    R *part = reinterpret_cast<R *>(smem_raw);  // [NW - 1][NCOL][64]
-    __shared__ int64_t colofs[NCOL];  // first real of each column's input, -1 past the tile
-    const int4 tl = tiles[tile0 + blockIdx.x];
-    const int o = tl.x, e0 = tl.y, cnt = tl.z;
-    const int Dp = 2 * ncoef(p);
-    if ((int)threadIdx.x < NCOL) {
-        const int col = threadIdx.x, b = col / NCH, ch = col - b * NCH;
-        int64_t ofs = -1;
-        if (b < cnt) {
-            const int box = list[e0 + b];
-            const int from = L2L ? box_i[6 * box + 3] : box;
-            ofs = 2 * (((int64_t)from * NCH + ch) * ncs);
-        }
-        colofs[col] = ofs;
-    }
-    __syncthreads();
-    // wave w stages columns 4 w .. 4 w + 3, the loads of a row issued together
-    // (columns past the tile read offset 0 and store zero)
-    {
-        const int w0 = threadIdx.x >> 6, lane0 = threadIdx.x & 63;
-        const R *Xr = reinterpret_cast<const R *>(X);
-        int64_t ofs[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            ofs[c] = colofs[4 * w0 + c];
-        for (int k = lane0; k < Dp; k += 64) {
-            R v[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                v[c] = Xr[(ofs[c] < 0 ? 0 : ofs[c]) + k];
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                xs[k * NCOL + 4 * w0 + c] = ofs[c] < 0 ? R(0) : v[c];
-        }
-    }
-    __syncthreads();
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int r = blockIdx.y * 64 + lane;
-    const bool active = r < Dp;
-    int n = 0, m = 0;
-    idx_to_nm(active ? r >> 1 : 0, n, m);
-    const int k0 = L2L ? 2 * cidx(n, 0) : 0;  // L2L: inputs of degree >= n
-    const int k1 = L2L ? Dp : 2 * ncoef(n);   // M2M: inputs of degree <= n
-    const R *A = ops + (int64_t)o * D * D + (active ? r : 0);
-    R acc[NCOL];
-#pragma unroll
-    for (int q = 0; q < NCOL; ++q)
-        acc[q] = 0;
-    // wave w takes the inputs k = w + NW t, t < nit, the same for all its
-    // lanes; entries outside the lane's triangle [k0, k1) are zeroed after an
-    // unguarded read (rows past Dp read row 0 and are not stored), so the
-    // operator reads of the next PF steps stay in flight
-    {
-        constexpr int PF = 8;
-        const int nit = w < Dp ? (Dp - w + NW - 1) / NW : 0;
-        if (nit > 0) {
-            R ring[PF];
-#pragma unroll
-            for (int j = 0; j < PF; ++j)
-                ring[j] = A[(int64_t)(w + NW * min(j, nit - 1)) * D];
-            auto step = [&](int t, R &slot) {
-                const int k = w + NW * t;
-                const R a = (k >= k0 && k < k1) ? slot : R(0);
-                const R *x = xs + k * NCOL;
-#pragma unroll
-                for (int q = 0; q < NCOL; ++q)
-                    acc[q] += a * x[q];
-                slot = A[(int64_t)(w + NW * min(t + PF, nit - 1)) * D];
-            };
-            const int nfull = nit - nit % PF;
-            for (int t0 = 0; t0 < nfull; t0 += PF) {
-#pragma unroll
-                for (int j = 0; j < PF; ++j)
-                    step(t0 + j, ring[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < PF; ++j)
-                if (nfull + j < nit)
-                    step(nfull + j, ring[j]);
-        }
-    }
-    __syncthreads();  // xs is dead from here on
-    if (w > 0) {
-#pragma unroll
-        for (int q = 0; q < NCOL; ++q)
-            part[((w - 1) * NCOL + q) * 64 + lane] = acc[q];
-    }
-    __syncthreads();
-    if (w != 0 || !active)
-        return;
-#pragma unroll
-    for (int q = 0; q < NCOL; ++q)
-        for (int v = 0; v < NW - 1; ++v)
-            acc[q] += part[(v * NCOL + q) * 64 + lane];
-#pragma unroll
-    for (int bq = 0; bq < BPT; ++bq) {
-        if (bq >= cnt)
-            break;
-        const int box = list[e0 + bq];
-        R v[NCH];
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-            v[ch] = acc[bq * NCH + ch];
-        if constexpr (NCH == 4) {
-            const double *cC = box_r + 5 * (int64_t)box, *cP = box_r + 5 * (int64_t)box_i[6 * box + 3];
-            const R d0 = (R)(cC[0] - cP[0]), d1 = (R)(cC[1] - cP[1]), d2 = (R)(cC[2] - cP[2]);
-            const R dv = d0 * v[0] + d1 * v[1] + d2 * v[2];
-            v[3] = L2L ? v[3] - dv : v[3] + dv;
-        }
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            R *dst = reinterpret_cast<R *>(Y + ((int64_t)box * NCH + ch) * ncs) + r;
-            if constexpr (L2L)
-                *dst += v[ch];
-            else
-                *dst = v[ch];
-        }
-    }
-}
+// are fixed real linear maps of the stored coefficients, one per octant
+// (k_octant_mfma, below, applies them on the matrix cores).  M2M writes
+// per-child terms that k_m2m_sum adds up per parent in child order; L2L adds
+// into the child.  Stokes: the fourth channel changes centre with the first
+// three (M2M: + d . Z, L2L: - d . Z, d = c_C - c_P).
 
 // M_P = sum of the per-child terms Z_C over the children of P, in child order
 template <typename R, int NCH>
@@ -819,6 +683,146 @@ __device__ __forceinline__ Acc4<double>::type mfma_16x16x4(double a, double b, A
 __device__ __forceinline__ Acc4<float>::type mfma_16x16x4(float a, float b, Acc4<float>::type c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// M2M and L2L with the octant operators on the matrix cores.  A block takes a
+// tile of 16 columns (boxes x channels) of one level and octant and a chunk
+// of 64 output rows, as 16x16x4 steps.  Wave w takes rows 16 w .. +15
+// of the chunk over the inputs that the triangular structure leaves (M2M:
+// degree <= the tile's last row's; L2L: >= its first row's; the operators
+// hold exact zeros elsewhere), so no wave sums another's partials: A from the
+// operator (rows contiguous per input, several reads in flight), B from the
+// staged inputs, one 8-byte LDS read per lane and step (a vector form with
+// lane = row read 16 broadcast inputs per step and was bound by LDS).  The
+// rows are then put back through LDS and written, one lane per row, with the
+// Stokes change of centre.  Dynamic LDS: octant_mfma_shm.
+template <typename R> size_t octant_mfma_shm(int p)
+{
+    const size_t Dp4 = (2 * (size_t)ncoef(p) + 3) & ~(size_t)3;
+    return sizeof(R) * 16 * std::max<size_t>(Dp4, 64);
+}
+
+template <typename R, int NCH, bool L2L>
+__global__ __launch_bounds__(256) void k_octant_mfma(int p, int ncs, int D, const R *__restrict__ ops,
+                                                     const int4 *__restrict__ tiles, int tile0,
+                                                     const int32_t *__restrict__ list,
+                                                     const int32_t *__restrict__ box_i,
+                                                     const double *__restrict__ box_r, const cplx<R> *__restrict__ X,
+                                                     cplx<R> *__restrict__ Y)
+{
+    constexpr int NCOL = 16;
+    constexpr int BPT = NCOL / NCH;  // boxes per tile
+    constexpr int PF = 8;            // operator reads in flight
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *xs = reinterpret_cast<R *>(smem_raw);   // [Dp4][NCOL] (inputs past Dp zero), then
+    R *out = reinterpret_cast<R *>(smem_raw);  // [NCOL][64] the chunk's rows
+    __shared__ int64_t colofs[NCOL];  // first real of each column's input, -1 past the tile
+    const int4 tl = tiles[tile0 + blockIdx.x];
+    const int o = tl.x, e0 = tl.y, cnt = tl.z;
+    const int Dp = 2 * ncoef(p), Dp4 = (Dp + 3) & ~3;
+    if ((int)threadIdx.x < NCOL) {
+        const int col = threadIdx.x, b = col / NCH, ch = col - b * NCH;
+        int64_t ofs = -1;
+        if (b < cnt) {
+            const int box = list[e0 + b];
+            const int from = L2L ? box_i[6 * box + 3] : box;
+            ofs = 2 * (((int64_t)from * NCH + ch) * ncs);
+        }
+        colofs[col] = ofs;
+    }
+    __syncthreads();
+    {
+        // wave w stages columns 4 w .. 4 w + 3, the loads of a row issued together
+        const int w0 = threadIdx.x >> 6, lane0 = threadIdx.x & 63;
+        const R *Xr = reinterpret_cast<const R *>(X);
+        int64_t ofs[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            ofs[c] = colofs[4 * w0 + c];
+        for (int k = lane0; k < Dp4; k += 64) {
+            R v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                v[c] = Xr[(ofs[c] < 0 ? 0 : ofs[c]) + min(k, Dp - 1)];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                xs[k * NCOL + 4 * w0 + c] = (ofs[c] < 0 || k >= Dp) ? R(0) : v[c];
+        }
+    }
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r0 = blockIdx.y * 64 + 16 * w;  // this wave's first row
+    int ka = 0, kb = 0;                       // its inputs, in steps of 4
+    if (r0 < Dp) {
+        int n0, m0, n1, m1;
+        idx_to_nm(r0 >> 1, n0, m0);
+        idx_to_nm(min(r0 + 15, Dp - 1) >> 1, n1, m1);
+        ka = L2L ? (2 * cidx(n0, 0)) & ~3 : 0;
+        kb = L2L ? Dp4 : min(Dp4, (2 * ncoef(n1) + 3) & ~3);
+    }
+    const int ia = lane & 15, kk = lane >> 4;  // A[i][k] and B[k][j] in lane i (or j) + 16 k
+    const R *A = ops + (int64_t)o * D * D + min(r0 + ia, Dp - 1);  // rows past Dp read row Dp - 1, not stored
+    typename Acc4<R>::type acc = {0, 0, 0, 0};
+    const int nst = (kb - ka) >> 2;
+    if (nst > 0) {
+        R ring[PF];
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
+            ring[j] = A[(int64_t)min(ka + 4 * min(j, nst - 1) + kk, Dp - 1) * D];
+        auto step = [&](int t, R &slot) {
+            const int k = ka + 4 * t;
+            acc = mfma_16x16x4(slot, xs[(k + kk) * NCOL + ia], acc);
+            slot = A[(int64_t)min(ka + 4 * min(t + PF, nst - 1) + kk, Dp - 1) * D];
+        };
+        const int nfull = nst - nst % PF;
+        for (int t0 = 0; t0 < nfull; t0 += PF) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j)
+                step(t0 + j, ring[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
+            if (nfull + j < nst)
+                step(nfull + j, ring[j]);
+    }
+    __syncthreads();  // xs is dead from here on
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = sizeof(R) == 8 ? 4 * v + kk : 4 * kk + v;  // row of element v in this lane
+        out[ia * 64 + 16 * w + i] = acc[v];
+    }
+    __syncthreads();
+    const int r = blockIdx.y * 64 + lane;
+    if (w != 0 || r >= Dp)
+        return;
+    R a[NCOL];
+#pragma unroll
+    for (int q = 0; q < NCOL; ++q)
+        a[q] = out[q * 64 + lane];
+#pragma unroll
+    for (int bq = 0; bq < BPT; ++bq) {
+        if (bq >= cnt)
+            break;
+        const int box = list[e0 + bq];
+        R v[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+            v[ch] = a[bq * NCH + ch];
+        if constexpr (NCH == 4) {
+            const double *cC = box_r + 5 * (int64_t)box, *cP = box_r + 5 * (int64_t)box_i[6 * box + 3];
+            const R d0 = (R)(cC[0] - cP[0]), d1 = (R)(cC[1] - cP[1]), d2 = (R)(cC[2] - cP[2]);
+            const R dv = d0 * v[0] + d1 * v[1] + d2 * v[2];
+            v[3] = L2L ? v[3] - dv : v[3] + dv;
+        }
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            R *dst = reinterpret_cast<R *>(Y + ((int64_t)box * NCH + ch) * ncs) + r;
+            if constexpr (L2L)
+                *dst += v[ch];
+            else
+                *dst = v[ch];
+        }
+    }
 }
 
 template <typename R, int NCH, int RT>
@@ -2430,7 +2434,6 @@ void up_pass(fmmbem_ctx *ctx, int p, hipStream_t st)
         m2m_op = P.m2m64;
     else
         m2m_op = P.m2m32;
-    const size_t op_shm = sizeof(R) * 16 * std::max<size_t>(2 * (size_t)ncoef(p), 3 * 64);
     const int row_chunks = (2 * ncoef(p) + 63) / 64;
     cplx<R> *Z = static_cast<cplx<R> *>(P.Z);
     // children of level l into parents of level l - 1, deepest first; levels
@@ -2440,7 +2443,7 @@ void up_pass(fmmbem_ctx *ctx, int p, hipStream_t st)
         const int q0 = P.par_begin[l - 1], npar = P.par_begin[l] - q0;
         if (ntile == 0 || npar == 0)
             continue;
-        k_octant_apply<R, NCH, false><<<dim3(ntile, row_chunks), 256, op_shm, st>>>(p, ncs, P.op_dim, m2m_op, P.tiles, t0,
+        k_octant_mfma<R, NCH, false><<<dim3(ntile, row_chunks), 256, octant_mfma_shm<R>(p), st>>>(p, ncs, P.op_dim, m2m_op, P.tiles, t0,
                                                                   P.level_list, T.box_i, T.box_r, M, Z);
         FB_HIP(hipGetLastError());
         k_m2m_sum<R, NCH><<<grid_for((int64_t)npar * NCH * ncoef(p), 256), 256, 0, st>>>(
@@ -2523,8 +2526,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
             l2l_op = P.l2l64;
         else
             l2l_op = P.l2l32;
-        const size_t op_shm = sizeof(R) * 16 * std::max<size_t>(2 * (size_t)ncoef(p), 3 * 64);
-        const bool rot = P.rot64_f && p >= ROT_MIN_P;
+            const bool rot = P.rot64_f && p >= ROT_MIN_P;
         const int row_chunks = (2 * ncoef(p) + 63) / 64;
 
         stage_begin(ctx, SO + 1, fs, &ev);
@@ -2604,7 +2606,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 const int t0 = P.tile_begin[l], ntile = P.tile_begin[l + 1] - t0;
                 if (ntile == 0)
                     continue;
-                k_octant_apply<R, NCH, true><<<dim3(ntile, row_chunks), 256, op_shm, fs>>>(
+                k_octant_mfma<R, NCH, true><<<dim3(ntile, row_chunks), 256, octant_mfma_shm<R>(p), fs>>>(
                     p, ncs, P.op_dim, l2l_op, P.tiles, t0, P.level_list, T.box_i, T.box_r, L, L);
                 FB_HIP(hipGetLastError());
             }
