@@ -318,6 +318,7 @@ struct M2LPlan {
     // the first and L2L out of levels above the second carry nothing
     int lmin_src = 0, lmin_tgt = 0;
     int32_t *leaf_rec = nullptr;        // [nleaf][LEAF_REC]: see LEAF_REC
+    int32_t *reduce_order = nullptr;    // [nbox] target boxes of the M2L sum, most pairs first
     void *Z = nullptr;                  // [nbox][nch][ncoef(p_max)] complex FP64: per-child M2M terms
     // stored FP64 pass-1 operators (m2l_stored): per translation, row tiles
     // rt < ops_nrt of 16 rows, column steps kt < ops_k4 of 4 inputs, 64

@@ -362,6 +362,12 @@ __global__ __launch_bounds__(256) void k_p2m_tile(int p, int ncs, const int32_t 
     const int ts = (int)blockDim.x / nm;
     cplx<R> *H = reinterpret_cast<cplx<R> *>(smem_raw);  // [ts][nc]
     R *Q = reinterpret_cast<R *>(smem_raw + sizeof(cplx<R>) * (size_t)ts * nc);  // [ts][NCH]
+    // 1/k for k <= p^2: a thread's column recurrence takes 1/((n - m)(n + m))
+    // with its own m, a read per step that from the constant table would be a
+    // per-lane memory load waited on at every step
+    R *inv = Q + (size_t)ts * NCH;  // [p^2 + 1]
+    for (int k = threadIdx.x; k <= p * p; k += blockDim.x)
+        inv[k] = inv_int<R>(k);
     const int b = leaves[blockIdx.x];
     const int lv = box_i[6 * b], pb = box_i[6 * b + 1], pe = box_i[6 * b + 2];
     const double s = ldexp(side, -(lv + 1));
@@ -409,7 +415,7 @@ __global__ __launch_bounds__(256) void k_p2m_tile(int p, int ncs, const int32_t 
             // the diagonal R_m^m, then the column R_n^m, n > m
             R cr = 1, ci = 0;
             for (int n = 1; n <= m; ++n) {
-                const R al = -inv_int<R>(2 * n);
+                const R al = -inv[2 * n];
                 const R A = al * x, B = al * y;
                 const R nr = A * cr - B * ci, ni = A * ci + B * cr;
                 cr = nr;
@@ -418,7 +424,7 @@ __global__ __launch_bounds__(256) void k_p2m_tile(int p, int ncs, const int32_t 
             h[cidx(m, m)] = cplx<R>{cr, -ci};
             R pr = 0, pi = 0;
             for (int n = m + 1; n <= p; ++n) {
-                const R f = inv_int<R>((n - m) * (n + m));
+                const R f = inv[(n - m) * (n + m)];
                 const R A = R(2 * n - 1) * f * z, G = n >= m + 2 ? f * r2 : R(0);
                 const R nr = A * cr - G * pr, ni = A * ci - G * pi;
                 pr = cr;
@@ -456,7 +462,7 @@ __global__ __launch_bounds__(256) void k_p2m_tile(int p, int ncs, const int32_t 
 template <typename R, int NCH> size_t p2m_tile_shm(int p)
 {
     const int ts = 256 / (p + 1);
-    return sizeof(cplx<R>) * (size_t)ts * ncoef(p) + sizeof(R) * (size_t)ts * NCH;
+    return sizeof(cplx<R>) * (size_t)ts * ncoef(p) + sizeof(R) * ((size_t)ts * NCH + (size_t)p * p + 1);
 }
 
 // P2M of dipole sources (the double layer): a moment d = w x n at y has
@@ -1573,12 +1579,13 @@ __global__ __launch_bounds__(256) void k_m2l_valu(int p, int ncs, int q_tab, con
 // after k_m2l_mfma) the fourth channel of each pair also changes centre from
 // c_S to c_T: Y_3 + (c_S - c_T) . (Y_0, Y_1, Y_2).
 template <typename R, int NCH, bool FIXC>
-__global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_t *__restrict__ ptr,
+__global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_t *__restrict__ order,
+                                                    const int32_t *__restrict__ ptr,
                                                     const int32_t *__restrict__ src, const double *__restrict__ box_r,
                                                     const cplx<R> *__restrict__ Y, cplx<R> *__restrict__ L)
 {
     __shared__ cplx<R> red[256];
-    const int T = blockIdx.x;
+    const int T = order[blockIdx.x];  // boxes with the most pairs first
     const int nc = ncoef(p), no = NCH * nc;
     const int e0 = ptr[T], e1 = ptr[T + 1];
     const double *cT = box_r + 5 * (int64_t)T;
@@ -2578,9 +2585,9 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         {
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
             if (NCH == 4 && !rot)  // the rotation M2L moves the fourth channel's centre itself
-                k_m2l_reduce<R, NCH, true><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
+                k_m2l_reduce<R, NCH, true><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, P.reduce_order, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             else
-                k_m2l_reduce<R, NCH, false><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
+                k_m2l_reduce<R, NCH, false><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, P.reduce_order, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             FB_HIP(hipGetLastError());
         }
         // one channel at the low orders: L2L down each leaf's chain of

@@ -300,6 +300,19 @@ void build_level_plan(fmmbem_ctx *ctx, hipStream_t st)
             P.lmin_tgt = std::min(P.lmin_tgt, hb[6 * b]);
     for (int64_t i = 0; i < T.n_m2l; ++i)
         P.lmin_src = std::min(P.lmin_src, hb[6 * srcs[i]]);
+    // the M2L sum's order of target boxes: most pairs first, so that the
+    // longest blocks do not end the pass (stable: box order among equals)
+    {
+        std::vector<int32_t> order(T.nbox);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
+        P.reduce_order = ctx->arena.alloc<int32_t>(std::max<size_t>(order.size(), 1));
+        if (!order.empty())
+            FB_HIP(hipMemcpyAsync(P.reduce_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice,
+                                  st));
+        FB_HIP(hipStreamSynchronize(st));  // order is a host vector
+    }
     // per leaf, for the fused downward pass: target range, level, the chain of
     // the leaf and its ancestors down to the coarsest M2L target level, and
     // the octant of each chain box in its parent (3 bits each)
