@@ -68,6 +68,33 @@ __device__ inline double sub_combination(double x, const double *__restrict__ V,
     return x;
 }
 
+// sub_combination of two rows at once (row i1 only where has1; its reads
+// then repeat row i0's), their loads issued together: twice the reads in
+// flight per thread, each row's arithmetic in the same order as alone
+__device__ inline void sub_combination2(double &x0, double &x1, const double *__restrict__ V, int64_t ldv, int nv,
+                                        int64_t i0, int64_t i1, bool has1, const double *__restrict__ c)
+{
+    const int64_t j1 = has1 ? i1 : i0;
+    int j = 0;
+    for (; j + AXPY_UNROLL <= nv; j += AXPY_UNROLL) {
+        double v0[AXPY_UNROLL], v1[AXPY_UNROLL];
+#pragma unroll
+        for (int u = 0; u < AXPY_UNROLL; ++u) {
+            v0[u] = V[(int64_t)(j + u) * ldv + i0];
+            v1[u] = V[(int64_t)(j + u) * ldv + j1];
+        }
+#pragma unroll
+        for (int u = 0; u < AXPY_UNROLL; ++u) {
+            x0 -= c[j + u] * v0[u];
+            x1 -= c[j + u] * v1[u];
+        }
+    }
+    for (; j < nv; ++j) {
+        x0 -= c[j] * V[(int64_t)j * ldv + i0];
+        x1 -= c[j] * V[(int64_t)j * ldv + j1];
+    }
+}
+
 // Classical Gram-Schmidt dots: block (b, g) takes row block b and the vectors
 // j = g CGS_JG .. + CGS_JG - 1 and writes part[j][b] = V_j . w over its rows.
 constexpr int CGS_JG = 8;
@@ -154,21 +181,32 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_sub_dots(int64_t n, int rpt, cons
     for (int q = 0; q < CGS_JG * NVC; ++q)
         s[q] = 0.0;
     const int64_t base = (int64_t)blockIdx.x * rpt * DOT_BLOCK + threadIdx.x;
-    for (int k = 0; k < rpt; ++k) {
-        const int64_t i = base + (int64_t)k * DOT_BLOCK;
-        if (i >= n)
+    for (int k = 0; k < rpt; k += 2) {  // rows k and k + 1 together
+        const int64_t i0 = base + (int64_t)k * DOT_BLOCK, i1 = i0 + DOT_BLOCK;
+        if (i0 >= n)
             break;
-        const double x = sub_combination(w[i], V, ldv, nv, i, hs);
-        w[i] = x;
+        const bool has1 = k + 1 < rpt && i1 < n;
+        double x0 = w[i0], x1 = has1 ? w[i1] : 0.0;
+        sub_combination2(x0, x1, V, ldv, nv, i0, i1, has1, hs);
+        w[i0] = x0;
+        if (has1)
+            w[i1] = x1;
+        else
+            x1 = 0.0;
+        const int64_t j1 = has1 ? i1 : i0;
 #pragma unroll
         for (int c = 0; c < NVC; ++c) {
-            double v[CGS_JG];
+            double v0[CGS_JG], v1[CGS_JG];
 #pragma unroll
-            for (int u = 0; u < CGS_JG; ++u)  // clamped, unguarded reads; the extra ones zeroed
-                v[u] = V[(int64_t)min(CGS_JG * c + u, nv - 1) * ldv + i];
+            for (int u = 0; u < CGS_JG; ++u) {  // clamped, unguarded reads; the extra ones zeroed
+                v0[u] = V[(int64_t)min(CGS_JG * c + u, nv - 1) * ldv + i0];
+                v1[u] = V[(int64_t)min(CGS_JG * c + u, nv - 1) * ldv + j1];
+            }
 #pragma unroll
-            for (int u = 0; u < CGS_JG; ++u)
-                s[CGS_JG * c + u] += (CGS_JG * c + u < nv ? v[u] : 0.0) * x;
+            for (int u = 0; u < CGS_JG; ++u) {
+                s[CGS_JG * c + u] += (CGS_JG * c + u < nv ? v0[u] : 0.0) * x0;
+                s[CGS_JG * c + u] += (CGS_JG * c + u < nv ? v1[u] : 0.0) * x1;
+            }
         }
     }
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -219,13 +257,19 @@ __global__ __launch_bounds__(DOT_BLOCK) void k_update_norm(int64_t n, int rpt, c
         }
     double s = 0.0;
     const int64_t base = (int64_t)b * rpt * DOT_BLOCK + threadIdx.x;
-    for (int k = 0; k < rpt; ++k) {
-        const int64_t i = base + (int64_t)k * DOT_BLOCK;
-        if (i >= n)
+    for (int k = 0; k < rpt; k += 2) {  // rows k and k + 1 together
+        const int64_t i0 = base + (int64_t)k * DOT_BLOCK, i1 = i0 + DOT_BLOCK;
+        if (i0 >= n)
             break;
-        const double x = sub_combination(w[i], V, ldv, nv, i, hs + nv);
-        w[i] = x;
-        s += x * x;
+        const bool has1 = k + 1 < rpt && i1 < n;
+        double x0 = w[i0], x1 = has1 ? w[i1] : 0.0;
+        sub_combination2(x0, x1, V, ldv, nv, i0, i1, has1, hs + nv);
+        w[i0] = x0;
+        s += x0 * x0;
+        if (has1) {
+            w[i1] = x1;
+            s += x1 * x1;
+        }
     }
     const double t = block_total(s, sh);
     if (threadIdx.x == 0)
