@@ -8,7 +8,7 @@ Gauss points, 393216 unknowns.  Stokes single layer, mu = 1, boundary data
 u = (1, 0, 0) at every centroid; GMRES(50) to a relative residual of 1e-6.
 A step is one relaxed solve: p from 16 down to p_min = 4 by the residual
 (Eq. 17/19), FP32 P2P/expansions once eps_k >= 1e-5, FP64 Arnoldi, Givens and
-true residuals, N_CRIT 128, M2L by rotation from p = 8 (the direct product
+true residuals, N_CRIT 128, M2L by rotation from p = 7 (the direct product
 below); `value` = such solves per second with the inputs resident in device
 memory.  Beside it: the fixed p = 16 FP64 solve (N_CRIT
 256, the fastest for fixed p), p50 and max over the samples, the event-timed
@@ -51,9 +51,9 @@ TOL = 1e-6
 STAGE_KERNEL = {
     "stokes": {"p2p_fp32": "k_p2p<float, 1>", "p2p_fp64": "k_p2p<double, 1>",
                "m2l_fp32": "k_m2l_mfma<float, 4, 1|4>", "m2l_fp64": "k_m2l_stored<4>|k_m2l_valu<double, 4, 2>"},
-    # M2L by rotation from p = 8 (the direct kernels below it)
+    # M2L by rotation from p = 7 (the direct kernels below it)
     "stokes_rot": {"p2p_fp32": "k_p2p<float, 1>", "p2p_fp64": "k_p2p<double, 1>",
-                   "m2l_fp32": "k_m2l_rot<float, 4, 2|4, 4> (p >= 8), k_m2l_mfma<float, 4, 1|4> (p < 8)",
+                   "m2l_fp32": "k_m2l_rot<float, 4, 2|4, 4> (p >= 7), k_m2l_mfma<float, 4, 1> (p < 7)",
                    "m2l_fp64": "k_m2l_rot<double, 4, 2, 4>"},
     "laplace": {"p2p_fp32": "k_p2p<float, 0>", "p2p_fp64": "k_p2p<double, 0>",
                 "m2l_fp32": "k_m2l_mfma<float, 1, 1|4>", "m2l_fp64": "k_m2l_valu<double, 1, 8>"},
@@ -353,7 +353,7 @@ def cpu_baseline(args, fb, syn, head, sphere_mesh, sphere_x):
 def laplace_sphere_32768(args, fb, syn, torch, dev):
     """Laplace single layer, 32768-panel sphere, Y_l^m data (l = 0..4):
     relaxed mixed (12 -> 3), relaxed FP64 and fixed p = 12 FP64 solves with
-    the stored near field and the rotation M2L (from p = 8); per-order mat-vec
+    the stored near field and the rotation M2L (from p = 7); per-order mat-vec
     times; the rooflines of the FP64 M2L and of the near-field product."""
     m = syn.sphere(6)
     nt = m.n_panels
@@ -629,7 +629,7 @@ def main():
     ap.add_argument("--fixed-reps", type=int, default=5, help="fixed-p solves of the 64-cell case (>= 5)")
     ap.add_argument("--m2l", choices=tuple(M2L_MODES), default="rot",
                     help="M2L of the 64-cell case: FP64 operators stored at build, generated per mat-vec, "
-                         "or by rotation from p = 8")
+                         "or by rotation from p = 7")
     ap.add_argument("--cmp-reps", type=int, default=20, help="solves per schedule of the secondary workloads")
     ap.add_argument("--matvec-reps", type=int, default=100, help="event-timed mat-vecs per order")
     ap.add_argument("--cpu-rows", type=int, default=4096, help="rows of the oracle's sampled mat-vec")

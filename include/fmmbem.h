@@ -107,12 +107,12 @@ typedef struct {
      * up to 16 rows (a sphere of 32768 panels at N_CRIT 64, p_max = 12: 2541
      * translations, 718 MB); see fmmbem_stats.n_translations and
      * m2l_op_bytes.  0 (default): generated on the fly.
-     * 2: M2L by rotation at p >= 8 in both precisions: per translation
+     * 2: M2L by rotation at p >= 7 in both precisions: per translation
      * direction, the real forms of the rotation taking the direction to +z
      * and back (every degree <= p_max, FP64 and FP32) are built at build and
      * stored; each pair's multipole expansion is rotated, translated along
      * the axis, and its local expansion rotated back, O(p^3) per pair
-     * instead of O(p^4).  Below p = 8 as with 0.  Memory: 24 T bytes per
+     * instead of O(p^4).  Below p = 7 as with 0.  Memory: 24 T bytes per
      * direction, T = sum over n <= p_max of 64 ceil(2 (n + 1) / 16)
      * ceil(2 (n + 1) / 4) (p_max = 16: 9664 values, 232 KB). */
     int32_t m2l_stored;

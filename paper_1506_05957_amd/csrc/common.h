@@ -345,7 +345,7 @@ struct M2LPlan {
     float *rot32_f = nullptr, *rot32_b = nullptr;
 };
 // orders from which the rotation M2L replaces the direct one (m2l_stored = 2)
-constexpr int ROT_MIN_P = 8;
+constexpr int ROT_MIN_P = 7;
 // orders up to which L2P (where the downward pass is not fused) evaluates the
 // far field without waiting for the near field, and a combine joins the two
 constexpr int L2P_FAR_MAX_P = 7;

@@ -86,7 +86,7 @@ def test_solve_parity_tight(orc, case, rule, mixed):
 @pytest.mark.parametrize("case", ["laplace_sphere_ylm", "stokes_sphere_u", "stokes_cells_u"])
 @pytest.mark.parametrize("rule,mixed", [(0, 0), (2, 1)])
 def test_solve_parity_rotation_m2l(orc, case, rule, mixed):
-    """M2L by rotation from p = 8 (m2l_stored = 2, the bench's configuration):
+    """M2L by rotation from p = 7 (m2l_stored = 2, the bench's configuration):
     the same parity bar against the oracle, fixed FP64 and relaxed mixed."""
     from paper_1506_05957_amd import fmmbem as fb
     kernel, mesh_name, rhs, p_init, p_min = CASES[case]

@@ -45,7 +45,7 @@ def matvec(fb, ctx, p, prec, x):
 def test_laplace_sphere_32768(orc, near_stored, m2l_stored):
     """The 32768-panel sphere, five Y_l^m right-hand sides, relaxed mixed
     solves at tol 1e-6; (1, 2) is the benchmark's configuration (near field
-    stored at build, M2L by rotation from p = 8); (1, 1) stores the direct FP64
+    stored at build, M2L by rotation from p = 7); (1, 1) stores the direct FP64
     M2L operators instead."""
     from paper_1506_05957_amd import fmmbem as fb
     announce(f"full size: Laplace sphere 32768, Y_l^m, relaxed 12 -> 3 mixed, near_stored={near_stored} "
