@@ -97,6 +97,8 @@ COUNTED_SOURCES = {
                                   ("rotations.cpp", "// Rotation operators", "}  // namespace fmmbem")],
     "k_m2l_rot<float, 4, 2, 4>": [("fmm.hip", "// M2L by rotation: the translation", "// LDS of k_m2l_rot"),
                                   ("rotations.cpp", "// Rotation operators", "}  // namespace fmmbem")],
+    "k_m2l_rot<double, 1, 2, 4>": [("fmm.hip", "// M2L by rotation: the translation", "// LDS of k_m2l_rot"),
+                                   ("rotations.cpp", "// Rotation operators", "}  // namespace fmmbem")],
 }
 
 
@@ -116,8 +118,8 @@ def source_sha1(kernel: str) -> str:
 def kernel_traffic(kernel: str, workload: str):
     """HBM bytes per launch of a kernel on a workload from the committed
     rocprofv3 counter records (FETCH_SIZE and WRITE_SIZE scaled by a plain
-    copy), or None when there is no record or the kernel's source changed
-    since the counters were taken."""
+    copy), or None when there is no record whose kernel source is the
+    current one (records taken before a change of the source are skipped)."""
     import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*hbm_counters*.md"))):
         try:
@@ -131,9 +133,9 @@ def kernel_traffic(kernel: str, workload: str):
                 continue
             try:
                 if kernel not in COUNTED_SOURCES or rec.get("source_sha1") != source_sha1(kernel):
-                    return None
+                    continue
             except (OSError, ValueError, KeyError):
-                return None
+                continue
             return float(rec["traffic_bytes_per_launch"])
     return None
 
@@ -350,6 +352,27 @@ def cpu_baseline(args, fb, syn, head, sphere_mesh, sphere_x):
 
 
 # ------------------------------------------------------------------ secondary sections
+def laplace_timed(args, fb, syn, torch, dev):
+    """The relaxed mixed solves of the 32768-panel Laplace sphere alone (the
+    configuration of laplace_sphere_32768, its five right-hand sides in turn,
+    `--steps` rounds after `--warmup`), for profiling its kernels."""
+    m = syn.sphere(6)
+    rhs = [torch.tensor(syn.ylm_rhs(m, l, mm), device=dev) for l, mm in syn.ylm_orders(0)]
+    ctx = fb.fmmbem_build(m.xyz, m.tri, fb.LAPLACE, fb.params(ncrit=64, p_max=12, near_stored=1, m2l_stored=2))
+    x = torch.empty(m.n_panels, dtype=torch.float64, device=dev)
+    s = fb.schedule(fb.LAPLACE, rule=fb.RELAX_BF, p_init=12, p_min=3, mixed=1)
+    for _ in range(args.warmup):
+        for b in rhs:
+            fb.fmmbem_solve_ctx(ctx, b, TOL, s, x)
+    ts = []
+    for _ in range(args.steps):
+        for b in rhs:
+            t, r = timed_solves(fb, torch, ctx, b, x, s, 1)
+            ts += t
+    fb.fmmbem_destroy(ctx)
+    return {"workload": "laplace_sl_sphere32768_ylm_tol1e-6", "relaxed_mixed_solve_ms": summary_ms(ts)}
+
+
 def laplace_sphere_32768(args, fb, syn, torch, dev):
     """Laplace single layer, 32768-panel sphere, Y_l^m data (l = 0..4):
     relaxed mixed (12 -> 3), relaxed FP64 and fixed p = 12 FP64 solves with
@@ -638,6 +661,8 @@ def main():
     ap.add_argument("--timed-only", action="store_true",
                     help="build, warm-up and the timed region only (for profiling the timed kernels)")
     ap.add_argument("--no-extra", action="store_true", help="headline only: no secondary sections")
+    ap.add_argument("--laplace-timed-only", action="store_true",
+                    help="only the relaxed solves of the 32768-panel Laplace sphere (for profiling them)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-calib", type=int, default=48)
@@ -668,6 +693,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.ncrit_sweep:
         print(json.dumps({"ncrit_sweep": ncrit_sweep(args, fb, syn, torch, dev)}))
+        return
+    if args.laplace_timed_only:
+        print(json.dumps(laplace_timed(args, fb, syn, torch, dev)))
         return
 
     head = cells_headline(args, fb, syn, torch, dev)
