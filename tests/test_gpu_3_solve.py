@@ -152,6 +152,39 @@ def test_solve_restarts_with_prefetch(orc):
     fb.fmmbem_destroy(ctx)
 
 
+def test_solve_restarts_with_prefetch_stokes(orc):
+    """GMRES(6), relaxed mixed, on Stokes cells with the near field on the fly
+    and the rotation M2L: the FP32 mat-vecs at p <= 7 run P2P on the main
+    stream right after the charges and the far chain (with its prefetched
+    upward pass) on the side stream, the others the other way round, and the
+    restarts switch between FP64 true residuals and such steps, so prefetched
+    work is used, redone at another order, or dropped across the two stream
+    orders.  At tol 1e-6 (the single layer's near null space, the normals,
+    stalls GMRES(6) near 1e-6, so a tighter tol would not end): the same bar
+    against the oracle as a fixed FP64 solve at that tol, and the same bits on
+    a second solve."""
+    from paper_1506_05957_amd import fmmbem as fb
+    announce("restarted relaxed solve, cells8x512 Stokes, GMRES(6), near field on the fly, rotation M2L")
+    m = MESHES["cells8x512"]()
+    b = np.tile([1.0, 0.0, 0.0], m.n_panels)
+    xo = orc.solve(1, m.xyz, m.tri, b, tol=1e-11)[0]
+    ctx = fb.fmmbem_build(m.xyz, m.tri, 1, fb.params(ncrit=64, p_max=16, m2l_stored=2))
+    xf, rf = solve(fb, ctx, b, 1e-6, fb.schedule(1, rule=0, mixed=0, p_init=16, p_min=16))
+    sched = fb.schedule(1, rule=fb.RELAX_BF, p_init=16, p_min=4, mixed=1, restart=6)
+    x, rep = solve(fb, ctx, b, 1e-6, sched)
+    ef = compare(orc, 1, "cells8x512", m, xf, xo)
+    err = compare(orc, 1, "cells8x512", m, x, xo)
+    announce(describe(rep, x, xo) + f" cmp={err:.1e} fixed={ef:.1e} restarts={rep['restarts']}")
+    assert rf["converged"] and rf["rel_res_true"] <= 1e-6
+    assert rep["converged"] and rep["restarts"] >= 2 and rep["rel_res_true"] <= 1e-6
+    assert err <= 2 * ef + 1e-5
+    low = [int(p) for p, q in zip(rep["p_hist"], rep["prec_hist"]) if int(q) == fb.FP32 and int(p) <= 7]
+    assert len(low) >= 2  # the swapped stream order ran
+    x2, rep2 = solve(fb, ctx, b, 1e-6, sched)
+    assert np.array_equal(x, x2) and rep2["iterations"] == rep["iterations"]
+    fb.fmmbem_destroy(ctx)
+
+
 @pytest.mark.parametrize("case", ["laplace_sphere_one", "stokes_sphere_u"])
 def test_solve_bench_tolerance(orc, case):
     from paper_1506_05957_amd import fmmbem as fb
