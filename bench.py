@@ -8,10 +8,10 @@ Gauss points, 393216 unknowns.  Stokes single layer, mu = 1, boundary data
 u = (1, 0, 0) at every centroid; GMRES(50) to a relative residual of 1e-6.
 A step is one relaxed solve: p from 16 down to p_min = 4 by the residual
 (Eq. 17/19), FP32 P2P/expansions once eps_k >= 1e-5, FP64 Arnoldi, Givens and
-true residuals, N_CRIT 128, M2L by rotation from p = 7 (the direct product
+true residuals, N_CRIT 112, M2L by rotation from p = 7 (the direct product
 below); `value` = such solves per second with the inputs resident in device
 memory.  Beside it: the fixed p = 16 FP64 solve (N_CRIT
-256, the fastest for fixed p), p50 and max over the samples, the event-timed
+192, the fastest for fixed p), p50 and max over the samples, the event-timed
 roofline of the P2P and M2L kernels inside the timed solves, and the oracle's
 CPU rate from a bounded row sample.
 
@@ -181,8 +181,8 @@ def rep_summary(reps):
 
 # ------------------------------------------------------------------ headline
 def cells_headline(args, fb, syn, torch, dev):
-    """The 64-cell Stokes case: relaxed mixed (N_CRIT 128) timed; fixed p = 16
-    FP64 (N_CRIT 256) beside it."""
+    """The 64-cell Stokes case: relaxed mixed (N_CRIT 112) timed; fixed p = 16
+    FP64 (N_CRIT 192) beside it."""
     m = syn.rbc_scene(64, 4, 0)
     nt = m.n_panels
     u = torch.tensor(np.tile([1.0, 0.0, 0.0], nt), device=dev)
@@ -229,7 +229,8 @@ def cells_headline(args, fb, syn, torch, dev):
                        "prec_history": [int(v) for v in last["prec_hist"]]},
            "stats": stats, "build_s": t_build, "mesh": m, "u": u, "x_relaxed": x_relaxed}
 
-    workload = "stokes_64rbc"
+    # counter records hold per-launch bytes of one tree: the leaf size is part of the workload
+    workload = f"stokes_64rbc_ncrit{args.ncrit_relaxed}"
     names = STAGE_KERNEL["stokes_rot" if args.m2l == "rot" else "stokes"]
     rl = {}
     for s in stages:
@@ -248,7 +249,7 @@ def cells_headline(args, fb, syn, torch, dev):
         fb.fmmbem_destroy(ctx)
         return out
 
-    # relaxed on the fixed schedule's tree (N_CRIT 256), for a same-tree factor
+    # relaxed on the fixed schedule's tree (N_CRIT 192), for a same-tree factor
     ctx2 = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=args.ncrit_fixed, p_max=16,
                                                               m2l_stored=M2L_MODES[args.m2l]))
     fb.fmmbem_solve_ctx(ctx2, u, TOL, fixed, x)  # warm-up
@@ -609,7 +610,7 @@ def serving(args, fb, syn):
 def ncrit_sweep(args, fb, syn, torch, dev):
     """Solve time against N_CRIT for both schedules on the Laplace 32768-panel
     sphere (on-the-fly near field) and the 64-cell Stokes case (with the
-    headline's M2L, --m2l)."""
+    headline's M2L, --m2l), and for the cells the mat-vec time per order."""
     out = {"laplace_sphere32768": {}, "stokes_64rbc": {}}
     m = syn.sphere(6)
     b = torch.tensor(syn.ylm_rhs(m, 3, 0), device=dev)
@@ -628,7 +629,7 @@ def ncrit_sweep(args, fb, syn, torch, dev):
     m = syn.rbc_scene(64, 4, 0)
     u = torch.tensor(np.tile([1.0, 0.0, 0.0], m.n_panels), device=dev)
     x = torch.empty_like(u)
-    for nc in (48, 64, 96, 128, 192, 256, 384):
+    for nc in (48, 64, 96, 112, 128, 160, 192, 256, 384):
         ctx = fb.fmmbem_build(m.xyz, m.tri, fb.STOKES, fb.params(ncrit=nc, p_max=16, m2l_stored=M2L_MODES[args.m2l]))
         row = {}
         for name, s in (("relaxed_mixed", fb.schedule(fb.STOKES, p_init=16, p_min=4)),
@@ -636,6 +637,9 @@ def ncrit_sweep(args, fb, syn, torch, dev):
             fb.fmmbem_solve_ctx(ctx, u, TOL, s, x)
             ts, reps = timed_solves(fb, torch, ctx, u, x, s, 2)
             row[name] = summary_ms(ts)["p50"]
+        # per-order mat-vec times: what a second cut of the tree for some orders would trade
+        mv = matvec_times(fb, torch, ctx, u, [(p, fb.FP32) for p in (4, 5, 6, 7, 10, 14)] + [(16, fb.FP64)], 20)
+        row["matvec_p50_ms"] = {k: v["p50"] for k, v in mv.items()}
         out["stokes_64rbc"][nc] = row
         print(f"bench: sweep 64 cells N_CRIT {nc}: {row}", file=sys.stderr, flush=True)
         fb.fmmbem_destroy(ctx)
@@ -647,8 +651,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10, help="timed relaxed solves of the 64-cell case")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--ncrit-relaxed", type=int, default=128)
-    ap.add_argument("--ncrit-fixed", type=int, default=256)
+    ap.add_argument("--ncrit-relaxed", type=int, default=112)
+    ap.add_argument("--ncrit-fixed", type=int, default=192)
     ap.add_argument("--fixed-reps", type=int, default=5, help="fixed-p solves of the 64-cell case (>= 5)")
     ap.add_argument("--m2l", choices=tuple(M2L_MODES), default="rot",
                     help="M2L of the 64-cell case: FP64 operators stored at build, generated per mat-vec, "

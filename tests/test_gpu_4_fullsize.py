@@ -104,7 +104,7 @@ def test_stokes_sphere_8192_drag(orc):
     fb.fmmbem_destroy(ctx)
 
 
-@pytest.mark.parametrize("ncrit,m2l_stored", [(128, 2), (256, 2), (128, 0)])
+@pytest.mark.parametrize("ncrit,m2l_stored", [(112, 2), (192, 2), (112, 0)])
 def test_stokes_64_cells(orc, ncrit, m2l_stored):
     """64 red blood cells x 2048 panels (131072 panels, 393216 unknowns), the
     relaxed mixed schedule (16 -> 4, the benchmark's headline) and fixed
