@@ -2793,10 +2793,20 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
     ctx->spec_up_p = -1;
     ctx->spec_near = false;
     ctx->spec_swap = false;
-    if (!have_charges)
+    bool up_here = false;
+    if (!have_charges) {
         charges_dispatch(ctx, prec, x, st);  // (joins the side stream first if it still runs)
-    else
+        // the upward pass before the near field's fork, as the prefetch
+        // orders them: the host's wait on the still pending fork event then
+        // no longer delays its launches (the GPU is full either way while
+        // both run, so this gains only that delay)
+        if (!swap && ctx->tree.n_m2l > 0) {
+            up_dispatch(ctx, p, prec, st);
+            up_here = true;
+        }
+    } else {
         (void)hipEventQuery(ctx->ev_fork);  // refresh its state: usually complete by now
+    }
     if (!have_near)
         near_dispatch(ctx, prec, swap ? st : ctx->side, x);
     // stored near field: its blocks already hold the corrections of their pairs
@@ -2806,7 +2816,7 @@ void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hi
                                                     : 1.0 / (4.0 * M_PI);
     const CombineArgs ca{ctx->tree.perm, C.ptr, C.col_orig, C.val, x, ctx->y_near, pref, y,
                          C.nnz > 0 ? ctx->y_corr : nullptr};
-    far_dispatch(ctx, p, prec, ca, st, have_up, swap);  // ends with the join and the combine on st
+    far_dispatch(ctx, p, prec, ca, st, have_up || up_here, swap);  // ends with the join and the combine on st
     ctx->side_pending = false;
     ctx->corr_on_near = false;
 }
