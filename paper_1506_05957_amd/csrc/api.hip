@@ -194,6 +194,7 @@ int fmmbem_build(const fmmbem_mesh *mesh, int kernel, const fmmbem_params *param
         build_translations(ctx, st);
         if (prm.near_stored)
             build_near_matrix(ctx, st);
+        correction_fp32(ctx, prm.near_stored ? ctx->nearm.rest : ctx->corr, st);
         if (prm.m2l_stored == 1)
             build_m2l_operators(ctx, st);
         const int ncs = ncoef(prm.p_max);

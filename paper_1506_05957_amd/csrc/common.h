@@ -270,6 +270,7 @@ struct Correction {
     int32_t *col = nullptr;  // [nnz] sorted source panel
     int32_t *col_orig = nullptr;  // [nnz] the same panel in the caller's order
     double *val = nullptr;   // [nnz] (Laplace) or [nnz][9] (Stokes), without the kernel prefactor
+    float *val32 = nullptr;  // the same values rounded to FP32, read by the FP32 mat-vecs
 };
 
 struct Timing {
@@ -509,6 +510,8 @@ struct GmresState {
 
 void build_geometry_and_tree(fmmbem_ctx *ctx, const fmmbem_mesh *mesh, hipStream_t st);
 void build_correction(fmmbem_ctx *ctx, hipStream_t st);
+// C.val32 from C.val (the correction that the mat-vecs read)
+void correction_fp32(fmmbem_ctx *ctx, Correction &C, hipStream_t st);
 void build_translations(fmmbem_ctx *ctx, hipStream_t st);
 void run_matvec(fmmbem_ctx *ctx, int p, int prec, const double *x, double *y, hipStream_t st);
 // launch the charges of a mat-vec on x at precision prec ahead of time (the

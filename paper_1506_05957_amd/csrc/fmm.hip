@@ -1701,13 +1701,14 @@ __device__ inline void combine_target(const CombineArgs &A, int64_t i, const dou
 
 // The correction's product yc = S x by sorted target (S: the near-singular
 // and self corrections, CSR by sorted target, columns in caller order; 1 or
-// 3 x 3 values per entry).  Sixteen lanes per row take its entries in turn;
+// 3 x 3 values per entry, FP64 or their FP32 copy, the products summed in
+// FP64).  Sixteen lanes per row take its entries in turn;
 // the lanes' sums are joined by a fixed butterfly, so the result does not
 // depend on the launch.  Launched where the far-field stream would otherwise
 // wait for the near field, so that the combine reads one value per component.
-template <int NQ>
+template <int NQ, typename V>
 __global__ __launch_bounds__(256) void k_corr_spmv(int64_t nt, const int32_t *__restrict__ ptr,
-                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                   const int32_t *__restrict__ col, const V *__restrict__ val,
                                                    const double *__restrict__ x, double *__restrict__ yc)
 {
     const int64_t i = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
@@ -1721,13 +1722,13 @@ __global__ __launch_bounds__(256) void k_corr_spmv(int64_t nt, const int32_t *__
         for (int e = ptr[i] + l; e < c1; e += 16) {
             const int64_t jo = col[e];
             if constexpr (NQ == 1) {
-                a[0] += val[e] * x[jo];
+                a[0] += (double)val[e] * x[jo];
             } else {
-                const double *v = val + 9 * (int64_t)e;
+                const V *v = val + 9 * (int64_t)e;
                 const double t0 = x[3 * jo], t1 = x[3 * jo + 1], t2 = x[3 * jo + 2];
-                a[0] += (v[0] * t0 + v[1] * t1) + v[2] * t2;
-                a[1] += (v[3] * t0 + v[4] * t1) + v[5] * t2;
-                a[2] += (v[6] * t0 + v[7] * t1) + v[8] * t2;
+                a[0] += ((double)v[0] * t0 + (double)v[1] * t1) + (double)v[2] * t2;
+                a[1] += ((double)v[3] * t0 + (double)v[4] * t1) + (double)v[5] * t2;
+                a[2] += ((double)v[6] * t0 + (double)v[7] * t1) + (double)v[8] * t2;
             }
         }
     }
@@ -1741,6 +1742,11 @@ __global__ __launch_bounds__(256) void k_corr_spmv(int64_t nt, const int32_t *__
         for (int q = 0; q < NQ; ++q)
             yc[NQ * i + q] = a[q];
 }
+
+// the correction's values that a mat-vec of precision R reads
+template <typename R> const R *corr_values(const Correction &C);
+template <> const double *corr_values<double>(const Correction &C) { return C.val; }
+template <> const float *corr_values<float>(const Correction &C) { return C.val32; }
 
 // combine_target for one channel with the target's inputs already read:
 // o = perm[i], its near field yn, its correction range [c0, c1) and (double
@@ -2379,7 +2385,7 @@ void launch_near(fmmbem_ctx *ctx, hipStream_t ns, const double *x)
     ctx->corr_on_near = on_side && C.nnz > 0;
     if (ctx->corr_on_near) {
         constexpr int NQ = STOKES ? 3 : 1;
-        k_corr_spmv<NQ><<<grid_for(nt, 16), 256, 0, ns>>>(nt, C.ptr, C.col_orig, C.val, x, ctx->y_corr);
+        k_corr_spmv<NQ><<<grid_for(nt, 16), 256, 0, ns>>>(nt, C.ptr, C.col_orig, corr_values<R>(C), x, ctx->y_corr);
         FB_HIP(hipGetLastError());
     }
     if (on_side) {
@@ -2466,13 +2472,15 @@ void up_pass(fmmbem_ctx *ctx, int p, hipStream_t st)
 // which combines far and near field into y.  Without a far field: y_far = 0,
 // join and combine.
 // the correction's product into ctx->y_corr on st (see k_corr_spmv)
-template <int KIND>
+template <typename R, int KIND>
 void corr_spmv(fmmbem_ctx *ctx, const CombineArgs &ca, hipStream_t st)
 {
     if (!ca.ycorr || ctx->corr_on_near)  // none, or already behind the near field
         return;
     constexpr int NQ = KIND == FMMBEM_STOKES_SL ? 3 : 1;
-    k_corr_spmv<NQ><<<grid_for(ctx->nt, 16), 256, 0, st>>>(ctx->nt, ca.cptr, ca.ccol, ca.cval, ca.x, ctx->y_corr);
+    const Correction &C = ctx->prm.near_stored ? ctx->nearm.rest : ctx->corr;
+    k_corr_spmv<NQ><<<grid_for(ctx->nt, 16), 256, 0, st>>>(ctx->nt, ca.cptr, ca.ccol, corr_values<R>(C), ca.x,
+                                                           ctx->y_corr);
     FB_HIP(hipGetLastError());
 }
 
@@ -2533,7 +2541,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
             l2l_op = P.l2l64;
         else
             l2l_op = P.l2l32;
-            const bool rot = P.rot64_f && p >= ROT_MIN_P;
+        const bool rot = P.rot64_f && p >= ROT_MIN_P;
         const int row_chunks = (2 * ncoef(p) + 63) / 64;
 
         stage_begin(ctx, SO + 1, fs, &ev);
@@ -2598,7 +2606,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
             FB_REQUIRE(!swap, FMMBEM_EINTERNAL, "one channel keeps the near field on the side stream");
             const size_t dshm = down_leaf_shm<R>(p, std::max(1, T.nlevels - std::max(P.lmin_tgt, 0)));
             if (dshm > 0) {
-                corr_spmv<KIND>(ctx, ca, st);  // while the near field may still run
+                corr_spmv<R, KIND>(ctx, ca, st);  // while the near field may still run
                 FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));  // the combine needs the near field
                 k_down_leaf<R, KIND><<<T.nleaf, 256, dshm, st>>>(p, ncs, P.op_dim, l2l_op, P.leaf_rec, T.box_r,
                                                                  side, nt, G.tc, G.tc32, L, ca);
@@ -2617,7 +2625,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                     p, ncs, P.op_dim, l2l_op, P.tiles, t0, P.level_list, T.box_i, T.box_r, L, L);
                 FB_HIP(hipGetLastError());
             }
-            corr_spmv<KIND>(ctx, ca, fs);  // while the near field may still run
+            corr_spmv<R, KIND>(ctx, ca, fs);  // while the near field may still run
             const size_t lshm = l2p_shm<R, KIND>(p);
             if (swap || p <= L2P_FAR_MAX_P) {
                 // the far field while the near field may still run, then the combine
@@ -2645,7 +2653,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         hipEvent_t ev4;
         stage_begin(ctx, SO + 4, st, &ev4);
         fill_zero(ctx->y_far, ctx->n, st);
-        corr_spmv<KIND>(ctx, ca, st);
+        corr_spmv<R, KIND>(ctx, ca, st);
         FB_HIP(hipStreamWaitEvent(st, ctx->ev_join, 0));
         k_combine<KIND><<<grid_for(nt, 64), 64, 0, st>>>(nt, ca, ctx->y_far);
         FB_HIP(hipGetLastError());

@@ -217,7 +217,28 @@ __global__ void k_corr_fill(int64_t nt, const int32_t *__restrict__ panel_leaf, 
     }
 }
 
+__global__ void k_round_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        b[i] = (float)a[i];
+}
+
 }  // namespace
+
+// The FP32 mat-vecs read the correction in FP32: its rounding (2^-24
+// relative per value, the products still summed in FP64) is far below the
+// error those mat-vecs are allowed (the schedule takes FP32 only where
+// Eq. 19 allows at least fp32_eps, 1e-5 by default), and
+// the correction product, which reads the values once per mat-vec and is
+// bound by that read, moves half the bytes
+void correction_fp32(fmmbem_ctx *ctx, Correction &C, hipStream_t st)
+{
+    const int64_t n = std::max<int64_t>(C.nnz, 1) * (ctx->kernel == FMMBEM_STOKES_SL ? 9 : 1);
+    C.val32 = ctx->arena.alloc<float>(n);
+    k_round_f32<<<grid_for(n, 256), 256, 0, st>>>(n, C.val, C.val32);
+    FB_HIP(hipGetLastError());
+}
 
 void build_correction(fmmbem_ctx *ctx, hipStream_t st)
 {

@@ -60,7 +60,7 @@ int64_t estimate_bytes(int64_t nt, int kernel, const fmmbem_params &prm, const f
     const int nch = kernel == FMMBEM_STOKES_SL ? 4 : 1;
     const int64_t nbox = 2 + (nt * 8) / std::max(1, prm.ncrit);  // generous
     int64_t geo = nt * (24 + 8 + 72 + 128 + 12 + 64 + 8 + 4 + 4);
-    int64_t corr = nt * 32 * (4 + 8 * (kernel == FMMBEM_STOKES_SL ? 9 : 1));
+    int64_t corr = nt * 32 * (4 + (8 + 4) * (kernel == FMMBEM_STOKES_SL ? 9 : 1));  // FP64 and FP32 values
     int64_t exp = 3 * nbox * nch * ncoef(prm.p_max) * 16;
     const int64_t dop = 2 * ncoef(prm.p_max);
     int64_t ops = 8 * dop * dop * (8 + 8 + 4 + 4);  // M2M and L2L octant operators, FP64 and FP32
