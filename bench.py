@@ -84,6 +84,8 @@ COUNTED_SOURCES = {
                         ("tree.hip", "// P2P work units", "}  // namespace")],
     "k_p2p<float, 0>": [("fmm.hip", "// P2P: one block per work unit", "// The downward pass of one leaf"),
                         ("tree.hip", "// P2P work units", "}  // namespace")],
+    "k_p2p<double, 1>": [("fmm.hip", "// P2P: one block per work unit", "// The downward pass of one leaf"),
+                         ("tree.hip", "// P2P work units", "}  // namespace")],
     "k_near_spmv<float, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
     "k_near_spmv<double, false>": [("nearfield.hip", "// y_near = stored near field", "}  // namespace")],
     "k_m2l_mfma<float, 4, 1|4>": [("fmm.hip", "// M2L, in two passes.", "// LDS of k_m2l_mfma")],
