@@ -676,8 +676,11 @@ __global__ void k_m2m_sum(int p, int ncs, int npar, const int32_t *__restrict__ 
 // column tiles of the chunk.  Lane layout
 // (both precisions): A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; the
 // result D[i][j] is element i % 4 of lane j + 16 (i / 4) in FP32 and element
-// i / 4 of lane j + 16 (i % 4) in FP64.  The Stokes
-// change of centre of the fourth channel is applied when Y is summed.
+// i / 4 of lane j + 16 (i % 4) in FP64.  Stokes: column j is channel j mod 4
+// of its pair, so the lanes of the fourth channel take the pair's first three
+// channels from their neighbours and move its centre from c_S to c_T as they
+// write it out, Y_3 + (c_S - c_T) . (Y_0, Y_1, Y_2) (the FP64 direct kernels
+// leave that to the sum of Y).
 template <typename R> struct Acc4;
 template <> struct Acc4<double> { typedef double type __attribute__((ext_vector_type(4))); };
 template <> struct Acc4<float> { typedef float type __attribute__((ext_vector_type(4))); };
@@ -837,7 +840,8 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(int p, int ncs, int q_tab, con
                                                   const uint64_t *__restrict__ trans_key,
                                                   const int32_t *__restrict__ pair_sorted,
                                                   const int32_t *__restrict__ pairs, const cplx<R> *__restrict__ table,
-                                                  const cplx<R> *__restrict__ M, cplx<R> *__restrict__ Y)
+                                                  const double *__restrict__ box_r, const cplx<R> *__restrict__ M,
+                                                  cplx<R> *__restrict__ Y)
 {
     typedef typename Acc4<R>::type acc_t;
     constexpr int NT = 4;   // column tiles of a chunk (at most 64 columns)
@@ -849,7 +853,8 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(int p, int ncs, int q_tab, con
     const int ldb = min(Kp, KW) + 1;
     int64_t *colsrc = reinterpret_cast<int64_t *>(smem_raw);  // [64]: first real of the column's input, or -1
     int64_t *coldst = colsrc + 64;                             // [64]: first real of the column's result
-    cplx<R> *It = reinterpret_cast<cplx<R> *>(coldst + 64);    // [(q+1)^2]
+    R *gsh = reinterpret_cast<R *>(coldst + 64);               // [16][3]: c_S - c_T of the chunk's pairs (Stokes)
+    cplx<R> *It = reinterpret_cast<cplx<R> *>(gsh + 48);       // [(q+1)^2]
     R *Bs = reinterpret_cast<R *>(It + fq);                    // [64][ldb]: a window of the chunk's inputs
     uint16_t *qnm = reinterpret_cast<uint16_t *>(Bs + 64 * ldb);  // [nc]: n | m << 8
     const int c = blockIdx.x;
@@ -877,6 +882,15 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(int p, int ncs, int q_tab, con
         }
         colsrc[col] = s;
         coldst[col] = d;
+        if (NCH == 4 && col < 48) {
+            const int pl = col / 3, xyz = col - 3 * pl;
+            R g = 0;
+            if (pl < pe - pb) {
+                const int pr = pair_sorted[pb + pl];
+                g = (R)(box_r[5 * (int64_t)pairs[2 * pr + 1] + xyz] - box_r[5 * (int64_t)pairs[2 * pr] + xyz]);
+            }
+            gsh[col] = g;
+        }
     }
     const int nwave = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -959,16 +973,32 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(int p, int ncs, int q_tab, con
         const int rt = w + i * nwave;
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
+            if (ct >= nct)  // wave-uniform
+                break;
             const int col = ct * 16 + li;
-            if (ct >= nct || col >= ncol)
-                continue;
             R *dst = reinterpret_cast<R *>(Y) + coldst[col];
+            R g0 = 0, g1 = 0, g2 = 0;
+            if constexpr (NCH == 4) {
+                const R *gq = gsh + 3 * (col >> 2);
+                g0 = gq[0];
+                g1 = gq[1];
+                g2 = gq[2];
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 // output element v of this lane: row 4 lk + v (FP32 form), 4 v + lk (FP64 form)
                 const int row = rt * 16 + (sizeof(R) == 8 ? 4 * v + lk : 4 * lk + v);
-                if (row < Dp)
-                    dst[row] = acc[i][ct][v];
+                R val = acc[i][ct][v];
+                if constexpr (NCH == 4) {
+                    // every lane shuffles (no lane is off here); the channels 0..2 of
+                    // this lane's pair and rows sit in lanes 4 (li / 4) + 0..2
+                    const int q0 = lane & ~3;
+                    const R y0 = __shfl(val, q0), y1 = __shfl(val, q0 + 1), y2 = __shfl(val, q0 + 2);
+                    if ((li & 3) == 3)
+                        val += g0 * y0 + g1 * y1 + g2 * y2;
+                }
+                if (col < ncol && row < Dp)
+                    dst[row] = val;
             }
         }
     }
@@ -1471,7 +1501,7 @@ template <typename R, int NCH> size_t m2l_rot_shm(int p, int nt)
 template <typename R> size_t m2l_mfma_shm(int p)
 {
     const int q = 2 * p, Kp = (2 * ncoef(p) + 3) & ~3;
-    return 2 * 64 * sizeof(int64_t) + sizeof(cplx<R>) * (size_t)(q + 1) * (q + 1) +
+    return 2 * 64 * sizeof(int64_t) + 48 * sizeof(R) + sizeof(cplx<R>) * (size_t)(q + 1) * (q + 1) +
            sizeof(R) * 64 * (size_t)(std::min(Kp, 64) + 1) + sizeof(uint16_t) * (size_t)ncoef(p);
 }
 
@@ -2562,10 +2592,12 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 FB_REQUIRE(nrt <= 16, FMMBEM_EINVAL, "FP32 M2L beyond its order limit");
                 if (nrt <= 4)
                     k_m2l_mfma<R, NCH, 1><<<P.n_chunks, 64 * nrt, m2l_mfma_shm<R>(p), fs>>>(
-                        p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
+                        p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table,
+                        T.box_r, M, Y);
                 else
                     k_m2l_mfma<R, NCH, 4><<<P.n_chunks, 256, m2l_mfma_shm<R>(p), fs>>>(
-                        p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
+                        p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table,
+                        T.box_r, M, Y);
             } else if (P.ops64) {
                 k_m2l_stored<NCH><<<P.n_chunks, 256, 0, fs>>>(p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin,
                                                                P.chunk_trans, P.pair_sorted, T.m2l_pairs, P.ops64,
@@ -2592,7 +2624,8 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         stage_begin(ctx, SO + 3, fs, &ev);
         {
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
-            if (NCH == 4 && !rot)  // the rotation M2L moves the fourth channel's centre itself
+            // the rotation and the FP32 direct M2L move the fourth channel's centre themselves
+            if (NCH == 4 && !rot && sizeof(R) == 8)
                 k_m2l_reduce<R, NCH, true><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, P.reduce_order, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             else
                 k_m2l_reduce<R, NCH, false><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, P.reduce_order, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
