@@ -1511,14 +1511,22 @@ template <typename R> size_t m2l_mfma_shm(int p)
 // at once (their coefficients wave-uniform, scalar loads) and every input
 // (n, m), the lane forms its two operator entries (for a and b) from P and Q
 // in LDS and adds them times (a, b) of each pair; Horner in n applies the
-// 2^(-eS n) scaling.
+// 2^(-eS n) scaling.  Stokes: a lane holds the four channels of each pair's
+// row, so it moves the fourth channel's centre from c_S to c_T as it writes,
+// Y_3 + (c_S - c_T) . (Y_0, Y_1, Y_2), from the rounded Y values (the same
+// arithmetic as in the sum of Y, which then leaves it out).
+template <typename R> __device__ inline R mul_rn(R a, R b);
+template <> __device__ inline double mul_rn<double>(double a, double b) { return __dmul_rn(a, b); }
+template <> __device__ inline float mul_rn<float>(float a, float b) { return __fmul_rn(a, b); }
+
 template <typename R, int NCH, int PB>
 __global__ __launch_bounds__(256) void k_m2l_valu(int p, int ncs, int q_tab, const int32_t *__restrict__ chunk_begin,
                                                   const int32_t *__restrict__ chunk_trans,
                                                   const uint64_t *__restrict__ trans_key,
                                                   const int32_t *__restrict__ pair_sorted,
                                                   const int32_t *__restrict__ pairs, const cplx<R> *__restrict__ table,
-                                                  const cplx<R> *__restrict__ M, cplx<R> *__restrict__ Y)
+                                                  const double *__restrict__ box_r, const cplx<R> *__restrict__ M,
+                                                  cplx<R> *__restrict__ Y)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int q = 2 * p;
@@ -1596,9 +1604,18 @@ __global__ __launch_bounds__(256) void k_m2l_valu(int p, int ncs, int q_tab, con
             if (base + j >= pe)
                 continue;
             const int orig = pair_sorted[base + j];
+            R y[NCH];
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch)
-                reinterpret_cast<R *>(Y + ((int64_t)orig * NCH + ch) * nc)[r] = f * acc[j][ch];
+                y[ch] = mul_rn(f, acc[j][ch]);
+            if constexpr (NCH == 4) {
+                const double *cS = box_r + 5 * (int64_t)pairs[2 * orig + 1], *cT = box_r + 5 * (int64_t)pairs[2 * orig];
+                const R g0 = (R)(cS[0] - cT[0]), g1 = (R)(cS[1] - cT[1]), g2 = (R)(cS[2] - cT[2]);
+                y[3] += g0 * y[0] + g1 * y[1] + g2 * y[2];
+            }
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                reinterpret_cast<R *>(Y + ((int64_t)orig * NCH + ch) * nc)[r] = y[ch];
         }
     }
 }
@@ -2606,7 +2623,8 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
                 constexpr int PB = NCH == 1 ? 8 : 2;
                 const size_t shm = sizeof(cplx<R>) * (size_t)(2 * p + 1) * (2 * p + 1);
                 k_m2l_valu<R, NCH, PB><<<P.n_chunks, 256, shm, fs>>>(
-                    p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table, M, Y);
+                    p, ncs, P.q, P.chunk_begin, P.chunk_trans, P.trans_key, P.pair_sorted, T.m2l_pairs, table,
+                    T.box_r, M, Y);
             }
             FB_HIP(hipGetLastError());
         }
@@ -2624,8 +2642,8 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         stage_begin(ctx, SO + 3, fs, &ev);
         {
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
-            // the rotation and the FP32 direct M2L move the fourth channel's centre themselves
-            if (NCH == 4 && !rot && sizeof(R) == 8)
+            // every M2L kernel but the stored-operator one moves the fourth channel's centre itself
+            if (NCH == 4 && !rot && sizeof(R) == 8 && P.ops64)
                 k_m2l_reduce<R, NCH, true><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, P.reduce_order, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
             else
                 k_m2l_reduce<R, NCH, false><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, P.reduce_order, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
