@@ -1071,6 +1071,7 @@ __global__ __launch_bounds__(256, 3) void k_m2l_stored(int p, int ncs, int nrt_s
                                                     const int32_t *__restrict__ chunk_trans,
                                                     const int32_t *__restrict__ pair_sorted,
                                                     const int32_t *__restrict__ pairs, const double *__restrict__ ops,
+                                                    const double *__restrict__ box_r,
                                                     const cplx<double> *__restrict__ M, cplx<double> *__restrict__ Y)
 {
     typedef Acc4<double>::type acc_t;
@@ -1079,6 +1080,7 @@ __global__ __launch_bounds__(256, 3) void k_m2l_stored(int p, int ncs, int nrt_s
     static_assert(WS % PF == 0 && 4 * WS == 64, "a window is 64 inputs, whole ring groups");
     __shared__ double Bs[4 * WS * ldb];
     __shared__ int colbase[16 * NT];
+    __shared__ double gsh[48];  // Stokes: c_S - c_T of the chunk's pairs
     const int nc = ncoef(p), Dp = 2 * nc, nsteps = (Dp + 3) / 4, nrt = (Dp + 15) / 16;
     const int c = blockIdx.x;
     const int u = chunk_trans[c], pb = chunk_begin[c];
@@ -1093,6 +1095,15 @@ __global__ __launch_bounds__(256, 3) void k_m2l_stored(int p, int ncs, int nrt_s
             cb = 2 * (pairs[2 * pair_sorted[pb + pl] + 1] * NCH + ch) * ncs;  // first real
         }
         colbase[j] = cb;
+        if (NCH == 4 && j < 48) {
+            const int pl = j / 3, xyz = j - 3 * pl;
+            double g = 0;
+            if (4 * pl < ncol) {
+                const int pr = pair_sorted[pb + pl];
+                g = box_r[5 * (int64_t)pairs[2 * pr + 1] + xyz] - box_r[5 * (int64_t)pairs[2 * pr] + xyz];
+            }
+            gsh[j] = g;
+        }
     }
     __syncthreads();
     const double *Mr = reinterpret_cast<const double *>(M);
@@ -1161,16 +1172,28 @@ __global__ __launch_bounds__(256, 3) void k_m2l_stored(int p, int ncs, int nrt_s
                 continue;
 #pragma unroll
             for (int ct = 0; ct < NT; ++ct) {
+                if (ct >= nct)  // wave-uniform
+                    break;
                 const int col = ct * 16 + li;
-                if (ct >= nct || col >= ncol)
-                    continue;
                 const int pl = col / NCH, ch = col - pl * NCH;
-                double *dst = reinterpret_cast<double *>(Y + ((int64_t)pair_sorted[pb + pl] * NCH + ch) * nc);
+                double *dst = col < ncol
+                                  ? reinterpret_cast<double *>(Y + ((int64_t)pair_sorted[pb + pl] * NCH + ch) * nc)
+                                  : nullptr;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = rt * 16 + 4 * v + lk;  // FP64 output layout
-                    if (row < Dp)
-                        dst[row] = acc[i][ct][v];
+                    double val = acc[i][ct][v];
+                    if constexpr (NCH == 4) {
+                        // the fourth channel moves its centre from c_S to c_T, from the
+                        // pair's first three channels in the neighbouring lanes (every
+                        // lane shuffles)
+                        const int q0 = lane & ~3;
+                        const double y0 = __shfl(val, q0), y1 = __shfl(val, q0 + 1), y2 = __shfl(val, q0 + 2);
+                        if (ch == 3)
+                            val += gsh[3 * pl] * y0 + gsh[3 * pl + 1] * y1 + gsh[3 * pl + 2] * y2;
+                    }
+                    if (col < ncol && row < Dp)
+                        dst[row] = val;
                 }
             }
         }
@@ -1622,20 +1645,17 @@ __global__ __launch_bounds__(256) void k_m2l_valu(int p, int ncs, int q_tab, con
 
 // Pass 2: L(T) = sum of Y over T's pairs (CSR order), all boxes; block =
 // (box, chunk of 256 outputs), thread = (pair slice, output), slices summed
-// in a fixed order.  With FIXC (Stokes
-// after k_m2l_mfma) the fourth channel of each pair also changes centre from
-// c_S to c_T: Y_3 + (c_S - c_T) . (Y_0, Y_1, Y_2).
-template <typename R, int NCH, bool FIXC>
+// in a fixed order.  (Stokes: every M2L kernel has already moved the fourth
+// channel of each pair from c_S to c_T.)
+template <typename R, int NCH>
 __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_t *__restrict__ order,
                                                     const int32_t *__restrict__ ptr,
-                                                    const int32_t *__restrict__ src, const double *__restrict__ box_r,
                                                     const cplx<R> *__restrict__ Y, cplx<R> *__restrict__ L)
 {
     __shared__ cplx<R> red[256];
     const int T = order[blockIdx.x];  // boxes with the most pairs first
     const int nc = ncoef(p), no = NCH * nc;
     const int e0 = ptr[T], e1 = ptr[T + 1];
-    const double *cT = box_r + 5 * (int64_t)T;
     {
         const int o0 = blockIdx.y * (int)blockDim.x;  // this block's outputs: o0 .. o0 + span - 1
         const int span = min((int)blockDim.x, no - o0);
@@ -1645,10 +1665,8 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_
         R sr = 0, si = 0;
         if (sl < nsl_here) {
             // U reads issued together (clamped to the last pair, the extra
-            // ones dropped), then added in pair order; the fourth channel's
-            // change of centre reads its pair's first three channels and
-            // source centre in the same batch
-            constexpr int U = FIXC ? 4 : 8;
+            // ones dropped), then added in pair order
+            constexpr int U = 8;
             for (int e = e0 + sl; e < e1; e += U * nsl_here) {
                 cplx<R> v[U];
                 int64_t ee[U];
@@ -1656,27 +1674,6 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(int p, int ncs, const int32_
                 for (int u = 0; u < U; ++u) {
                     ee[u] = min(e + u * nsl_here, e1 - 1);
                     v[u] = Y[ee[u] * no + t];
-                }
-                if constexpr (FIXC) {
-                    if (ch == 3) {
-                        cplx<R> y0[U], y1[U], y2[U];
-                        int sb[U];
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const cplx<R> *y = Y + ee[u] * no + idx;
-                            y0[u] = y[0];
-                            y1[u] = y[nc];
-                            y2[u] = y[2 * nc];
-                            sb[u] = src[ee[u]];
-                        }
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const double *cS = box_r + 5 * (int64_t)sb[u];
-                            const R g0 = (R)(cS[0] - cT[0]), g1 = (R)(cS[1] - cT[1]), g2 = (R)(cS[2] - cT[2]);
-                            v[u].re += g0 * y0[u].re + g1 * y1[u].re + g2 * y2[u].re;
-                            v[u].im += g0 * y0[u].im + g1 * y1[u].im + g2 * y2[u].im;
-                        }
-                    }
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
@@ -2618,7 +2615,7 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
             } else if (P.ops64) {
                 k_m2l_stored<NCH><<<P.n_chunks, 256, 0, fs>>>(p, ncs, P.ops_nrt, P.ops_k4, P.chunk_begin,
                                                                P.chunk_trans, P.pair_sorted, T.m2l_pairs, P.ops64,
-                                                               M, Y);
+                                                               T.box_r, M, Y);
             } else {
                 constexpr int PB = NCH == 1 ? 8 : 2;
                 const size_t shm = sizeof(cplx<R>) * (size_t)(2 * p + 1) * (2 * p + 1);
@@ -2642,11 +2639,8 @@ void far_chain(fmmbem_ctx *ctx, int p, const CombineArgs &ca, hipStream_t st, bo
         stage_begin(ctx, SO + 3, fs, &ev);
         {
             cplx<R> *Y = static_cast<cplx<R> *>(ctx->Y);
-            // every M2L kernel but the stored-operator one moves the fourth channel's centre itself
-            if (NCH == 4 && !rot && sizeof(R) == 8 && P.ops64)
-                k_m2l_reduce<R, NCH, true><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, P.reduce_order, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
-            else
-                k_m2l_reduce<R, NCH, false><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, P.reduce_order, T.m2l_ptr, T.m2l_src, T.box_r, Y, L);
+            k_m2l_reduce<R, NCH><<<dim3(T.nbox, (NCH * ncoef(p) + 255) / 256), 256, 0, fs>>>(p, ncs, P.reduce_order,
+                                                                                          T.m2l_ptr, Y, L);
             FB_HIP(hipGetLastError());
         }
         // one channel at the low orders: L2L down each leaf's chain of
