@@ -64,8 +64,10 @@ typedef enum {
  *               problem, (1/2 I - K) u = -V du/dn (Eq. 5, 11)             (second kind, 1) */
 typedef enum { FMMBEM_LAPLACE_SL = 0, FMMBEM_STOKES_SL = 1, FMMBEM_LAPLACE_DL = 2 } fmmbem_kernel;
 
-/* Arithmetic of the P2P and expansion (P2M ... L2P) kernels.  Inputs, outputs,
- * the near-field correction and all Krylov arithmetic are FP64 in both cases. */
+/* Arithmetic of the P2P and expansion (P2M ... L2P) kernels.  Inputs, outputs
+ * and all Krylov arithmetic are FP64 in both cases; the near-singular
+ * correction is summed in FP64 in both, from its values rounded to FP32 in an
+ * FP32 mat-vec. */
 typedef enum { FMMBEM_FP64 = 0, FMMBEM_FP32 = 1 } fmmbem_precision;
 
 /* Expansion-order schedule for GMRES (Sec. 2.6).  With rho the relative
